@@ -1,0 +1,226 @@
+"""Throughput of the MOT-JVIE hot path on one MI355X.
+
+Workload: 8x8 array of inhomogeneous dielectric pillars on a 320x320x48 voxel
+grid (14,745,600 unknowns), dt = 16 dt_CFL (ell = 52 history lags), FP32 FFT
+products with FP64 Krylov vectors and FP64 iterative refinement, TFQMR
+tolerance 1e-6.  A "step" is one MOT step (Eq. 3): excitation, history
+right-hand side, the Z0 solve and the history update.
+
+Timed region: K steps after W warm-up steps, inputs resident in HBM, the
+history ring already full (ell zero currents pushed before the march starts,
+so every timed step multiplies all ell lags).  Prints one JSON line.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid):
+    """Minimal HBM bytes of one launch of a pass (roofline)."""
+    nx, ny, nz = n
+    kx, py, pz = nx + 1, 2 * ny, 2 * nz
+    N = nx * ny * nz
+    c = 2 * t_bytes                       # one complex value
+    a = 3 * nz * ny * kx * c              # after x pass
+    b = 3 * nz * py * kx * c              # after y pass (z < nz)
+    f = 3 * pz * py * kx * c              # full spectrum
+    lam = 6 * (nz + 1) * (ny + 1) * kx * t_bytes
+    return {
+        "x_forward": 3 * N * io_bytes + a,
+        "y_forward": a + b,
+        "z_fused": b + lam + b,
+        "y_inverse": b + a,
+        "x_inverse_epilogue": a + 3 * N * io_bytes + N * 8 + 3 * N * io_bytes,
+        "z_forward": b + f,
+        "history_mac": nvalid * (f + lam) + f,
+        "z_inverse": f + b,
+    }.get(kind)
+
+
+def cpu_baseline(w, eps, log_fn):
+    """Oracle FP64 Z0 product (FFT form, NumPy) at the benchmark size."""
+    import numpy as np
+    import workloads as W
+    from oracle import green, operators
+    g0 = green.green_octant(*w.n, 0, alpha=w.alpha)
+    lam, _ = operators.embed_spectra(g0)
+    J = W.random_current(w.n, seed=1)
+    log_fn("cpu baseline: timing one oracle Z0 product at full size")
+    t = time.perf_counter()
+    operators.z0_apply(g0, eps, J, lam=lam)
+    dt = time.perf_counter() - t
+    return {"value": 1.0 / dt, "unit": "Z0 matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": "one FP64 Z0 product (Eq. 11/12, numpy.fft, spectra precomputed) at "
+                      f"{w.n[0]}x{w.n[1]}x{w.n[2]}; {dt:.1f} s",
+            "cpu": _cpu_name()}
+
+
+def _cpu_name():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="f32_refined", choices=["f32_refined", "f64", "f32"])
+    ap.add_argument("--matvec-reps", type=int, default=30)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2607_28309_amd import native
+
+    w = W.PILLARS
+    n = w.n
+    torch.cuda.set_device(0)
+    eps = w.eps()
+    N = n[0] * n[1] * n[2]
+    t0 = time.perf_counter()
+    ctx = native.Context(*n, alpha=w.alpha, precision=args.precision)
+    ctx.set_material(torch.from_numpy(eps.ravel()).cuda())
+    log(f"context: {ctx.info()}")
+    imag = ctx.build_green_spectra()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = ctx.info()
+    nl = info["nlags"]
+    log(f"spectra built in {setup_s:.1f} s (ell = {nl}, max |Im| = {imag:.2e})")
+
+    # full history ring: J_{n<0} = 0 pushed ell times
+    zero = torch.zeros(3 * N, dtype=torch.float64, device="cuda")
+    for _ in range(nl):
+        ctx.history_update(zero)
+    torch.cuda.synchronize()
+    p = W.pulse(w.ppw)
+    L = w.alpha / math.sqrt(3.0)
+    einc = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    J = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+
+    def one_step(s):
+        ctx.excitation(p, (args.start_step + s) * L, einc)
+        return ctx.step(einc, J, tol=args.tol, stats=True)[1]
+
+    for s in range(args.warmup):
+        st = one_step(s)
+        log(f"warm-up step {s}: {st['iters']} iterations, relres {st['relres']:.2e}")
+    ctx.profile(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stats = []
+    for s in range(args.steps):
+        stats.append(one_step(args.warmup + s))
+        log(f"step {s}: {stats[-1]['iters']} it, {stats[-1]['matvecs']} mv "
+            f"({stats[-1]['matvecs_f64']} f64), relres {stats[-1]['relres']:.2e}, "
+            f"lhs {stats[-1]['ms_lhs']:.1f} ms, rhs {stats[-1]['ms_rhs']:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # Z0 product throughput (FP32 and FP64), events on torch's current stream
+    mv = {}
+    for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        Jm = torch.randn(3 * N, dtype=tdt, device="cuda")
+        ym = torch.empty_like(Jm)
+        for _ in range(3):
+            ctx.z0_matvec(Jm, ym, dt_name)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.matvec_reps):
+            ctx.z0_matvec(Jm, ym, dt_name)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.matvec_reps
+        mv[dt_name] = {"ms": ms, "per_s": 1e3 / ms}
+        log(f"z0_matvec {dt_name}: {ms:.3f} ms")
+        del Jm, ym
+
+    # roofline of the kernel with the largest share of the timed region
+    ring_t = 8 if args.precision == "f64" else 4
+    best = None
+    kernels = {}
+    for (kind, prec), (ms, cnt) in prof.items():
+        kernels[f"{kind}.{prec}"] = {"ms_total": round(ms, 3), "launches": cnt, "ms_avg": round(ms / cnt, 4)}
+        if best is None or ms > best[2]:
+            best = (kind, prec, ms, cnt)
+    kind, prec, ms, cnt = best
+    tb = 8 if prec == "f64" else 4
+    if kind in ("history_mac", "z_forward", "z_inverse"):
+        tb = ring_t
+    io = 4 if args.precision == "f32" else 8
+    alg = algorithmic_bytes(kind, n, tb, io, nl)
+    avg_s = ms / cnt / 1e3
+    achieved = alg / avg_s / 1e9 if alg else None
+    roofline = {"bound": "hbm", "kernel": f"{kind}.{prec}", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": None, "algorithmic_bytes_per_launch": alg, "avg_launch_ms": ms / cnt}
+    # Z0 pipeline as a whole (five passes)
+    pipe_bytes = sum(algorithmic_bytes(k, n, 4, 4, nl) for k in
+                     ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue"))
+
+    its = [s["iters"] for s in stats]
+    out = {
+        "metric": "Z0 FFT-matvecs/s + MOT steps/s at 15M unknowns; achieved HBM GB/s vs peak",
+        "value": args.steps / elapsed,
+        "unit": "MOT steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision != "f64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(n), "unknowns": 3 * N, "alpha": w.alpha, "nlags": nl,
+                   "precision": args.precision, "tol": args.tol, "parallelism": "single GPU"},
+        "z0_matvecs_per_s": {k: v["per_s"] for k, v in mv.items()},
+        "z0_matvec_ms": {k: v["ms"] for k, v in mv.items()},
+        "z0_pipeline_gbs_f32": pipe_bytes / (mv["f32"]["ms"] / 1e3) / 1e9,
+        "iters_per_step": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)},
+        "matvecs_per_step": sum(s["matvecs"] for s in stats) / len(stats),
+        "relres_max": max(s["relres"] for s in stats),
+        "ms_lhs_mean": sum(s["ms_lhs"] for s in stats) / len(stats),
+        "ms_rhs_mean": sum(s["ms_rhs"] for s in stats) / len(stats),
+        "setup_s": setup_s,
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, eps, log)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * mot_jvie.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * large-time-step marching-on-in-time current-density volume integral
+ * equation (MOT-JVIE) solver for dielectric scattering of Kumar, Gerini and
+ * van Beurden, "Large-Time-Step Operation in a Volume Integral Equation for
+ * Dielectric Scattering".
+ *
+ * Problem (Sec. II): the TDJVIE of Eq. 1, discretized on a uniform voxel grid
+ * with piecewise-constant spatial basis per Cartesian current component,
+ * centre-point testing, Dirac temporal testing at t_n = n dt and the causal
+ * quadratic-spline temporal basis (support [-dt, 2dt), T(0) = T(dt) = 1/2),
+ * gives the MOT recursion of Eq. 3:
+ *     Z0 J_n = E_n - sum_{k=1..ell} Z_k J_{n-k},   ell from Eq. 4,
+ *     Z_k    = T(k dt) diag(eps_r) - diag(eps_r - 1) G_k,
+ * so that Z0 = D - X G (Eq. 10) with D = diag(eps_r)/2, X = diag(eps_r - 1).
+ * G_k is block Toeplitz (it depends only on voxel offsets); every product
+ * with it is evaluated matrix-free through the circulant embedding and 3-D
+ * FFTs of Eq. 11, assembled as Z0 J = D J - X (G J) (Eq. 12).
+ *
+ * Units: c0 = eps0 = h = 1 (h the voxel edge); times in h/c0.  The time step
+ * is dt = alpha * dt_CFL with dt_CFL = h/(c0 sqrt 3), i.e. c0 dt / h = alpha/sqrt 3.
+ *
+ * Layouts (all arrays are caller-owned DEVICE memory, contiguous, at least
+ * 16-byte aligned):
+ *   voxel arrays (eps_r):            [nz][ny][nx], x fastest;
+ *   current / field vectors (J, y):  [3][nz][ny][nx], component p in {x,y,z}
+ *                                    slowest, then z, y, x.
+ *   Green tables:                    [6][nz][ny][nx] over non-negative offsets
+ *                                    (dz, dy, dx), components (xx,yy,zz,xy,xz,yz).
+ *
+ * Threading and streams: one context per stream; a context is not
+ * thread-safe.  Every call enqueues on the context's stream and returns
+ * without waiting, except where noted (mot_step and build_green_spectra read
+ * scalars back).  No C++ exception crosses this interface.
+ *
+ * Errors: 0 on success, a negative MOT_E* code otherwise; mot_strerror()
+ * names the code and mot_last_error() gives the detail of the last failure
+ * on a context (HIP error strings included).
+ */
+#ifndef MOT_JVIE_H
+#define MOT_JVIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MOT_OK = 0,
+  MOT_EINVAL = -1,      /* bad shape, null pointer, unsupported length, bad enum */
+  MOT_ENOMEM = -2,      /* device allocation failed */
+  MOT_EHIP = -3,        /* a HIP call failed; see mot_last_error */
+  MOT_ENOCONV = -4,     /* TFQMR reached max_iter; J_n holds the last iterate */
+  MOT_EBREAKDOWN = -5,  /* TFQMR breakdown (rho or sigma exactly zero) */
+  MOT_ENONFINITE = -6,  /* a NaN/Inf appeared in the right-hand side or the solution */
+  MOT_ESTATE = -7       /* call out of order (e.g. no material or no spectra yet) */
+};
+
+typedef struct mot_ctx mot_ctx;
+
+typedef enum {
+  MOT_F64 = 0,          /* FFTs, spectra and Krylov vectors in FP64 */
+  MOT_F32 = 1,          /* FFTs and spectral products in FP32 */
+  MOT_F32_REFINED = 2   /* FP32 FFT products inside an FP64 iterative refinement */
+} mot_precision;
+
+typedef struct {
+  int32_t nx, ny, nz; /* voxels per axis; nx even; 2*nx, 2*ny, 2*nz and nx must be
+                         supported FFT lengths (products of 2, 3, 5 listed by
+                         mot_length_supported) */
+  int32_t alpha;      /* dt = alpha * dt_CFL, integer >= 1; 0 => use cdt */
+  double cdt;         /* c0 dt / h when alpha == 0 (must be > 0) */
+  int32_t nlags;      /* ell; 0 => Eq. 4 with p = 2 and R_max = sqrt(sum (N_i - 1/2)^2) */
+  int32_t quad;       /* Gauss-Legendre nodes per quadrature piece, 0 => 20 (max 32) */
+} mot_grid;
+
+typedef struct {
+  int32_t iters;        /* TFQMR iterations (two half steps each), all refinement sweeps */
+  int32_t matvecs;      /* Z0 products in the solve, all precisions */
+  int32_t matvecs_f64;  /* of which in FP64 */
+  int32_t refinements;  /* outer refinement sweeps (MOT_F32_REFINED), else 0 */
+  double relres;        /* final ||b - Z0 J_n|| / ||b|| evaluated in FP64 */
+  double ms_lhs;        /* time of the solve (LHS of Eq. 6) */
+  double ms_rhs;        /* time of the right-hand side: history update + assembly (RHS of Eq. 6) */
+} mot_stats;
+
+/* Modulated Gaussian plane wave of Eq. 7 and Eq. 8:
+ *   E^i(r,t) = amp e exp(-tau^2/(2 sigma^2)) cos(2 pi f0 tau),
+ *   tau = t - t0 - k.(r - r_c), r_c the grid centre, r the voxel centre. */
+typedef struct {
+  double e[3];   /* polarization */
+  double k[3];   /* unit propagation direction */
+  double f0, sigma, t0, amp;
+} mot_pulse;
+
+/* Create a context for `grid` with the given precision on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Allocates the FFT workspaces,
+ * the Krylov vectors, the spectra and the history ring (ell spectra of past
+ * currents: 3*(2nz)*(2ny)*(nx+1) complex each, FP64 for MOT_F64, else FP32).
+ * Errors: MOT_EINVAL (shape, lengths, alpha/cdt), MOT_ENOMEM, MOT_EHIP. */
+int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_ctx** out);
+
+/* Release everything the context owns.  Accepts NULL. */
+int mot_destroy(mot_ctx* ctx);
+
+/* Sizes: out[0] = ell, out[1..3] = 2nx, 2ny, 2nz, out[4] = padded row
+ * stride of the spectral buffers, out[5] = device bytes held by the context,
+ * out[6] = steps taken since the last reset.  Host array of n >= 7 entries. */
+int mot_info(const mot_ctx* ctx, int64_t* out, int32_t n);
+
+/* Operator precompute (Sec. II: Z_k for lags 0..ell; Sec. IV: spectra of the
+ * circulant embedding).  For k = 0..ell evaluates G_k on the non-negative
+ * octant of offsets (FP64 quadrature on the device), embeds each of its six
+ * components on the doubled grid with the reflection signs, takes a 3-D FFT in
+ * FP64 and keeps the real part on the octant of frequencies, scaled by
+ * 1/(8 nx ny nz).  Blocks until done.  Errors: MOT_EHIP. */
+int build_green_spectra(mot_ctx* ctx);
+
+/* Largest |imaginary part| met while building the spectra (they are real up
+ * to rounding because every component is even or odd-odd per axis). */
+double mot_spectra_imag(const mot_ctx* ctx);
+
+/* Set eps_r per voxel (device pointer, nx*ny*nz FP64, copied).  Voxels with
+ * eps_r = 1 carry no current.  Errors: MOT_EINVAL. */
+int mot_set_material(mot_ctx* ctx, const double* eps_r);
+
+/* y = Z0 J (Eq. 12) with the FFT product of Eq. 11.
+ *   dtype MOT_F64:         J, y FP64 device vectors, FP64 transforms;
+ *   dtype MOT_F32:         J, y FP32 device vectors, FP32 transforms;
+ *   dtype MOT_F32_REFINED: J, y FP64 device vectors, FP32 transforms (the
+ *                          inner operator of the refined solver).
+ * J and y must not overlap.  Errors: MOT_EINVAL, MOT_ESTATE, MOT_EHIP. */
+int z0_matvec(mot_ctx* ctx, const void* J, void* y, mot_precision dtype);
+
+/* Green-convolution only: y = (G_k J) for lag k (same dtypes as z0_matvec;
+ * k = 0 uses the present-time spectra, k >= 1 the history spectra, whose
+ * precision is the ring's).  Test entry point for the history operators. */
+int gk_matvec(mot_ctx* ctx, int32_t k, const void* J, void* y, mot_precision dtype);
+
+/* Push J_n (FP64 device vector) into the history ring and prepare the
+ * history right-hand side of the next step,
+ *   h_{n+1} = -sum_{k=1..ell} Z_k J_{n+1-k}
+ *           = -(eps_r/2) J_n + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
+ * using the spectra of past currents (each current is transformed once).
+ * Errors: MOT_ESTATE, MOT_EHIP. */
+int history_update(mot_ctx* ctx, const double* J_n);
+
+/* Copy the prepared history right-hand side (FP64, 3N) to `out` (device). */
+int mot_get_history_rhs(mot_ctx* ctx, double* out);
+
+/* out = (eps_r - 1) d/dt E^i(r_m, t) at every voxel centre (the tested
+ * excitation of Eq. 1), FP64 device vector of 3N. */
+int mot_excitation(mot_ctx* ctx, const mot_pulse* pulse, double t, double* out);
+
+/* One MOT step (Eq. 3): b = einc + h_n, solve Z0 J_n = b by TFQMR from
+ * J = 0 to ||b - Z0 J_n|| <= tol ||b|| (true residual, FP64), then
+ * history_update(J_n) and n += 1.  b = 0 gives J_n = 0 after 0 iterations.
+ * einc, J_n: FP64 device vectors of 3N (distinct).  `stats` may be NULL.
+ * Errors: MOT_ENOCONV (J_n = last iterate, history still advanced),
+ * MOT_EBREAKDOWN, MOT_ENONFINITE, MOT_ESTATE, MOT_EHIP. */
+int mot_step(mot_ctx* ctx, const double* einc, double* J_n, double tol, int32_t max_iter, mot_stats* stats);
+
+/* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
+int mot_reset(mot_ctx* ctx);
+
+/* Evaluate G_k on the octant of offsets into `out` ([6][nz][ny][nx] FP64,
+ * device), exactly as build_green_spectra does.  Entries outside the causal
+ * region of lag k are exact zeros. */
+int mot_green_table(mot_ctx* ctx, int32_t k, double* out);
+
+/* Kernel timing.  When enabled, every launch of the hot path is bracketed by
+ * a pair of HIP events on the context's stream and its duration is added to
+ * one of MOT_PROF_NCLASS classes:
+ *   class = 2*kind + (FP64 ? 1 : 0), kind: 0 x forward, 1 y forward,
+ *   2 z fused (forward, Lambda, inverse), 3 y inverse, 4 x inverse + Eq. 12
+ *   epilogue, 5 z forward (history spectra), 6 history multiply-accumulate,
+ *   7 z inverse (history), 8 Krylov vector/reduction kernels (FP64: odd class),
+ *   9 excitation.
+ * mot_profile_read copies the accumulated milliseconds and launch counts of
+ * the n = MOT_PROF_NCLASS classes to host arrays, then clears them (it
+ * waits for the stream).  Timing adds a few microseconds per launch. */
+#define MOT_PROF_NCLASS 20
+int mot_profile(mot_ctx* ctx, int32_t enable);
+int mot_profile_read(mot_ctx* ctx, double* ms, int64_t* counts, int32_t n);
+
+/* Host helpers (no GPU needed). */
+int32_t mot_nlags(const mot_grid* grid);           /* ell of Eq. 4 (reading above), or < 0 */
+int64_t mot_zk_nnz(const mot_grid* grid, int32_t k); /* nonzeros of Z_k with dyad weights 3/3/5/9, or < 0 */
+int32_t mot_length_supported(int32_t n);           /* 1 if n is a supported FFT length */
+
+const char* mot_strerror(int status);
+const char* mot_last_error(const mot_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOT_JVIE_H */

@@ -1,0 +1,258 @@
+// Register-resident Stockham FFT building blocks for gfx950.
+//
+// A batch of `np` pencils of compile-time length M is transformed by one
+// workgroup laid out as (p = tid % np, jt = tid / np): np pencils times TJ
+// threads per pencil.  Every thread keeps E = M/TJ complex values in VGPRs;
+// each radix stage is a register butterfly followed by one exchange through a
+// single LDS buffer laid out element-major, lds[element * np + pencil], so
+// that lanes with consecutive pencil indices touch consecutive addresses.
+// The first stage's loads and the last stage's stores go through caller
+// functors (global memory for strided pencils, LDS for contiguous rows).
+//
+// Stockham autosort, decimation in time: with span Ns (product of the radices
+// already applied), butterfly j of a stage with radix R reads elements
+// j + r*M/R, multiplies element r by W_{Ns R}^{(j mod Ns) r}, applies the
+// length-R DFT and writes element (j/Ns)*Ns*R + (j mod Ns) + r*Ns.  The
+// twiddles come from a table tw[q] = exp(-2 pi i q / M) held in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace motfft {
+
+template <typename T> struct cvec;
+template <> struct cvec<float> { using t = float2; };
+template <> struct cvec<double> { using t = double2; };
+template <typename T> using cpx = typename cvec<T>::t;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { return C{a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C> __device__ __forceinline__ C mul_i(C a) {
+  return INV ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+// cos/sin of 2 pi j / R for the composite radices 6, 8, 10 (j < R/2)
+__host__ __device__ constexpr double rot_cos(int R, int j) {
+  return R == 6 ? (j == 0 ? 1.0 : j == 1 ? 0.5 : -0.5)
+       : R == 8 ? (j == 0 ? 1.0 : j == 1 ? 0.70710678118654752440 : j == 2 ? 0.0 : -0.70710678118654752440)
+       : (j == 0 ? 1.0 : j == 1 ? 0.80901699437494742410 : j == 2 ? 0.30901699437494742410
+                : j == 3 ? -0.30901699437494742410 : -0.80901699437494742410);
+}
+__host__ __device__ constexpr double rot_sin(int R, int j) {
+  return R == 6 ? (j == 0 ? 0.0 : 0.86602540378443864676)
+       : R == 8 ? (j == 0 ? 0.0 : j == 2 ? 1.0 : 0.70710678118654752440)
+       : (j == 0 ? 0.0 : (j == 1 || j == 4) ? 0.58778525229247312917 : 0.95105651629515357212);
+}
+
+// In-register DFT of length R: v[k] <- sum_j v[j] exp(-+2 pi i jk/R).
+template <int R, bool INV, typename T> struct Dft {
+  // even composite radix R = 2Q: radix-2 split, rotate the odd half, two DFT_Q
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    constexpr int Q = R / 2;
+    cpx<T> a[Q], b[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      a[j] = cadd(v[j], v[j + Q]);
+      cpx<T> d = csub(v[j], v[j + Q]);
+      const T c = (T)rot_cos(R, j);
+      const T s = INV ? (T)rot_sin(R, j) : -(T)rot_sin(R, j);
+      b[j] = cpx<T>{d.x * c - d.y * s, d.x * s + d.y * c};
+    }
+    Dft<Q, INV, T>::run(a);
+    Dft<Q, INV, T>::run(b);
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      v[2 * m] = a[m];
+      v[2 * m + 1] = b[m];
+    }
+  }
+};
+template <bool INV, typename T> struct Dft<2, INV, T> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  }
+};
+template <bool INV, typename T> struct Dft<3, INV, T> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T s = (T)0.86602540378443864676;
+    cpx<T> t1 = cadd(v[1], v[2]);
+    cpx<T> t2 = csub(v[1], v[2]);
+    cpx<T> m = cpx<T>{v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
+    cpx<T> n = mul_i<INV>(cscale(t2, s));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, n);
+    v[2] = csub(m, n);
+  }
+};
+template <bool INV, typename T> struct Dft<4, INV, T> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> t0 = cadd(v[0], v[2]);
+    cpx<T> t1 = csub(v[0], v[2]);
+    cpx<T> t2 = cadd(v[1], v[3]);
+    cpx<T> t3 = mul_i<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+template <bool INV, typename T> struct Dft<5, INV, T> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+    cpx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    cpx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    cpx<T> a1 = cpx<T>{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    cpx<T> a2 = cpx<T>{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    cpx<T> b1 = cpx<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    cpx<T> b2 = cpx<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    b1 = mul_i<INV>(b1);
+    b2 = mul_i<INV>(b2);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+template <int... Rs> struct RadixList {};
+
+template <int A, int B> struct Gcd { static constexpr int value = Gcd<B, A % B>::value; };
+template <int A> struct Gcd<A, 0> { static constexpr int value = A; };
+
+// Threads per pencil: gcd over stages of M/R, so every thread owns the same
+// number of butterflies in every stage.
+template <int M, typename L> struct PlanTJ;
+template <int M, int R> struct PlanTJ<M, RadixList<R>> { static constexpr int value = M / R; };
+template <int M, int R, int R2, int... Rest> struct PlanTJ<M, RadixList<R, R2, Rest...>> {
+  static constexpr int value = Gcd<M / R, PlanTJ<M, RadixList<R2, Rest...>>::value>::value;
+};
+
+template <int M, typename L> struct FirstRadix;
+template <int M, int R, int... Rest> struct FirstRadix<M, RadixList<R, Rest...>> { static constexpr int value = R; };
+
+// Run the stages of RadixList on registers v (inputs of the first remaining
+// stage already loaded).  `store(p, element, value)` receives the outputs of
+// the last stage.
+template <typename T, int M, int TJ, bool INV, int NS, typename L> struct Stages;
+
+template <typename T, int M, int TJ, bool INV, int NS, int R, int... Rest>
+struct Stages<T, M, TJ, INV, NS, RadixList<R, Rest...>> {
+  template <typename Store>
+  static __device__ __forceinline__ void run(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt,
+                                             int np, Store&& store) {
+    constexpr int B = M / (R * TJ);
+    constexpr int TWS = M / (NS * R);
+#pragma unroll
+    for (int t = 0; t < B; ++t) {
+      const int j = jt + t * TJ;
+      if (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[k * r * TWS];
+          v[t * R + r] = INV ? cmulc(v[t * R + r], w) : cmul(v[t * R + r], w);
+        }
+      }
+      Dft<R, INV, T>::run(&v[t * R]);
+    }
+    if constexpr (sizeof...(Rest) == 0) {
+#pragma unroll
+      for (int t = 0; t < B; ++t) {
+        const int j = jt + t * TJ;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(p, base + r * NS, v[t * R + r]);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < B; ++t) {
+        const int j = jt + t * TJ;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[(base + r * NS) * np + p] = v[t * R + r];
+      }
+      __syncthreads();
+      constexpr int R2 = FirstRadix<M, RadixList<Rest...>>::value;
+      constexpr int B2 = M / (R2 * TJ);
+      constexpr int MR2 = M / R2;
+#pragma unroll
+      for (int t = 0; t < B2; ++t)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[(jt + t * TJ + r * MR2) * np + p];
+      __syncthreads();
+      Stages<T, M, TJ, INV, NS * R, RadixList<Rest...>>::run(v, lds, tw, p, jt, np, store);
+    }
+  }
+};
+
+// Plan of radices per supported length.
+template <int M> struct Plan;
+#define MOT_PLAN(M_, ...) \
+  template <> struct Plan<M_> { using list = RadixList<__VA_ARGS__>; };
+MOT_PLAN(8, 8)
+MOT_PLAN(12, 4, 3)
+MOT_PLAN(16, 4, 4)
+MOT_PLAN(20, 4, 5)
+MOT_PLAN(24, 4, 6)
+MOT_PLAN(32, 8, 4)
+MOT_PLAN(40, 4, 10)
+MOT_PLAN(48, 8, 6)
+MOT_PLAN(64, 8, 8)
+MOT_PLAN(80, 8, 10)
+MOT_PLAN(96, 8, 4, 3)
+MOT_PLAN(120, 2, 2, 6, 5)
+MOT_PLAN(128, 8, 4, 4)
+MOT_PLAN(160, 8, 4, 5)
+MOT_PLAN(180, 6, 6, 5)
+MOT_PLAN(192, 8, 8, 3)
+MOT_PLAN(240, 2, 2, 6, 10)
+MOT_PLAN(320, 8, 8, 5)
+MOT_PLAN(480, 2, 2, 2, 6, 10)
+MOT_PLAN(640, 8, 8, 10)
+#undef MOT_PLAN
+
+// Supported transform lengths, for host-side dispatch.
+#define MOT_FOR_EACH_LEN(X) \
+  X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(120) X(128) X(160) X(180) \
+  X(192) X(240) X(320) X(480) X(640)
+
+template <int M> struct PlanInfo {
+  using list = typename Plan<M>::list;
+  static constexpr int TJ = PlanTJ<M, list>::value;
+  static constexpr int E = M / TJ;
+  static constexpr int R0 = FirstRadix<M, list>::value;
+};
+
+// Load the first stage's inputs for pencil p: element(e) returns value e.
+template <typename T, int M, typename Load>
+__device__ __forceinline__ void load_first(cpx<T>* v, int p, int jt, Load&& elem) {
+  using PI = PlanInfo<M>;
+  constexpr int R = PI::R0;
+  constexpr int B = M / (R * PI::TJ);
+#pragma unroll
+  for (int t = 0; t < B; ++t)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[t * R + r] = elem(p, jt + t * PI::TJ + r * (M / R));
+}
+
+template <typename T, int M, bool INV, typename Store>
+__device__ __forceinline__ void run_fft(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt, int np,
+                                        Store&& store) {
+  using PI = PlanInfo<M>;
+  Stages<T, M, PI::TJ, INV, 1, typename PI::list>::run(v, lds, tw, p, jt, np, store);
+}
+
+}  // namespace motfft

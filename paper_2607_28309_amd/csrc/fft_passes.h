@@ -1,0 +1,54 @@
+// Launch interface of the FFT passes of the Toeplitz/circulant product
+// (Eq. 11): x real-to-complex, y complex, z complex with the spectral
+// multiply fused in, and their inverses.  Layout of every spectral buffer:
+// [component][plane][row][kxs] complex, kx fastest, kxs = padded Nx+1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace motfft {
+
+enum ZMode { Z_FWD = 0, Z_INV = 1, Z_FUSED = 2 };
+
+// Epilogue of the inverse x pass:
+//   y = (ca*eps + c0) * J + (cb*eps + cb0) * g,    g = the transformed field
+// (Eq. 12: ca = 1/2, c0 = 0, cb = -1, cb0 = 1 gives D J - X (G J)).
+struct Epilogue {
+  double ca, c0, cb, cb0;
+};
+
+// Precision tags: T = compute type; IO = element type of real vectors.
+// Returns hipSuccess or an error; hipErrorInvalidValue for an unsupported length.
+
+// x pass, forward: `nrows` rows of `row_len` reals (row stride row_len) ->
+// rows of Nx+1 complex (stride kxs).  M = complex FFT length (= Nx), the
+// first n_in complex pairs of each row are read, the rest are zero.
+template <typename T, typename IO>
+hipError_t x_forward(const IO* in, void* out, int M, int nrows, int row_len, int n_in, int kxs,
+                     const void* tw, const void* tw2, hipStream_t s);
+
+// x pass, inverse with epilogue: rows of M+1 complex -> first n_out reals of
+// a length-2M real signal; y/J rows of row_len reals, eps indexed by
+// (row mod rows_per_comp) * row_len + x.
+template <typename T, typename IO>
+hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
+                     int nrows, int rows_per_comp, int row_len, int n_out, int kxs, const void* tw,
+                     const void* tw2, hipStream_t s);
+
+// y pass: `planes` planes; input rows_in rows (first n_in read), output
+// rows_out rows (first n_out written).
+template <typename T>
+hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kxs, int planes,
+                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s);
+
+// z pass over `nc` (1 or 3) components; ny = number of ky rows.
+// FUSED multiplies by Lambda (6 real components, octant-compressed
+// [6][M/2+1][ny/2+1][kxs]) between the forward and inverse transforms.
+template <typename T>
+hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
+                  int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,
+                  hipStream_t s);
+
+bool length_supported(int M);
+
+}  // namespace motfft

@@ -1,0 +1,398 @@
+// FFT passes of the circulant-embedded Green product (Eq. 11, Eq. 12).
+//
+// x pass: a real row of length 2M (zero beyond the first n_in pairs) is
+//   packed as z[n] = x[2n] + i x[2n+1], transformed with a length-M complex
+//   FFT and unpacked to the M+1 non-redundant bins
+//   X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) W_{2M}^k (Z[k] - conj Z[M-k]).
+//   The inverse repacks Z[k] = (X[k] + conj X[M-k]) + i W_{2M}^{-k} (X[k] - conj X[M-k]),
+//   applies the inverse length-M FFT and keeps the first n_out reals, fused
+//   with the diagonal terms of Eq. 12.
+// y pass: complex pencils along y for a tile of kx columns; the forward pass
+//   reads only the Ny physical rows (the rest of the doubled grid is zero),
+//   the inverse writes only the Ny rows that the truncation T{} keeps.
+// z pass: pencils along z for a kx tile at one ky, all components together,
+//   so that the 3x3 real spectral multiply sum_q Lambda_pq J_q sits between
+//   the forward and the inverse transform without leaving the workgroup.
+#include "fft_core.h"
+#include "fft_passes.h"
+
+namespace motfft {
+
+constexpr int floor_pow2(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int LDS_BUDGET = 81920;
+
+template <typename T, int M> struct XCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int NP =
+      cmax(1, floor_pow2(cmin(256 / TJ, (LDS_BUDGET - (2 * M + 1) * SZ) / ((M + 1) * SZ))));
+  static constexpr int BLOCK = NP * TJ;
+};
+template <typename T, int M> struct YCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int NP = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ))));
+  static constexpr int BLOCK = NP * TJ;
+};
+template <typename T, int M, int NC> struct ZCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int W =
+      cmax(1, floor_pow2(cmin(cmin(16, 1024 / (NC * TJ)), (LDS_BUDGET - M * SZ) / (NC * M * SZ))));
+  static constexpr int NP = NC * W;
+  static constexpr int BLOCK = NP * TJ;
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void load_table(cpx<T>* dst, const cpx<T>* src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+template <typename IO> struct io2;
+template <> struct io2<float> { using t = float2; };
+template <> struct io2<double> { using t = double2; };
+
+// ------------------------------------------------------------------ x pass
+template <typename T, typename IO, int M>
+__global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __restrict__ in,
+                                                                  cpx<T>* __restrict__ out, int nrows,
+                                                                  int row_len, int n_in, int kxs,
+                                                                  const cpx<T>* __restrict__ tw_g,
+                                                                  const cpx<T>* __restrict__ tw2_g) {
+  using C = XCfg<T, M>;
+  constexpr int NP = C::NP;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = lds + (M + 1) * NP;
+  cpx<T>* tw2 = tw + M;
+  load_table<T, M>(tw, tw_g, M);
+  load_table<T, M>(tw2, tw2_g, M + 1);
+  const int row0 = blockIdx.x * NP;
+  using V2 = typename io2<IO>::t;
+  for (int idx = threadIdx.x; idx < NP * M; idx += blockDim.x) {
+    const int row = idx / M, n = idx - row * M;
+    const int grow = row0 + row;
+    cpx<T> val{(T)0, (T)0};
+    if (grow < nrows && n < n_in) {
+      V2 pr = *reinterpret_cast<const V2*>(in + (size_t)grow * row_len + 2 * n);
+      val = cpx<T>{(T)pr.x, (T)pr.y};
+    }
+    lds[n * NP + row] = val;
+  }
+  __syncthreads();
+  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
+  cpx<T> v[PlanInfo<M>::E];
+  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NP + pp]; });
+  __syncthreads();
+  run_fft<T, M, false>(v, lds, tw, p, jt, NP, [&](int pp, int e, cpx<T> val) { lds[e * NP + pp] = val; });
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NP * (M + 1); idx += blockDim.x) {
+    const int row = idx / (M + 1), k = idx - row * (M + 1);
+    const int grow = row0 + row;
+    if (grow >= nrows) continue;
+    const cpx<T> zk = lds[(k == M ? 0 : k) * NP + row];
+    const cpx<T> zm = lds[(k == 0 ? 0 : M - k) * NP + row];
+    // E = (zk + conj zm)/2, O = -i/2 (zk - conj zm)
+    const cpx<T> e{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+    const cpx<T> o{(T)0.5 * (zk.y + zm.y), (T)-0.5 * (zk.x - zm.x)};
+    out[(size_t)grow * kxs + k] = cadd(e, cmul(tw2[k], o));
+  }
+}
+
+template <typename T, typename IO, int M>
+__global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
+    const cpx<T>* __restrict__ in, IO* __restrict__ y, const IO* __restrict__ J,
+    const double* __restrict__ eps, Epilogue ep, int nrows, int rows_per_comp, int row_len, int n_out,
+    int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g) {
+  using C = XCfg<T, M>;
+  constexpr int NP = C::NP;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = lds + (M + 1) * NP;
+  cpx<T>* tw2 = tw + M;
+  load_table<T, M>(tw, tw_g, M);
+  load_table<T, M>(tw2, tw2_g, M + 1);
+  const int row0 = blockIdx.x * NP;
+  for (int idx = threadIdx.x; idx < NP * (M + 1); idx += blockDim.x) {
+    const int row = idx / (M + 1), k = idx - row * (M + 1);
+    const int grow = row0 + row;
+    lds[k * NP + row] = grow < nrows ? in[(size_t)grow * kxs + k] : cpx<T>{(T)0, (T)0};
+  }
+  __syncthreads();
+  constexpr int H = M / 2 + 1;
+  for (int idx = threadIdx.x; idx < NP * H; idx += blockDim.x) {
+    const int row = idx / H, k = idx - row * H;
+    const int m = M - k;
+    const cpx<T> xk = lds[k * NP + row];
+    const cpx<T> xm = lds[m * NP + row];
+    // Z[k] = (Xk + conj Xm) + i W^{-k} (Xk - conj Xm)
+    const cpx<T> dk{xk.x - xm.x, xk.y + xm.y};
+    const cpx<T> rk = cmulc(dk, tw2[k]);
+    const cpx<T> zk{xk.x + xm.x - rk.y, xk.y - xm.y + rk.x};
+    const cpx<T> dm{xm.x - xk.x, xm.y + xk.y};
+    const cpx<T> rm = cmulc(dm, tw2[m]);
+    const cpx<T> zm{xm.x + xk.x - rm.y, xm.y - xk.y + rm.x};
+    lds[k * NP + row] = zk;
+    if (m < M && m != k) lds[m * NP + row] = zm;
+  }
+  __syncthreads();
+  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
+  cpx<T> v[PlanInfo<M>::E];
+  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NP + pp]; });
+  __syncthreads();
+  run_fft<T, M, true>(v, lds, tw, p, jt, NP, [&](int pp, int e, cpx<T> val) { lds[e * NP + pp] = val; });
+  __syncthreads();
+  using V2 = typename io2<IO>::t;
+  const int half = n_out / 2;
+  for (int idx = threadIdx.x; idx < NP * half; idx += blockDim.x) {
+    const int row = idx / half, n = idx - row * half;
+    const int grow = row0 + row;
+    if (grow >= nrows) continue;
+    const cpx<T> z = lds[n * NP + row];
+    const size_t off = (size_t)grow * row_len + 2 * n;
+    const size_t eoff = (size_t)(grow % rows_per_comp) * row_len + 2 * n;
+    const double2 e2 = *reinterpret_cast<const double2*>(eps + eoff);
+    const V2 j2 = *reinterpret_cast<const V2*>(J + off);
+    V2 r;
+    r.x = (IO)(((T)(ep.ca * e2.x + ep.c0)) * (T)j2.x + ((T)(ep.cb * e2.x + ep.cb0)) * z.x);
+    r.y = (IO)(((T)(ep.ca * e2.y + ep.c0)) * (T)j2.y + ((T)(ep.cb * e2.y + ep.cb0)) * z.y);
+    *reinterpret_cast<V2*>(y + off) = r;
+  }
+}
+
+// ------------------------------------------------------------------ y pass
+template <typename T, int M, bool INV>
+__global__ __launch_bounds__((YCfg<T, M>::BLOCK)) void k_y_pass(const cpx<T>* __restrict__ in,
+                                                               cpx<T>* __restrict__ out, int kxn, int kxs,
+                                                               int rows_in, int n_in, int rows_out,
+                                                               int n_out, const cpx<T>* __restrict__ tw_g) {
+  using C = YCfg<T, M>;
+  constexpr int NP = C::NP;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = lds + M * NP;
+  load_table<T, M>(tw, tw_g, M);
+  __syncthreads();
+  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
+  const int kx = blockIdx.x * NP + p;
+  const bool ok = kx < kxn;
+  const cpx<T>* src = in + (size_t)blockIdx.y * rows_in * kxs + kx;
+  cpx<T>* dst = out + (size_t)blockIdx.y * rows_out * kxs + kx;
+  cpx<T> v[PlanInfo<M>::E];
+  load_first<T, M>(v, p, jt, [&](int, int e) {
+    return (ok && e < n_in) ? src[(size_t)e * kxs] : cpx<T>{(T)0, (T)0};
+  });
+  run_fft<T, M, INV>(v, lds, tw, p, jt, NP, [&](int, int e, cpx<T> val) {
+    if (ok && e < n_out) dst[(size_t)e * kxs] = val;
+  });
+}
+
+// ------------------------------------------------------------------ z pass
+template <typename T, int M, int NC, int MODE>
+__global__ __launch_bounds__((ZCfg<T, M, NC>::BLOCK)) void k_z_pass(
+    const cpx<T>* in, cpx<T>* out, int kxn, int kxs, int ny, int rows_in,
+    int n_in, int rows_out, int n_out, const T* __restrict__ lam, const cpx<T>* __restrict__ tw_g) {
+  using C = ZCfg<T, M, NC>;
+  constexpr int W = C::W, NP = C::NP;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = lds + M * NP;
+  load_table<T, M>(tw, tw_g, M);
+  __syncthreads();
+  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
+  const int comp = p / W, c = p - comp * W;
+  const int kx0 = blockIdx.x * W;
+  const int kx = kx0 + c;
+  const int ky = blockIdx.y;
+  const bool ok = kx < kxn;
+  const size_t plane = (size_t)ny * kxs;
+  const cpx<T>* src = in + ((size_t)comp * rows_in) * plane + (size_t)ky * kxs + kx;
+  cpx<T>* dst = out + ((size_t)comp * rows_out) * plane + (size_t)ky * kxs + kx;
+  cpx<T> v[PlanInfo<M>::E];
+  load_first<T, M>(v, p, jt, [&](int, int e) {
+    return (ok && e < n_in) ? src[(size_t)e * plane] : cpx<T>{(T)0, (T)0};
+  });
+  if constexpr (MODE == Z_FWD || MODE == Z_INV) {
+    run_fft<T, M, MODE == Z_INV>(v, lds, tw, p, jt, NP, [&](int, int e, cpx<T> val) {
+      if (ok && e < n_out) dst[(size_t)e * plane] = val;
+    });
+  } else {
+    run_fft<T, M, false>(v, lds, tw, p, jt, NP, [&](int pp, int e, cpx<T> val) { lds[e * NP + pp] = val; });
+    __syncthreads();
+    // spectral 3x3 multiply, Lambda octant-compressed with reflection signs
+    const int kyc = ky <= ny / 2 ? ky : ny - ky;
+    const T sy = ky <= ny / 2 ? (T)1 : (T)-1;
+    const size_t lky = (size_t)(ny / 2 + 1) * kxs;
+    const size_t lcomp = (size_t)(M / 2 + 1) * lky;
+    for (int idx = threadIdx.x; idx < W * M; idx += blockDim.x) {
+      const int cc = idx % W, kz = idx / W;
+      const int kxx = kx0 + cc;
+      if (kxx >= kxn) continue;
+      const int kzc = kz <= M / 2 ? kz : M - kz;
+      const T sz = kz <= M / 2 ? (T)1 : (T)-1;
+      const T* L = lam + (size_t)kzc * lky + (size_t)kyc * kxs + kxx;
+      const T lxx = L[0], lyy = L[lcomp], lzz = L[2 * lcomp];
+      const T lxy = sy * L[3 * lcomp], lxz = sz * L[4 * lcomp], lyz = sy * sz * L[5 * lcomp];
+      cpx<T>* q = lds + kz * NP + cc;
+      const cpx<T> jx = q[0], jy = q[W], jz = q[2 * W];
+      q[0] = cpx<T>{lxx * jx.x + lxy * jy.x + lxz * jz.x, lxx * jx.y + lxy * jy.y + lxz * jz.y};
+      q[W] = cpx<T>{lxy * jx.x + lyy * jy.x + lyz * jz.x, lxy * jx.y + lyy * jy.y + lyz * jz.y};
+      q[2 * W] = cpx<T>{lxz * jx.x + lyz * jy.x + lzz * jz.x, lxz * jx.y + lyz * jy.y + lzz * jz.y};
+    }
+    __syncthreads();
+    load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NP + pp]; });
+    __syncthreads();
+    run_fft<T, M, true>(v, lds, tw, p, jt, NP, [&](int, int e, cpx<T> val) {
+      if (ok && e < n_out) dst[(size_t)e * plane] = val;
+    });
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+bool length_supported(int M) {
+  switch (M) {
+#define X(m) case m:
+    MOT_FOR_EACH_LEN(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T, typename IO>
+hipError_t x_forward(const IO* in, void* out, int M, int nrows, int row_len, int n_in, int kxs,
+                     const void* tw, const void* tw2, hipStream_t s) {
+  switch (M) {
+#define X(m)                                                                                          \
+  case m: {                                                                                           \
+    using C = XCfg<T, m>;                                                                             \
+    const size_t sh = (size_t)((m + 1) * C::NP + 2 * m + 1) * sizeof(cpx<T>);                         \
+    hipLaunchKernelGGL((k_x_forward<T, IO, m>), dim3((nrows + C::NP - 1) / C::NP), dim3(C::BLOCK), sh, \
+                       s, in, (cpx<T>*)out, nrows, row_len, n_in, kxs, (const cpx<T>*)tw,              \
+                       (const cpx<T>*)tw2);                                                           \
+    return hipGetLastError();                                                                         \
+  }
+    MOT_FOR_EACH_LEN(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, typename IO>
+hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
+                     int nrows, int rows_per_comp, int row_len, int n_out, int kxs, const void* tw,
+                     const void* tw2, hipStream_t s) {
+  switch (M) {
+#define X(m)                                                                                          \
+  case m: {                                                                                           \
+    using C = XCfg<T, m>;                                                                             \
+    const size_t sh = (size_t)((m + 1) * C::NP + 2 * m + 1) * sizeof(cpx<T>);                         \
+    hipLaunchKernelGGL((k_x_inverse<T, IO, m>), dim3((nrows + C::NP - 1) / C::NP), dim3(C::BLOCK), sh, \
+                       s, (const cpx<T>*)in, y, J, eps, ep, nrows, rows_per_comp, row_len, n_out, kxs, \
+                       (const cpx<T>*)tw, (const cpx<T>*)tw2);                                        \
+    return hipGetLastError();                                                                         \
+  }
+    MOT_FOR_EACH_LEN(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kxs, int planes,
+                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s) {
+  switch (M) {
+#define X(m)                                                                                       \
+  case m: {                                                                                        \
+    using C = YCfg<T, m>;                                                                          \
+    const size_t sh = (size_t)(m * C::NP + m) * sizeof(cpx<T>);                                    \
+    dim3 g((kx + C::NP - 1) / C::NP, planes);                                                      \
+    if (inverse)                                                                                   \
+      hipLaunchKernelGGL((k_y_pass<T, m, true>), g, dim3(C::BLOCK), sh, s, (const cpx<T>*)in,      \
+                         (cpx<T>*)out, kx, kxs, rows_in, n_in, rows_out, n_out, (const cpx<T>*)tw); \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_y_pass<T, m, false>), g, dim3(C::BLOCK), sh, s, (const cpx<T>*)in,     \
+                         (cpx<T>*)out, kx, kxs, rows_in, n_in, rows_out, n_out, (const cpx<T>*)tw); \
+    return hipGetLastError();                                                                      \
+  }
+    MOT_FOR_EACH_LEN(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int M, int NC>
+static hipError_t z_launch(const void* in, void* out, int mode, int kx, int kxs, int ny, int rows_in,
+                           int n_in, int rows_out, int n_out, const T* lam, const void* tw, hipStream_t s) {
+  using C = ZCfg<T, M, NC>;
+  const size_t sh = (size_t)(M * C::NP + M) * sizeof(cpx<T>);
+  dim3 g((kx + C::W - 1) / C::W, ny);
+  const cpx<T>* i_ = (const cpx<T>*)in;
+  cpx<T>* o_ = (cpx<T>*)out;
+  const cpx<T>* t_ = (const cpx<T>*)tw;
+  if (mode == Z_FWD)
+    hipLaunchKernelGGL((k_z_pass<T, M, NC, Z_FWD>), g, dim3(C::BLOCK), sh, s, i_, o_, kx, kxs, ny, rows_in,
+                       n_in, rows_out, n_out, lam, t_);
+  else if (mode == Z_INV)
+    hipLaunchKernelGGL((k_z_pass<T, M, NC, Z_INV>), g, dim3(C::BLOCK), sh, s, i_, o_, kx, kxs, ny, rows_in,
+                       n_in, rows_out, n_out, lam, t_);
+  else if (NC == 3)
+    hipLaunchKernelGGL((k_z_pass<T, M, 3, Z_FUSED>), g, dim3(ZCfg<T, M, 3>::BLOCK), sh, s, i_, o_, kx, kxs,
+                       ny, rows_in, n_in, rows_out, n_out, lam, t_);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
+                  int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,
+                  hipStream_t s) {
+  switch (M) {
+#define X(m)                                                                                      \
+  case m:                                                                                         \
+    return nc == 3 ? z_launch<T, m, 3>(in, out, mode, kx, kxs, ny, rows_in, n_in, rows_out, n_out, \
+                                       lam, tw, s)                                                \
+                   : z_launch<T, m, 1>(in, out, mode, kx, kxs, ny, rows_in, n_in, rows_out, n_out, \
+                                       lam, tw, s);
+    MOT_FOR_EACH_LEN(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t x_forward<float, float>(const float*, void*, int, int, int, int, int, const void*,
+                                            const void*, hipStream_t);
+template hipError_t x_forward<float, double>(const double*, void*, int, int, int, int, int, const void*,
+                                             const void*, hipStream_t);
+template hipError_t x_forward<double, double>(const double*, void*, int, int, int, int, int, const void*,
+                                              const void*, hipStream_t);
+template hipError_t x_inverse<float, float>(const void*, float*, const float*, const double*, Epilogue, int,
+                                            int, int, int, int, int, const void*, const void*, hipStream_t);
+template hipError_t x_inverse<float, double>(const void*, double*, const double*, const double*, Epilogue,
+                                             int, int, int, int, int, int, const void*, const void*,
+                                             hipStream_t);
+template hipError_t x_inverse<double, double>(const void*, double*, const double*, const double*, Epilogue,
+                                              int, int, int, int, int, int, const void*, const void*,
+                                              hipStream_t);
+template hipError_t y_pass<float>(const void*, void*, int, bool, int, int, int, int, int, int, int,
+                                  const void*, hipStream_t);
+template hipError_t y_pass<double>(const void*, void*, int, bool, int, int, int, int, int, int, int,
+                                   const void*, hipStream_t);
+template hipError_t z_pass<float>(const void*, void*, int, int, int, int, int, int, int, int, int, int,
+                                  const float*, const void*, hipStream_t);
+template hipError_t z_pass<double>(const void*, void*, int, int, int, int, int, int, int, int, int, int,
+                                   const double*, const void*, hipStream_t);
+
+}  // namespace motfft

@@ -1,0 +1,870 @@
+// C ABI of the MOT-JVIE hot path: context, Z0 product (Eq. 11/12), history
+// update, excitation (Eq. 7/8) and the MOT step (Eq. 3) with a
+// device-resident TFQMR solve.  See include/mot_jvie.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fft_core.h"
+#include "fft_passes.h"
+#include "mot_internal.h"
+
+using motfft::cpx;
+using namespace motimpl;
+
+struct mot_ctx {
+  mot_grid grid;
+  int nx, ny, nz, px, py, pz, kx, kxs, nl, alpha, nq;
+  double L;
+  long long N, n3;
+  mot_precision prec;
+  int ring_f64;
+  hipStream_t stream;
+  // twiddles: [0] float, [1] double
+  void* twx[2];
+  void* tw2x[2];
+  void* twy[2];
+  void* twz[2];
+  double* eps;
+  bool have_eps, have_spectra;
+  double* lam0_64;
+  float* lam0_32;
+  void* lamh;          // lags 1..nl, ring precision
+  size_t lam_comp;     // elements per component per lag: (nz+1)(ny+1)kxs
+  void* wsA;
+  void* wsB;
+  void* spec;          // MAC output, ring precision, 3*pz*py*kxs complex
+  void* ring;
+  size_t slot_elems;   // complex elements per ring slot
+  long long nstep;
+  int head;
+  double* hrhs;
+  double* kv[13];
+  double* partials;
+  double* scal;
+  double* hscal;       // pinned host mirror
+  hipEvent_t ev[3];
+  // kernel timing (mot_profile)
+  int prof_on, prof_used, prof_cap;
+  hipEvent_t* prof_ev;
+  int* prof_cls;
+  double prof_ms[MOT_PROF_NCLASS];
+  long long prof_cnt[MOT_PROF_NCLASS];
+  double spectra_imag;
+  size_t bytes;
+  char err[512];
+};
+
+namespace {
+
+enum { V_X = 0, V_B, V_W, V_U, V_U2, V_V, V_D, V_AU, V_AU2, V_RT, V_TMP, V_XO, V_RO };
+
+int set_err(mot_ctx* c, int code, const char* fmt, const char* a = "", int line = 0) {
+  if (c) snprintf(c->err, sizeof(c->err), fmt, a, line);
+  return code;
+}
+int fail_hip(mot_ctx* c, hipError_t e, const char* what, int line) {
+  if (c) snprintf(c->err, sizeof(c->err), "%s failed at line %d: %s", what, line, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? MOT_ENOMEM : MOT_EHIP;
+}
+#define HT(call)                                                  \
+  do {                                                            \
+    hipError_t e_ = (call);                                       \
+    if (e_ != hipSuccess) return fail_hip(c, e_, #call, __LINE__); \
+  } while (0)
+#define TRY(call)          \
+  do {                     \
+    int r_ = (call);       \
+    if (r_ != MOT_OK) return r_; \
+  } while (0)
+
+long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
+
+enum Kind { K_XF = 0, K_YF, K_ZFUSED, K_YI, K_XI, K_ZF, K_MAC, K_ZI, K_KRY, K_EINC };
+
+int prof_flush(mot_ctx* c) {
+  if (c->prof_used == 0) return MOT_OK;
+  HT(hipEventSynchronize(c->prof_ev[2 * c->prof_used - 1]));
+  for (int i = 0; i < c->prof_used; ++i) {
+    float ms = 0.f;
+    HT(hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+    c->prof_ms[c->prof_cls[i]] += ms;
+    c->prof_cnt[c->prof_cls[i]] += 1;
+  }
+  c->prof_used = 0;
+  return MOT_OK;
+}
+
+// Brackets one launch with an event pair when timing is on.
+struct Prof {
+  mot_ctx* c;
+  int idx = -1;
+  Prof(mot_ctx* c_, int kind, bool f64) : c(c_) {
+    if (!c->prof_on) return;
+    if (c->prof_used == c->prof_cap && prof_flush(c) != MOT_OK) return;
+    idx = c->prof_used++;
+    c->prof_cls[idx] = 2 * kind + (f64 ? 1 : 0);
+    (void)hipEventRecord(c->prof_ev[2 * idx], c->stream);
+  }
+  ~Prof() {
+    if (idx >= 0) (void)hipEventRecord(c->prof_ev[2 * idx + 1], c->stream);
+  }
+};
+#define PROF(kind, f64) Prof prof_scope_##__LINE__(c, kind, f64)
+#define HTP(kind, f64, call) \
+  do {                       \
+    Prof p_(c, kind, f64);   \
+    HT(call);                \
+  } while (0)
+
+int nlags_of(const mot_grid* g) {
+  if (g->nlags > 0) return g->nlags;
+  const long long ax = 2LL * g->nx - 1, ay = 2LL * g->ny - 1, az = 2LL * g->nz - 1;
+  if (g->alpha > 0) {
+    // least c with (2 c alpha)^2 >= 3 sum (2N_i - 1)^2
+    const long long m = 3 * (ax * ax + ay * ay + az * az);
+    long long c = (long long)floor(sqrt((double)m) / (2.0 * g->alpha));
+    if (c < 0) c = 0;
+    while ((2 * c * g->alpha) * (2 * c * g->alpha) < m) ++c;
+    while (c > 0 && (2 * (c - 1) * g->alpha) * (2 * (c - 1) * g->alpha) >= m) --c;
+    return (int)c + 2;
+  }
+  const double rmax = 0.5 * sqrt((double)(ax * ax + ay * ay + az * az));
+  return (int)ceil(rmax / g->cdt) + 2;
+}
+
+bool grid_ok(const mot_grid* g) {
+  if (!g || g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || (g->nx & 1)) return false;
+  if (g->alpha < 0 || (g->alpha == 0 && !(g->cdt > 0.0))) return false;
+  if (g->quad < 0 || g->quad > 32 || g->quad == 1) return false;
+  return motfft::length_supported(g->nx) && motfft::length_supported(2 * g->ny) &&
+         motfft::length_supported(2 * g->nz);
+}
+
+__global__ void k_fill_zero(uint4* p, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+int zero_bytes(mot_ctx* c, void* p, size_t bytes) {
+  if (!p || bytes == 0) return MOT_OK;
+  hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, c->stream, (uint4*)p, bytes / 16);
+  HT(hipGetLastError());
+  return MOT_OK;
+}
+
+int dmalloc(mot_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return MOT_OK;
+  bytes = (size_t)round_up((long long)bytes, 256);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    snprintf(c->err, sizeof(c->err), "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return MOT_ENOMEM;
+  }
+  c->bytes += bytes;
+  return MOT_OK;
+}
+
+// exp(-2 pi i q / M), q = 0..count-1, in both precisions
+int make_twiddles(mot_ctx* c, int M, int count, void** out) {
+  std::vector<double> d(2 * count);
+  std::vector<float> f(2 * count);
+  for (int q = 0; q < count; ++q) {
+    // angle reduced to [0, pi/4]-accurate evaluation via long double
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)q / (long double)M;
+    d[2 * q] = (double)cosl(a);
+    d[2 * q + 1] = (double)sinl(a);
+    f[2 * q] = (float)cosl(a);
+    f[2 * q + 1] = (float)sinl(a);
+  }
+  TRY(dmalloc(c, &out[0], sizeof(float) * 2 * count));
+  TRY(dmalloc(c, &out[1], sizeof(double) * 2 * count));
+  HT(hipMemcpy(out[0], f.data(), sizeof(float) * 2 * count, hipMemcpyHostToDevice));
+  HT(hipMemcpy(out[1], d.data(), sizeof(double) * 2 * count, hipMemcpyHostToDevice));
+  return MOT_OK;
+}
+
+// ---------------------------------------------------------------- history MAC
+// S(k) = sum_{j=1..nvalid} Lambda_j(k) J^_{n+1-j}(k): one thread per octant
+// frequency (kx, kyc, kzc); its (up to) four mirror points ky in {kyc, Py-kyc},
+// kz in {kzc, Pz-kzc} share the six Lambda_j values read once per lag.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mac(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
+                                             cpx<T>* __restrict__ out, int nl, int nvalid, int head, int nx,
+                                             int ny, int nz, int kxs) {
+  const long long cnt = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= cnt) return;
+  const int kx = (int)(id % (nx + 1)), kyc = (int)((id / (nx + 1)) % (ny + 1)),
+            kzc = (int)(id / ((long long)(nx + 1) * (ny + 1)));
+  const int py = 2 * ny, pz = 2 * nz;
+  const size_t plane = (size_t)py * kxs;          // one kz plane of one component
+  const size_t comp = (size_t)pz * plane;         // one component
+  const size_t slot = 3 * comp;
+  const size_t lcomp = (size_t)(nz + 1) * (ny + 1) * kxs;
+  const size_t lo = ((size_t)kzc * (ny + 1) + kyc) * kxs + kx;
+  // mirror points (a: kz side, b: ky side); a duplicate of point 0 on the
+  // kyc in {0, Ny} or kzc in {0, Nz} planes is computed but not stored
+  const bool dupy = (kyc == 0 || kyc == ny), dupz = (kzc == 0 || kzc == nz);
+  size_t off[4];
+  bool keep[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int a = i >> 1, b = i & 1;
+    const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
+    off[i] = (size_t)(kz % pz) * plane + (size_t)(ky % py) * kxs + kx;
+    keep[i] = !((a && dupz) || (b && dupy));
+  }
+  cpx<T> acc[4][3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[i][q] = cpx<T>{(T)0, (T)0};
+  for (int j = 1; j <= nvalid; ++j) {
+    const int s = (head - (j - 1) + nl) % nl;
+    const T* L = lamh + (size_t)(j - 1) * 6 * lcomp + lo;
+    const T lxx = L[0], lyy = L[lcomp], lzz = L[2 * lcomp], lxy = L[3 * lcomp], lxz = L[4 * lcomp],
+            lyz = L[5 * lcomp];
+    const cpx<T>* R = ring + (size_t)s * slot;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T sy = (i & 1) ? (T)-1 : (T)1, sz = (i >> 1) ? (T)-1 : (T)1;
+      const cpx<T> jx = R[off[i]], jy = R[comp + off[i]], jz = R[2 * comp + off[i]];
+      const T xy = sy * lxy, xz = sz * lxz, yz = sy * sz * lyz;
+      acc[i][0].x += lxx * jx.x + xy * jy.x + xz * jz.x;
+      acc[i][0].y += lxx * jx.y + xy * jy.y + xz * jz.y;
+      acc[i][1].x += xy * jx.x + lyy * jy.x + yz * jz.x;
+      acc[i][1].y += xy * jx.y + lyy * jy.y + yz * jz.y;
+      acc[i][2].x += xz * jx.x + yz * jy.x + lzz * jz.x;
+      acc[i][2].y += xz * jx.y + yz * jy.y + lzz * jz.y;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (keep[i])
+#pragma unroll
+      for (int q = 0; q < 3; ++q) out[q * comp + off[i]] = acc[i][q];
+}
+
+// ---------------------------------------------------------------- excitation
+__global__ void k_einc(mot_pulse p, double t, const double* __restrict__ eps, double* __restrict__ out, int nx,
+                       int ny, int nz) {
+  const long long N = (long long)nx * ny * nz;
+  const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int ix = (int)(m % nx), iy = (int)((m / nx) % ny), iz = (int)(m / ((long long)nx * ny));
+  const double x = ix + 0.5 - 0.5 * nx, y = iy + 0.5 - 0.5 * ny, z = iz + 0.5 - 0.5 * nz;
+  const double tau = t - p.t0 - (p.k[0] * x + p.k[1] * y + p.k[2] * z);
+  const double w = 2.0 * 3.14159265358979323846 * p.f0;
+  const double env = exp(-tau * tau / (2.0 * p.sigma * p.sigma));
+  const double dg = env * (-(tau / (p.sigma * p.sigma)) * cos(w * tau) - w * sin(w * tau));
+  const double a = (eps[m] - 1.0) * p.amp * dg;
+  out[m] = a * p.e[0];
+  out[N + m] = a * p.e[1];
+  out[2 * N + m] = a * p.e[2];
+}
+
+}  // namespace
+
+namespace motimpl {
+hipError_t launch_mac(const void* ring, const void* lamh, void* out, int f64, int nl, int nvalid, int head, int nx,
+                      int ny, int nz, int kxs, hipStream_t s) {
+  const long long cnt = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  dim3 g((unsigned)((cnt + 255) / 256));
+  if (f64)
+    hipLaunchKernelGGL(k_mac<double>, g, dim3(256), 0, s, (const cpx<double>*)ring, (const double*)lamh,
+                       (cpx<double>*)out, nl, nvalid, head, nx, ny, nz, kxs);
+  else
+    hipLaunchKernelGGL(k_mac<float>, g, dim3(256), 0, s, (const cpx<float>*)ring, (const float*)lamh,
+                       (cpx<float>*)out, nl, nvalid, head, nx, ny, nz, kxs);
+  return hipGetLastError();
+}
+hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* out, int nx, int ny, int nz,
+                       hipStream_t s) {
+  const long long N = (long long)nx * ny * nz;
+  hipLaunchKernelGGL(k_einc, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, *p, t, eps, out, nx, ny, nz);
+  return hipGetLastError();
+}
+}  // namespace motimpl
+
+namespace {
+
+// ---------------------------------------------------------------- Green product
+// y = epilogue(J, G J) with spectra `lam` (precision T) through the five passes.
+template <typename T, typename IO>
+int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue ep) {
+  const int ti = sizeof(T) == 8 ? 1 : 0;
+  hipStream_t s = c->stream;
+  const int rows = 3 * c->nz * c->ny;
+  const bool d = ti == 1;
+  HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nx, c->nx / 2, c->kxs, c->twx[ti], c->tw2x[ti], s)));
+  HTP(K_YF, d, motfft::y_pass<T>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py, c->py,
+                                 c->twy[ti], s));
+  HTP(K_ZFUSED, d, motfft::z_pass<T>(c->wsB, c->wsB, c->pz, motfft::Z_FUSED, 3, c->kx, c->kxs, c->py, c->nz, c->nz,
+                                     c->nz, c->nz, lam, c->twz[ti], s));
+  HTP(K_YI, d, motfft::y_pass<T>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny, c->ny,
+                                 c->twy[ti], s));
+  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, J, c->eps, ep, c->nx, rows, c->nz * c->ny, c->nx, c->nx,
+                                         c->kxs, c->twx[ti], c->tw2x[ti], s)));
+  return MOT_OK;
+}
+
+const motfft::Epilogue EP_Z0{0.5, 0.0, -1.0, 1.0};      // D J - X (G J)
+const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};        // G J
+const motfft::Epilogue EP_HIST{-0.5, 0.0, 1.0, -1.0};   // -(eps/2) J + X (G J)
+
+// Z0 product on FP64 vectors in the requested compute precision.
+int apply_z0(mot_ctx* c, const double* in, double* out, bool f64) {
+  if (f64) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0);
+  return green_product<float, double>(c, in, out, c->lam0_32, EP_Z0);
+}
+
+int reduce_sync(mot_ctx* c) {
+  HT(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->stream));
+  HT(hipStreamSynchronize(c->stream));
+  return MOT_OK;
+}
+
+struct SolveOut {
+  int iters = 0, matvecs = 0, matvecs64 = 0;
+  double relres = 0.0;
+};
+
+// TFQMR for Z0 x = b from x = 0 (b, x: FP64 device vectors; x may not alias b).
+int tfqmr(mot_ctx* c, bool f64, const double* b, double* x, double tol, int max_iter, SolveOut* so) {
+  hipStream_t s = c->stream;
+  const long long n = c->n3;
+  double** v = c->kv;
+  double* P = c->partials;
+  HTP(K_KRY, true, dot_partial(b, b, n, P, s));
+  HTP(K_KRY, true, reduce_to(P, c->scal, S_B2, 0, s));
+  TRY(reduce_sync(c));
+  const double b2 = c->hscal[S_B2];
+  if (!std::isfinite(b2)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
+  if (b2 == 0.0) {
+    HTP(K_KRY, true, vec_zero(x, n, s));
+    so->relres = 0.0;
+    return MOT_OK;
+  }
+  const double bnorm = sqrt(b2);
+  auto mv = [&](const double* in, double* out) {
+    so->matvecs++;
+    if (f64) so->matvecs64++;
+    return apply_z0(c, in, out, f64);
+  };
+  HTP(K_KRY, true, tfqmr_init(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));
+  TRY(mv(v[V_U], v[V_AU]));
+  HTP(K_KRY, true, tfqmr_v0(v[V_V], v[V_AU], v[V_RT], n, P, s));
+  HTP(K_KRY, true, reduce_to(P, c->scal, S_SIGMA, 0, s));
+  HTP(K_KRY, true, sc_init(c->scal, s));
+  for (int it = 1; it <= max_iter; ++it) {
+    so->iters = it;
+    HTP(K_KRY, true, sc_alpha(c->scal, s));
+    HTP(K_KRY, true, tfqmr_half0(x, v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], c->scal, false, n, P, s));
+    HTP(K_KRY, true, reduce_to(P, c->scal, S_W2, 0, s));
+    HTP(K_KRY, true, sc_half(c->scal, true, s));
+    TRY(mv(v[V_U2], v[V_AU2]));
+    HTP(K_KRY, true, tfqmr_half1(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], c->scal, n, P, s));
+    HTP(K_KRY, true, reduce_to(P, c->scal, S_W2, 0, s));
+    HTP(K_KRY, true, sc_half(c->scal, false, s));
+    HTP(K_KRY, true, tfqmr_rho(x, v[V_D], v[V_W], v[V_RT], c->scal, n, P, s));
+    HTP(K_KRY, true, reduce_to(P, c->scal, S_RHONEW, 0, s));
+    HTP(K_KRY, true, sc_beta(c->scal, s));
+    TRY(reduce_sync(c));
+    const double* h = c->hscal;
+    const bool breakdown = h[S_FLAG] != 0.0;
+    const double bound = h[S_TAU] * sqrt(2.0 * it + 1.0);
+    if (!std::isfinite(bound)) return set_err(c, MOT_ENONFINITE, "TFQMR quasi-residual is not finite%s%d");
+    if (bound <= tol * bnorm || breakdown || it == max_iter) {
+      // true residual with the solver's own operator
+      TRY(mv(x, v[V_TMP]));
+      HTP(K_KRY, true, vec_sub(b, v[V_TMP], v[V_TMP], n, P, s));
+      HTP(K_KRY, true, reduce_to(P, c->scal, S_R2, 0, s));
+      TRY(reduce_sync(c));
+      so->relres = sqrt(c->hscal[S_R2]) / bnorm;
+      if (!std::isfinite(so->relres)) return set_err(c, MOT_ENONFINITE, "TFQMR residual is not finite%s%d");
+      if (so->relres <= tol) return MOT_OK;
+      if (breakdown) return set_err(c, MOT_EBREAKDOWN, "TFQMR breakdown (rho or sigma = 0)%s%d");
+      if (it == max_iter) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
+    }
+    HTP(K_KRY, true, tfqmr_u(v[V_U], v[V_W], v[V_U2], c->scal, n, s));
+    TRY(mv(v[V_U], v[V_AU]));
+    HTP(K_KRY, true, tfqmr_v(v[V_V], v[V_AU], v[V_AU2], v[V_RT], c->scal, n, P, s));
+    HTP(K_KRY, true, reduce_to(P, c->scal, S_SIGMA, 0, s));
+  }
+  return set_err(c, MOT_ENOCONV, "TFQMR did not converge (max_iter < 1)%s%d");
+}
+
+// Solve Z0 x = b in the context precision; result in x.
+int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_stats* st) {
+  SolveOut so;
+  int rc = MOT_OK;
+  int refinements = 0;
+  if (c->prec == MOT_F64 || c->prec == MOT_F32) {
+    rc = tfqmr(c, c->prec == MOT_F64, b, x, tol, max_iter, &so);
+  } else {
+    // FP32 inner TFQMR inside an FP64 residual-correction loop
+    hipStream_t s = c->stream;
+    const long long n = c->n3;
+    double** v = c->kv;
+    double* P = c->partials;
+    HTP(K_KRY, true, dot_partial(b, b, n, P, s));
+    HTP(K_KRY, true, reduce_to(P, c->scal, S_B2, 0, s));
+    TRY(reduce_sync(c));
+    const double bnorm = sqrt(c->hscal[S_B2]);
+    if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
+    HTP(K_KRY, true, vec_zero(x, n, s));
+    if (bnorm == 0.0) {
+      so.relres = 0.0;
+    } else {
+      HTP(K_KRY, true, vec_copy_scale(b, 1.0, v[V_RO], n, s));
+      double rnorm = bnorm;
+      const int max_ref = 12;
+      while (true) {
+        ++refinements;
+        double tin = 0.5 * tol * bnorm / rnorm;
+        if (tin < 2e-6) tin = 2e-6;
+        SolveOut inner;
+        int irc = tfqmr(c, false, v[V_RO], v[V_XO], tin, max_iter, &inner);
+        so.iters += inner.iters;
+        so.matvecs += inner.matvecs;
+        if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
+        HTP(K_KRY, true, vec_add(x, v[V_XO], x, n, P, s));  // x += correction
+        TRY(apply_z0(c, x, v[V_TMP], true));
+        so.matvecs++;
+        so.matvecs64++;
+        HTP(K_KRY, true, vec_sub(b, v[V_TMP], v[V_RO], n, P, s));
+        HTP(K_KRY, true, reduce_to(P, c->scal, S_R2, 0, s));
+        TRY(reduce_sync(c));
+        rnorm = sqrt(c->hscal[S_R2]);
+        so.relres = rnorm / bnorm;
+        if (!std::isfinite(rnorm)) return set_err(c, MOT_ENONFINITE, "refined residual is not finite%s%d");
+        if (so.relres <= tol) break;
+        if (refinements >= max_ref || so.iters >= max_iter) {
+          rc = set_err(c, MOT_ENOCONV, "refinement did not reach the tolerance%s%d");
+          break;
+        }
+      }
+    }
+  }
+  if (st) {
+    st->iters = so.iters;
+    st->matvecs = so.matvecs;
+    st->matvecs_f64 = so.matvecs64;
+    st->refinements = refinements;
+    st->relres = so.relres;
+  }
+  return rc;
+}
+
+template <typename Tr>
+int history_update_t(mot_ctx* c, const double* J) {
+  const int ti = sizeof(Tr) == 8 ? 1 : 0;
+  hipStream_t s = c->stream;
+  const int rows = 3 * c->nz * c->ny;
+  const int slot = (int)(c->nstep % c->nl);
+  cpx<Tr>* dst = (cpx<Tr>*)c->ring + (size_t)slot * c->slot_elems;
+  const bool d = ti == 1;
+  HTP(K_XF, d, (motfft::x_forward<Tr, double>(J, c->wsA, c->nx, rows, c->nx, c->nx / 2, c->kxs, c->twx[ti],
+                                              c->tw2x[ti], s)));
+  HTP(K_YF, d, motfft::y_pass<Tr>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py,
+                                  c->py, c->twy[ti], s));
+  HTP(K_ZF, d, motfft::z_pass<Tr>(c->wsB, dst, c->pz, motfft::Z_FWD, 3, c->kx, c->kxs, c->py, c->nz, c->nz, c->pz,
+                                  c->pz, nullptr, c->twz[ti], s));
+  const long long nvalid = c->nstep + 1 < c->nl ? c->nstep + 1 : c->nl;
+  HTP(K_MAC, d, launch_mac(c->ring, c->lamh, c->spec, sizeof(Tr) == 8, c->nl, (int)nvalid, slot, c->nx, c->ny,
+                           c->nz, c->kxs, s));
+  HTP(K_ZI, d, motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz,
+                                  c->nz, c->nz, nullptr, c->twz[ti], s));
+  HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
+                                  c->ny, c->twy[ti], s));
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, EP_HIST, c->nx, rows, c->nz * c->ny,
+                                              c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s)));
+  c->head = slot;
+  c->nstep += 1;
+  return MOT_OK;
+}
+
+int history_update_impl(mot_ctx* c, const double* J) {
+  return c->ring_f64 ? history_update_t<double>(c, J) : history_update_t<float>(c, J);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* mot_strerror(int status) {
+  switch (status) {
+    case MOT_OK: return "ok";
+    case MOT_EINVAL: return "invalid argument";
+    case MOT_ENOMEM: return "out of device memory";
+    case MOT_EHIP: return "HIP runtime error";
+    case MOT_ENOCONV: return "TFQMR did not converge";
+    case MOT_EBREAKDOWN: return "TFQMR breakdown";
+    case MOT_ENONFINITE: return "non-finite value";
+    case MOT_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char* mot_last_error(const mot_ctx* ctx) { return ctx ? ctx->err : "no context"; }
+
+int32_t mot_length_supported(int32_t n) { return motfft::length_supported(n) ? 1 : 0; }
+
+int32_t mot_nlags(const mot_grid* grid) {
+  if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0) return MOT_EINVAL;
+  if (grid->alpha < 0 || (grid->alpha == 0 && !(grid->cdt > 0.0))) return MOT_EINVAL;
+  return nlags_of(grid);
+}
+
+int64_t mot_zk_nnz(const mot_grid* g, int32_t k) {
+  if (!g || g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || k < 0) return MOT_EINVAL;
+  if (g->alpha < 0 || (g->alpha == 0 && !(g->cdt > 0.0))) return MOT_EINVAL;
+  const double L = g->alpha > 0 ? g->alpha / sqrt(3.0) : g->cdt;
+  const long long a2 = (long long)g->alpha * g->alpha;
+  int64_t total = 0;
+  for (int dz = 0; dz < g->nz; ++dz)
+    for (int dy = 0; dy < g->ny; ++dy)
+      for (int dx = 0; dx < g->nx; ++dx) {
+        bool m;
+        if (g->alpha > 0) {
+          auto m1 = [](int v) { return (long long)(v > 0 ? 2 * v - 1 : 0); };
+          const long long lo = 3 * (m1(dx) * m1(dx) + m1(dy) * m1(dy) + m1(dz) * m1(dz));
+          m = lo < 4LL * (k + 1) * (k + 1) * a2;
+          if (m && k > 2) {
+            const long long hi = 3LL * ((2LL * dx + 1) * (2LL * dx + 1) + (2LL * dy + 1) * (2LL * dy + 1) +
+                                        (2LL * dz + 1) * (2LL * dz + 1));
+            m = hi > 4LL * (k - 2) * (k - 2) * a2;
+          }
+        } else {
+          const double mx = dx > 0 ? dx - 0.5 : 0.0, my = dy > 0 ? dy - 0.5 : 0.0, mz = dz > 0 ? dz - 0.5 : 0.0;
+          const double dmin = sqrt(mx * mx + my * my + mz * mz);
+          const double dmax = sqrt((dx + .5) * (dx + .5) + (dy + .5) * (dy + .5) + (dz + .5) * (dz + .5));
+          m = dmin < (k + 1) * L && dmax > (k - 2) * L;
+        }
+        if (!m) continue;
+        const int nzc = (dx != 0) + (dy != 0) + (dz != 0);
+        static const int w[4] = {3, 3, 5, 9};
+        // offsets +-d: each nonzero component doubles the count
+        const int64_t mult = (int64_t)(dx ? 2 : 1) * (dy ? 2 : 1) * (dz ? 2 : 1);
+        total += mult * w[nzc] * (int64_t)(g->nx - dx) * (g->ny - dy) * (g->nz - dz);
+      }
+  return total;
+}
+
+int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_ctx** out) {
+  if (!out) return MOT_EINVAL;
+  *out = nullptr;
+  if (!grid_ok(grid) || (prec != MOT_F64 && prec != MOT_F32 && prec != MOT_F32_REFINED)) return MOT_EINVAL;
+  mot_ctx* c = new (std::nothrow) mot_ctx();
+  if (!c) return MOT_ENOMEM;
+  memset(c, 0, sizeof(*c));
+  c->grid = *grid;
+  c->nx = grid->nx;
+  c->ny = grid->ny;
+  c->nz = grid->nz;
+  c->px = 2 * c->nx;
+  c->py = 2 * c->ny;
+  c->pz = 2 * c->nz;
+  c->kx = c->nx + 1;
+  c->kxs = (int)round_up(c->kx, 16);
+  c->alpha = grid->alpha;
+  c->L = grid->alpha > 0 ? grid->alpha / sqrt(3.0) : grid->cdt;
+  c->nl = nlags_of(grid);
+  c->nq = grid->quad > 0 ? grid->quad : 20;
+  c->N = (long long)c->nx * c->ny * c->nz;
+  c->n3 = 3 * c->N;
+  c->prec = prec;
+  c->ring_f64 = prec == MOT_F64 ? 1 : 0;
+  c->stream = (hipStream_t)hip_stream;
+  const size_t rsz = c->ring_f64 ? sizeof(double) : sizeof(float);
+  c->lam_comp = (size_t)(c->nz + 1) * (c->ny + 1) * c->kxs;
+  c->slot_elems = (size_t)3 * c->pz * c->py * c->kxs;
+  int rc = MOT_OK;
+  auto fail = [&](int r) {
+    mot_destroy(c);
+    return r;
+  };
+  if ((rc = make_twiddles(c, c->nx, c->nx, c->twx)) != MOT_OK) return fail(rc);
+  if ((rc = make_twiddles(c, 2 * c->nx, c->nx + 1, c->tw2x)) != MOT_OK) return fail(rc);
+  if ((rc = make_twiddles(c, c->py, c->py, c->twy)) != MOT_OK) return fail(rc);
+  if ((rc = make_twiddles(c, c->pz, c->pz, c->twz)) != MOT_OK) return fail(rc);
+  const size_t wsA = (size_t)3 * c->nz * c->ny * c->kxs * 16;
+  const size_t wsB = (size_t)3 * c->nz * c->py * c->kxs * 16;
+  if ((rc = dmalloc(c, (void**)&c->eps, sizeof(double) * c->N)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, &c->wsA, wsA)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, &c->wsB, wsB)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->lam0_64, sizeof(double) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->lam0_32, sizeof(float) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, &c->lamh, rsz * 6 * c->lam_comp * c->nl)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, &c->spec, rsz * 2 * c->slot_elems)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, &c->ring, rsz * 2 * c->slot_elems * c->nl)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->hrhs, sizeof(double) * c->n3)) != MOT_OK) return fail(rc);
+  for (int i = 0; i < 13; ++i)
+    if ((rc = dmalloc(c, (void**)&c->kv[i], sizeof(double) * c->n3)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * RED_BLOCKS)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->scal, sizeof(double) * S_NSLOT)) != MOT_OK) return fail(rc);
+  if (hipHostMalloc((void**)&c->hscal, sizeof(double) * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
+    c->hscal = nullptr;
+    return fail(MOT_ENOMEM);
+  }
+  for (int i = 0; i < 3; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) return fail(MOT_EHIP);
+  if ((rc = mot_reset(c)) != MOT_OK) return fail(rc);
+  if ((rc = zero_bytes(c, c->wsA, wsA)) != MOT_OK) return fail(rc);
+  if ((rc = zero_bytes(c, c->wsB, wsB)) != MOT_OK) return fail(rc);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(MOT_EHIP);
+  *out = c;
+  return MOT_OK;
+}
+
+int mot_destroy(mot_ctx* c) {
+  if (!c) return MOT_OK;
+  (void)hipStreamSynchronize(c->stream);
+  void* bufs[] = {c->eps, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
+                  c->partials, c->scal};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int i = 0; i < 13; ++i)
+    if (c->kv[i]) (void)hipFree(c->kv[i]);
+  for (int t = 0; t < 2; ++t) {
+    void* tb[] = {c->twx[t], c->tw2x[t], c->twy[t], c->twz[t]};
+    for (void* b : tb)
+      if (b) (void)hipFree(b);
+  }
+  for (int i = 0; i < 3; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->prof_ev) {
+    for (int i = 0; i < 2 * c->prof_cap; ++i) (void)hipEventDestroy(c->prof_ev[i]);
+    delete[] c->prof_ev;
+    delete[] c->prof_cls;
+  }
+  delete c;
+  return MOT_OK;
+}
+
+int mot_info(const mot_ctx* c, int64_t* out, int32_t n) {
+  if (!c || !out || n < 7) return MOT_EINVAL;
+  out[0] = c->nl;
+  out[1] = c->px;
+  out[2] = c->py;
+  out[3] = c->pz;
+  out[4] = c->kxs;
+  out[5] = (int64_t)c->bytes;
+  out[6] = c->nstep;
+  return MOT_OK;
+}
+
+double mot_spectra_imag(const mot_ctx* c) { return c ? c->spectra_imag : -1.0; }
+
+int mot_set_material(mot_ctx* c, const double* eps_r) {
+  if (!c || !eps_r) return MOT_EINVAL;
+  HT(hipMemcpyAsync(c->eps, eps_r, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
+  c->have_eps = true;
+  return MOT_OK;
+}
+
+int mot_green_table(mot_ctx* c, int32_t k, double* out) {
+  if (!c || !out || k < 0) return MOT_EINVAL;
+  HT(launch_green(out, c->nx, c->ny, c->nz, k, c->alpha, c->L, c->nq, c->stream));
+  return MOT_OK;
+}
+
+int build_green_spectra(mot_ctx* c) {
+  if (!c) return MOT_EINVAL;
+  hipStream_t s = c->stream;
+  const size_t esz = (size_t)c->px * c->py * c->pz;
+  const size_t ssz = (size_t)c->pz * c->py * c->kxs;  // complex elements of one component's spectrum
+  const int nblk = compress_blocks(c->nx, c->ny, c->nz);
+  double *goct = nullptr, *E = nullptr, *imax = nullptr;
+  void *T1 = nullptr, *T2 = nullptr;
+  int rc = MOT_OK;
+  const size_t before = c->bytes;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    if (goct) (void)hipFree(goct);
+    if (E) (void)hipFree(E);
+    if (imax) (void)hipFree(imax);
+    if (T1) (void)hipFree(T1);
+    if (T2) (void)hipFree(T2);
+    c->bytes = before;
+  };
+  if ((rc = dmalloc(c, (void**)&goct, sizeof(double) * 6 * c->N)) != MOT_OK ||
+      (rc = dmalloc(c, (void**)&E, sizeof(double) * esz)) != MOT_OK ||
+      (rc = dmalloc(c, &T1, 16 * ssz)) != MOT_OK || (rc = dmalloc(c, &T2, 16 * ssz)) != MOT_OK ||
+      (rc = dmalloc(c, (void**)&imax, sizeof(double) * nblk)) != MOT_OK) {
+    cleanup();
+    return rc;
+  }
+  const double scale = 1.0 / ((double)c->px * c->py * c->pz);
+  double imag = 0.0;
+  std::vector<double> hmax(nblk);
+  for (int k = 0; k <= c->nl && rc == MOT_OK; ++k) {
+    hipError_t e = launch_green(goct, c->nx, c->ny, c->nz, k, c->alpha, c->L, c->nq, s);
+    for (int comp = 0; comp < 6 && e == hipSuccess; ++comp) {
+      if ((e = launch_embed(goct, E, comp, c->nx, c->ny, c->nz, s)) != hipSuccess) break;
+      if ((e = motfft::x_forward<double, double>(E, T1, c->nx, c->pz * c->py, c->px, c->nx, c->kxs, c->twx[1],
+                                                 c->tw2x[1], s)) != hipSuccess)
+        break;
+      if ((e = motfft::y_pass<double>(T1, T2, c->py, false, c->kx, c->kxs, c->pz, c->py, c->py, c->py, c->py,
+                                      c->twy[1], s)) != hipSuccess)
+        break;
+      if ((e = motfft::z_pass<double>(T2, T1, c->pz, motfft::Z_FWD, 1, c->kx, c->kxs, c->py, c->pz, c->pz, c->pz,
+                                      c->pz, nullptr, c->twz[1], s)) != hipSuccess)
+        break;
+      // base of lag k (component 0); k_compress adds the component offset
+      double* l64 = nullptr;
+      float* l32 = nullptr;
+      if (k == 0) {
+        l64 = c->lam0_64;
+        l32 = c->lam0_32;
+      } else if (c->ring_f64) {
+        l64 = (double*)c->lamh + (size_t)(k - 1) * 6 * c->lam_comp;
+      } else {
+        l32 = (float*)c->lamh + (size_t)(k - 1) * 6 * c->lam_comp;
+      }
+      if ((e = launch_compress(T1, l64, l32, imax, comp, c->nx, c->ny, c->nz, c->kxs, scale, s)) != hipSuccess)
+        break;
+      if ((e = hipMemcpyAsync(hmax.data(), imax, sizeof(double) * nblk, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        break;
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+      for (double v : hmax) imag = v > imag ? v : imag;
+    }
+    if (e != hipSuccess) rc = fail_hip(c, e, "spectra build", __LINE__);
+  }
+  cleanup();
+  if (rc != MOT_OK) return rc;
+  c->spectra_imag = imag;
+  c->have_spectra = true;
+  return MOT_OK;
+}
+
+int z0_matvec(mot_ctx* c, const void* J, void* y, mot_precision dtype) {
+  if (!c || !J || !y || J == y) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  switch (dtype) {
+    case MOT_F64:
+      return green_product<double, double>(c, (const double*)J, (double*)y, c->lam0_64, EP_Z0);
+    case MOT_F32:
+      return green_product<float, float>(c, (const float*)J, (float*)y, c->lam0_32, EP_Z0);
+    case MOT_F32_REFINED:
+      return green_product<float, double>(c, (const double*)J, (double*)y, c->lam0_32, EP_Z0);
+    default:
+      return MOT_EINVAL;
+  }
+}
+
+int gk_matvec(mot_ctx* c, int32_t k, const void* J, void* y, mot_precision dtype) {
+  if (!c || !J || !y || J == y || k < 0 || k > c->nl) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  if (k == 0) {
+    if (dtype == MOT_F64) return green_product<double, double>(c, (const double*)J, (double*)y, c->lam0_64, EP_G);
+    if (dtype == MOT_F32) return green_product<float, float>(c, (const float*)J, (float*)y, c->lam0_32, EP_G);
+    if (dtype == MOT_F32_REFINED)
+      return green_product<float, double>(c, (const double*)J, (double*)y, c->lam0_32, EP_G);
+    return MOT_EINVAL;
+  }
+  const size_t off = (size_t)(k - 1) * 6 * c->lam_comp;
+  if (c->ring_f64) {
+    if (dtype != MOT_F64) return MOT_EINVAL;
+    return green_product<double, double>(c, (const double*)J, (double*)y, (const double*)c->lamh + off, EP_G);
+  }
+  if (dtype == MOT_F32) return green_product<float, float>(c, (const float*)J, (float*)y, (const float*)c->lamh + off, EP_G);
+  if (dtype == MOT_F32_REFINED)
+    return green_product<float, double>(c, (const double*)J, (double*)y, (const float*)c->lamh + off, EP_G);
+  return MOT_EINVAL;
+}
+
+int history_update(mot_ctx* c, const double* J_n) {
+  if (!c || !J_n) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  return history_update_impl(c, J_n);
+}
+
+int mot_get_history_rhs(mot_ctx* c, double* out) {
+  if (!c || !out) return MOT_EINVAL;
+  HT(hipMemcpyAsync(out, c->hrhs, sizeof(double) * c->n3, hipMemcpyDeviceToDevice, c->stream));
+  return MOT_OK;
+}
+
+int mot_excitation(mot_ctx* c, const mot_pulse* p, double t, double* out) {
+  if (!c || !p || !out) return MOT_EINVAL;
+  if (!c->have_eps) return set_err(c, MOT_ESTATE, "material missing%s%d");
+  HTP(K_EINC, true, launch_einc(p, t, c->eps, out, c->nx, c->ny, c->nz, c->stream));
+  return MOT_OK;
+}
+
+int mot_profile(mot_ctx* c, int32_t enable) {
+  if (!c) return MOT_EINVAL;
+  if (enable && !c->prof_ev) {
+    const int cap = 8192;
+    c->prof_ev = new (std::nothrow) hipEvent_t[2 * cap];
+    c->prof_cls = new (std::nothrow) int[cap];
+    if (!c->prof_ev || !c->prof_cls) return MOT_ENOMEM;
+    for (int i = 0; i < 2 * cap; ++i) HT(hipEventCreate(&c->prof_ev[i]));
+    c->prof_cap = cap;
+  }
+  if (!enable) TRY(prof_flush(c));
+  c->prof_on = enable ? 1 : 0;
+  return MOT_OK;
+}
+
+int mot_profile_read(mot_ctx* c, double* ms, int64_t* counts, int32_t n) {
+  if (!c || !ms || !counts || n < MOT_PROF_NCLASS) return MOT_EINVAL;
+  TRY(prof_flush(c));
+  for (int i = 0; i < MOT_PROF_NCLASS; ++i) {
+    ms[i] = c->prof_ms[i];
+    counts[i] = c->prof_cnt[i];
+    c->prof_ms[i] = 0.0;
+    c->prof_cnt[i] = 0;
+  }
+  return MOT_OK;
+}
+
+int mot_reset(mot_ctx* c) {
+  if (!c) return MOT_EINVAL;
+  const size_t rsz = c->ring_f64 ? sizeof(double) : sizeof(float);
+  TRY(zero_bytes(c, c->ring, rsz * 2 * c->slot_elems * c->nl));
+  TRY(zero_bytes(c, c->hrhs, sizeof(double) * c->n3));
+  c->nstep = 0;
+  c->head = 0;
+  return MOT_OK;
+}
+
+int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t max_iter, mot_stats* st) {
+  if (!c || !einc || !J_n || einc == J_n || !(tol > 0.0) || max_iter < 1) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  hipStream_t s = c->stream;
+  double* b = c->kv[V_B];
+  double* x = c->kv[V_X];
+  if (st) HT(hipEventRecord(c->ev[0], s));
+  HTP(K_KRY, true, vec_add(einc, c->hrhs, b, c->n3, c->partials, s));
+  int rc = solve(c, b, x, tol, max_iter, st);
+  if (rc != MOT_OK && rc != MOT_ENOCONV && rc != MOT_EBREAKDOWN) return rc;
+  if (c->prec == MOT_F32_REFINED || rc == MOT_OK || rc == MOT_ENOCONV || rc == MOT_EBREAKDOWN)
+    HT(hipMemcpyAsync(J_n, x, sizeof(double) * c->n3, hipMemcpyDeviceToDevice, s));
+  if (st) HT(hipEventRecord(c->ev[1], s));
+  int hr = history_update_impl(c, J_n);
+  if (hr != MOT_OK) return hr;
+  if (st) {
+    HT(hipEventRecord(c->ev[2], s));
+    HT(hipEventSynchronize(c->ev[2]));
+    float a = 0.f, bms = 0.f;
+    HT(hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+    HT(hipEventElapsedTime(&bms, c->ev[1], c->ev[2]));
+    st->ms_lhs = a;
+    st->ms_rhs = bms;
+  }
+  return rc;
+}
+
+}  // extern "C"

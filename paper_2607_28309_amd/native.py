@@ -1,0 +1,225 @@
+"""ctypes binding of libmotjvie.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors to device pointers and the library's status codes to exceptions.
+Importing it loads the library and fails loudly if it is missing: there is
+no CPU fallback.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmotjvie.so")
+
+MOT_OK, MOT_EINVAL, MOT_ENOMEM, MOT_EHIP, MOT_ENOCONV, MOT_EBREAKDOWN, MOT_ENONFINITE, MOT_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MOT_F64, MOT_F32, MOT_F32_REFINED = 0, 1, 2
+PRECISIONS = {"f64": MOT_F64, "f32": MOT_F32, "f32_refined": MOT_F32_REFINED}
+
+EXPORTS = (
+    "mot_create", "mot_destroy", "mot_info", "build_green_spectra", "mot_spectra_imag",
+    "mot_set_material", "z0_matvec", "gk_matvec", "history_update", "mot_get_history_rhs",
+    "mot_excitation", "mot_step", "mot_reset", "mot_green_table", "mot_nlags", "mot_zk_nnz",
+    "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
+)
+PROF_NCLASS = 20
+PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
+              "history_mac", "z_inverse", "krylov", "excitation")
+
+
+class MotGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("alpha", ctypes.c_int32), ("cdt", ctypes.c_double), ("nlags", ctypes.c_int32),
+                ("quad", ctypes.c_int32)]
+
+
+class MotStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("matvecs", ctypes.c_int32), ("matvecs_f64", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("relres", ctypes.c_double), ("ms_lhs", ctypes.c_double),
+                ("ms_rhs", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class MotPulse(ctypes.Structure):
+    _fields_ = [("e", ctypes.c_double * 3), ("k", ctypes.c_double * 3), ("f0", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("t0", ctypes.c_double), ("amp", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2607_28309_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "mot_create": (ctypes.c_int, [ctypes.POINTER(MotGrid), ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "mot_destroy": (ctypes.c_int, [vp]),
+        "mot_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), i32]),
+        "build_green_spectra": (ctypes.c_int, [vp]),
+        "mot_spectra_imag": (dbl, [vp]),
+        "mot_set_material": (ctypes.c_int, [vp, vp]),
+        "z0_matvec": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "gk_matvec": (ctypes.c_int, [vp, i32, vp, vp, ctypes.c_int]),
+        "history_update": (ctypes.c_int, [vp, vp]),
+        "mot_get_history_rhs": (ctypes.c_int, [vp, vp]),
+        "mot_excitation": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp]),
+        "mot_step": (ctypes.c_int, [vp, vp, vp, dbl, i32, ctypes.POINTER(MotStats)]),
+        "mot_reset": (ctypes.c_int, [vp]),
+        "mot_green_table": (ctypes.c_int, [vp, i32, vp]),
+        "mot_nlags": (i32, [ctypes.POINTER(MotGrid)]),
+        "mot_zk_nnz": (i64, [ctypes.POINTER(MotGrid), i32]),
+        "mot_length_supported": (i32, [i32]),
+        "mot_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "mot_profile": (ctypes.c_int, [vp, i32]),
+        "mot_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
+        "mot_last_error": (ctypes.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+class MotError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"{LIB.mot_strerror(status).decode()} ({status}): {detail}")
+
+
+def make_grid(nx, ny, nz, alpha=0, cdt=0.0, nlags=0, quad=0):
+    return MotGrid(int(nx), int(ny), int(nz), int(alpha), float(cdt), int(nlags), int(quad))
+
+
+def nlags(nx, ny, nz, alpha=0, cdt=0.0):
+    return int(LIB.mot_nlags(ctypes.byref(make_grid(nx, ny, nz, alpha, cdt))))
+
+
+def zk_nnz(nx, ny, nz, k=0, alpha=0, cdt=0.0):
+    return int(LIB.mot_zk_nnz(ctypes.byref(make_grid(nx, ny, nz, alpha, cdt)), int(k)))
+
+
+def length_supported(n):
+    return bool(LIB.mot_length_supported(int(n)))
+
+
+def _ptr(t, dtype, numel):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"expected a contiguous {dtype} tensor of {numel} elements, got {t.dtype} "
+                         f"{tuple(t.shape)} contiguous={t.is_contiguous()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One solver context on one stream (torch's current stream by default)."""
+
+    def __init__(self, nx, ny, nz, alpha=0, cdt=0.0, precision="f64", nlags=0, quad=0, stream=None):
+        import torch
+        self.shape = (int(nx), int(ny), int(nz))
+        self.precision = precision
+        self.grid = make_grid(nx, ny, nz, alpha, cdt, nlags, quad)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = ctypes.c_void_p()
+        rc = LIB.mot_create(ctypes.byref(self.grid), PRECISIONS[precision], ctypes.c_void_p(s.cuda_stream),
+                            ctypes.byref(h))
+        if rc != MOT_OK:
+            raise MotError(rc, "mot_create")
+        self.h = h
+
+    def _check(self, rc, what, allow=()):
+        if rc != MOT_OK and rc not in allow:
+            raise MotError(rc, f"{what}: {LIB.mot_last_error(self.h).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.mot_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        out = (ctypes.c_int64 * 7)()
+        self._check(LIB.mot_info(self.h, out, 7), "mot_info")
+        keys = ("nlags", "px", "py", "pz", "kxs", "bytes", "steps")
+        return dict(zip(keys, list(out)))
+
+    def build_green_spectra(self):
+        self._check(LIB.build_green_spectra(self.h), "build_green_spectra")
+        return float(LIB.mot_spectra_imag(self.h))
+
+    def set_material(self, eps):
+        import torch
+        self._check(LIB.mot_set_material(self.h, _ptr(eps, torch.float64, self.N)), "mot_set_material")
+
+    def z0_matvec(self, J, y, dtype="f64"):
+        import torch
+        tdt = torch.float32 if dtype == "f32" else torch.float64
+        self._check(LIB.z0_matvec(self.h, _ptr(J, tdt, 3 * self.N), _ptr(y, tdt, 3 * self.N), PRECISIONS[dtype]),
+                    "z0_matvec")
+
+    def gk_matvec(self, k, J, y, dtype="f64"):
+        import torch
+        tdt = torch.float32 if dtype == "f32" else torch.float64
+        self._check(LIB.gk_matvec(self.h, int(k), _ptr(J, tdt, 3 * self.N), _ptr(y, tdt, 3 * self.N),
+                                  PRECISIONS[dtype]), "gk_matvec")
+
+    def history_update(self, J):
+        import torch
+        self._check(LIB.history_update(self.h, _ptr(J, torch.float64, 3 * self.N)), "history_update")
+
+    def history_rhs(self, out):
+        import torch
+        self._check(LIB.mot_get_history_rhs(self.h, _ptr(out, torch.float64, 3 * self.N)), "mot_get_history_rhs")
+
+    def excitation(self, pulse, t, out):
+        import torch
+        p = MotPulse((ctypes.c_double * 3)(*[float(v) for v in pulse["e"]]),
+                     (ctypes.c_double * 3)(*[float(v) for v in pulse["k"]]),
+                     float(pulse["f0"]), float(pulse["sigma"]), float(pulse["t0"]), float(pulse.get("amp", 1.0)))
+        self._check(LIB.mot_excitation(self.h, ctypes.byref(p), float(t), _ptr(out, torch.float64, 3 * self.N)),
+                    "mot_excitation")
+
+    def step(self, einc, J, tol=1e-6, max_iter=1000, stats=True, allow=()):
+        """One MOT step; returns (status, stats dict or None)."""
+        import torch
+        st = MotStats() if stats else None
+        rc = LIB.mot_step(self.h, _ptr(einc, torch.float64, 3 * self.N), _ptr(J, torch.float64, 3 * self.N),
+                          float(tol), int(max_iter), ctypes.byref(st) if st is not None else None)
+        self._check(rc, "mot_step", allow=allow)
+        return rc, (st.as_dict() if st is not None else None)
+
+    def reset(self):
+        self._check(LIB.mot_reset(self.h), "mot_reset")
+
+    def profile(self, enable=True):
+        self._check(LIB.mot_profile(self.h, 1 if enable else 0), "mot_profile")
+
+    def profile_read(self):
+        """{(kind, 'f32'|'f64'): (ms, launches)} accumulated since the last read."""
+        ms = (ctypes.c_double * PROF_NCLASS)()
+        cnt = (ctypes.c_int64 * PROF_NCLASS)()
+        self._check(LIB.mot_profile_read(self.h, ms, cnt, PROF_NCLASS), "mot_profile_read")
+        out = {}
+        for i in range(PROF_NCLASS):
+            if cnt[i]:
+                out[(PROF_KINDS[i // 2], "f64" if i % 2 else "f32")] = (float(ms[i]), int(cnt[i]))
+        return out
+
+    def green_table(self, k, out):
+        import torch
+        self._check(LIB.mot_green_table(self.h, int(k), _ptr(out, torch.float64, 6 * self.N)), "mot_green_table")

@@ -1,0 +1,328 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+Tolerances (derived in the design doc):
+  * integer work (masks, lag counts, support of G_k): bit-exact;
+  * G_k tables: |lib - oracle| <= 1e-11 max|G_k| (two independent FP64
+    quadratures of the same integrals, each accurate to ~1e-13);
+  * FP64 products: relative L2 <= 1e-10;
+  * FP32 products: relative L2 <= 1e-5 (the FP32 bar of the build);
+  * marched fields: max_n ||J_n - J_n^ref|| / max_n ||J_n^ref|| <= 1e-4.
+"""
+
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import basis, green, march, masks, operators
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [((8, 8, 8), 4), ((16, 16, 16), 1), ((24, 20, 12), 8), ((16, 6, 4), 16), ((40, 12, 6), 2)]
+
+
+@functools.lru_cache(maxsize=None)
+def og(n, k, alpha):
+    return green.green_octant(*n, k, alpha=alpha)
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def _eps(n, seed=21):
+    e = W.eps_iid(n, 1.5, 6.0, seed)
+    e.ravel()[::7] = 1.0        # some background voxels
+    return e
+
+
+def _ctx(native, n, alpha, prec="f64", eps=None, **kw):
+    c = native.Context(*n, alpha=alpha, precision=prec, **kw)
+    c.set_material(_t((_eps(n) if eps is None else eps).ravel()))
+    c.build_green_spectra()
+    return c
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+@pytest.mark.parametrize("n,alpha", GRIDS)
+def test_green_tables(gpu_lib, n, alpha):
+    import torch
+    c = _ctx(gpu_lib, n, alpha)
+    nl = c.info()["nlags"]
+    assert nl == basis.nlags(*n, alpha=alpha)
+    out = torch.empty(6 * math.prod(n), dtype=torch.float64, device="cuda")
+    for k in sorted({0, 1, 2, 3, nl // 2, nl}):
+        c.green_table(k, out)
+        lib = _np(out).reshape(6, n[2], n[1], n[0])
+        ref = og(n, k, alpha)
+        # support (causal mask and symmetry zeros) is bit-exact
+        assert np.array_equal(lib != 0.0, ref != 0.0), k
+        sc = max(np.abs(ref).max(), 1e-300)
+        assert np.abs(lib - ref).max() <= 1e-11 * sc, (k, np.abs(lib - ref).max() / sc)
+
+
+@pytest.mark.parametrize("n,alpha", GRIDS)
+def test_z0_matvec(gpu_lib, n, alpha):
+    import torch
+    eps = _eps(n)
+    c = _ctx(gpu_lib, n, alpha, "f32_refined", eps)
+    assert c.build_green_spectra() <= 1e-12
+    J = W.random_current(n, seed=5)
+    ref = operators.z0_apply(og(n, 0, alpha), eps, J)
+    y = torch.empty(J.size, dtype=torch.float64, device="cuda")
+    c.z0_matvec(_t(J.ravel()), y, "f64")
+    assert _rel(_np(y).reshape(J.shape), ref) <= 1e-10
+    c.z0_matvec(_t(J.ravel()), y, "f32_refined")
+    assert _rel(_np(y).reshape(J.shape), ref) <= 1e-5
+    y32 = torch.empty(J.size, dtype=torch.float32, device="cuda")
+    c.z0_matvec(_t(J.ravel(), torch.float32), y32, "f32")
+    assert _rel(_np(y32).reshape(J.shape), ref) <= 1e-5
+
+
+def test_z0_matvec_direct_sum_and_dense(gpu_lib):
+    # tiny grid: library vs the dense matrix and the direct Toeplitz sum
+    import torch
+    n, alpha = (8, 4, 2), 8
+    eps = _eps(n, 3)
+    c = _ctx(gpu_lib, n, alpha, "f64", eps)
+    J = W.random_current(n, seed=9)
+    Z = operators.z0_dense(og(n, 0, alpha), eps)
+    ref = (Z @ J.ravel()).reshape(J.shape)
+    y = torch.empty(J.size, dtype=torch.float64, device="cuda")
+    c.z0_matvec(_t(J.ravel()), y, "f64")
+    assert _rel(_np(y).reshape(J.shape), ref) <= 1e-10
+    assert _rel(operators.z0_apply(og(n, 0, alpha), eps, J, method="direct"), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_refined"])
+def test_history_lag_products(gpu_lib, prec):
+    import torch
+    n, alpha = (16, 6, 4), 2
+    eps = _eps(n)
+    c = _ctx(gpu_lib, n, alpha, prec, eps)
+    nl = c.info()["nlags"]
+    J = W.random_current(n, seed=2)
+    y = torch.empty(J.size, dtype=torch.float64, device="cuda")
+    tol = 1e-10 if prec == "f64" else 1e-5
+    for k in (1, 2, 3, nl // 2, nl):
+        ref = operators.gconv_fft(og(n, k, alpha), J)
+        if not np.abs(ref).max() > 0:
+            continue
+        c.gk_matvec(k, _t(J.ravel()), y, "f64" if prec == "f64" else "f32_refined")
+        assert _rel(_np(y).reshape(J.shape), ref) <= tol, k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_history_update(gpu_lib, prec):
+    # h_{n+1} = -(eps/2) J_n + (eps-1) sum_{k>=1} G_k * J_{n+1-k} after each push
+    import torch
+    n, alpha = (8, 6, 4), 2
+    eps = _eps(n, 4)
+    c = _ctx(gpu_lib, n, alpha, prec, eps)
+    nl = c.info()["nlags"]
+    Gs = [og(n, k, alpha) for k in range(nl + 1)]
+    hist = []
+    out = torch.empty(3 * math.prod(n), dtype=torch.float64, device="cuda")
+    tol = 1e-10 if prec == "f64" else 1e-5
+    for s in range(nl + 3):  # wraps the ring
+        J = W.random_current(n, seed=100 + s)
+        hist.insert(0, J)
+        c.history_update(_t(J.ravel()))
+        c.history_rhs(out)
+        acc = np.zeros_like(J)
+        for k in range(1, nl + 1):
+            if k - 1 < len(hist):
+                acc += operators.gconv_fft(Gs[k], hist[k - 1])
+        ref = -0.5 * eps[None] * J + (eps[None] - 1.0) * acc
+        assert _rel(_np(out).reshape(J.shape), ref) <= tol, s
+    assert c.info()["steps"] == nl + 3
+    c.reset()
+    c.history_rhs(out)
+    assert not _np(out).any()
+
+
+def test_excitation(gpu_lib):
+    import torch
+    n = (12, 10, 6)
+    eps = _eps(n)
+    c = _ctx(gpu_lib, n, 4, "f64", eps)
+    out = torch.empty(3 * math.prod(n), dtype=torch.float64, device="cuda")
+    for p in (W.pulse(20), W.pulse(40, k_hat=(0.6, 0.0, 0.8), e_hat=(0.0, 1.0, 0.0), amp=0.3)):
+        for t in (0.0, 100.0, 143.5, 400.0):
+            c.excitation(p, t, out)
+            ref = march.dt_einc(p, eps, t)
+            got = _np(out).reshape(ref.shape)
+            assert np.abs(got - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1e-300)
+
+
+def _march_gpu(native, n, alpha, prec, eps, p, steps, tol=1e-6):
+    import torch
+    c = _ctx(native, n, alpha, prec, eps)
+    L = basis.cdt_from_alpha(alpha)
+    N3 = 3 * math.prod(n)
+    einc = torch.empty(N3, dtype=torch.float64, device="cuda")
+    J = torch.empty(N3, dtype=torch.float64, device="cuda")
+    out, iters = [], []
+    for s in range(steps):
+        c.excitation(p, s * L, einc)
+        _, st = c.step(einc, J, tol=tol)
+        out.append(_np(J).reshape(3, n[2], n[1], n[0]))
+        iters.append(st["iters"])
+    return np.array(out), iters
+
+
+def _field_err(a, b):
+    num = max(np.linalg.norm(a[s] - b[s]) for s in range(len(b)))
+    return num / max(np.linalg.norm(b[s]) for s in range(len(b)))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_refined"])
+def test_march_cube16_alpha1(gpu_lib, prec):
+    # 16^3 homogeneous cube, eps_r = 4, dt = dt_CFL, 200 steps, h = lambda_min/20
+    w = W.CUBE16
+    eps = w.eps()
+    p = W.pulse(w.ppw)
+    L = basis.cdt_from_alpha(w.alpha)
+    Gs = [og(w.n, k, w.alpha) for k in range(basis.nlags(*w.n, alpha=w.alpha) + 1)]
+    ref, ref_it = march.run(eps, Gs, L, p, w.steps, tol=1e-6)
+    got, it = _march_gpu(gpu_lib, w.n, w.alpha, prec, eps, p, w.steps)
+    assert _field_err(got, ref) <= 1e-4
+    assert max(abs(a - b) for a, b in zip(it, ref_it)) <= 2 or prec != "f64"
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_refined"])
+def test_march_alpha8_inhomogeneous(gpu_lib, prec):
+    n, alpha = (24, 20, 12), 8
+    eps = W.eps_iid(n, 2.0, 6.0, 2)
+    p = W.pulse(20)
+    L = basis.cdt_from_alpha(alpha)
+    Gs = [og(n, k, alpha) for k in range(basis.nlags(*n, alpha=alpha) + 1)]
+    steps = 45
+    ref, _ = march.run(eps, Gs, L, p, steps, tol=1e-6)
+    got, it = _march_gpu(gpu_lib, n, alpha, prec, eps, p, steps)
+    assert _field_err(got, ref) <= 1e-4
+    assert max(it) >= 3
+
+
+def test_edge_cases(gpu_lib):
+    import torch
+    native = gpu_lib
+    n, alpha = (8, 6, 4), 4
+    N3 = 3 * math.prod(n)
+    # eps = 1 everywhere: no current, bitwise, and zero iterations
+    c = _ctx(native, n, alpha, "f64", W.eps_uniform(n, 1.0))
+    einc = torch.empty(N3, dtype=torch.float64, device="cuda")
+    J = torch.full((N3,), 7.0, dtype=torch.float64, device="cuda")
+    c.excitation(W.pulse(20), 140.0, einc)
+    _, st = c.step(einc, J)
+    assert st["iters"] == 0 and not _np(J).any()
+    # zero right-hand side at the first step
+    c2 = _ctx(native, n, alpha, "f32_refined")
+    einc.zero_()
+    _, st = c2.step(einc, J)
+    assert st["iters"] == 0 and not _np(J).any()
+    # max_iter = 1 with an unreachable tolerance: MOT_ENOCONV, history still advances
+    c.set_material(_t(_eps(n).ravel()))
+    c.excitation(W.pulse(20), 140.0, einc)
+    rc, st = c.step(einc, J, tol=1e-14, max_iter=1, allow=(native.MOT_ENOCONV,))
+    assert rc == native.MOT_ENOCONV and st["iters"] == 1
+    assert c.info()["steps"] == 2
+    # NaN in the excitation: MOT_ENONFINITE
+    einc[5] = float("nan")
+    rc, _ = c.step(einc, J, allow=(native.MOT_ENONFINITE,))
+    assert rc == native.MOT_ENONFINITE
+    # misuse is rejected before any work
+    with pytest.raises(native.MotError):
+        c.z0_matvec(J, J)
+    c3 = native.Context(*n, alpha=alpha)
+    with pytest.raises(native.MotError) as e:
+        c3.step(einc, J)
+    assert e.value.status == native.MOT_ESTATE
+
+
+def test_determinism(gpu_lib):
+    import torch
+    n, alpha = (24, 20, 12), 8
+    eps = _eps(n)
+    outs = []
+    for _ in range(2):
+        c = _ctx(gpu_lib, n, alpha, "f32_refined", eps)
+        N3 = 3 * math.prod(n)
+        einc = torch.empty(N3, dtype=torch.float64, device="cuda")
+        J = torch.empty(N3, dtype=torch.float64, device="cuda")
+        L = basis.cdt_from_alpha(alpha)
+        seq = []
+        for s in range(12, 16):
+            c.excitation(W.pulse(20), s * L, einc)
+            c.step(einc, J)
+            seq.append(_np(J))
+        y = torch.empty(N3, dtype=torch.float64, device="cuda")
+        c.z0_matvec(J, y, "f64")
+        seq.append(_np(y))
+        outs.append(seq)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_z0_matvec_pillars_full_size(gpu_lib, dtype):
+    # 8x8 pillar array, 320x320x48 voxels (14.7M unknowns), dt = 16 dt_CFL: the
+    # benchmarked size; checked on sampled voxels against the oracle's direct sum.
+    import torch
+    w = W.PILLARS
+    n, alpha = w.n, w.alpha
+    eps = w.eps()
+    c = _ctx(gpu_lib, n, alpha, "f32_refined", eps, nlags=1)
+    J = W.random_current(n, seed=44)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    y = torch.empty(J.size, dtype=tdt, device="cuda")
+    c.z0_matvec(_t(J.ravel(), tdt), y, dtype)
+    got = _np(y).reshape(J.shape)
+    Jin = J.astype(np.float32).astype(np.float64) if dtype == "f32" else J
+    g0 = og(n, 0, alpha)
+    nz, ny, nx = n[2], n[1], n[0]
+    # signed offsets d of the nonzero octant entries, with their 3x3 blocks
+    offs, blks = [], []
+    for dz, dy, dx in np.argwhere(np.abs(g0).sum(axis=0) > 0):
+        v = g0[:, dz, dy, dx]
+        for sz in ((1, -1) if dz else (1,)):
+            for sy in ((1, -1) if dy else (1,)):
+                for sx in ((1, -1) if dx else (1,)):
+                    sg = (sx, sy, sz)
+                    B = np.zeros((3, 3))
+                    for cc, (pp, qq) in enumerate(green.PAIR):
+                        B[pp, qq] = B[qq, pp] = v[cc] * (sg[pp] * sg[qq] if pp != qq else 1.0)
+                    offs.append((sz * dz, sy * dy, sx * dx))
+                    blks.append(B)
+    offs = np.array(offs)
+    blks = np.array(blks)           # (m, 3, 3)
+    rng = np.random.default_rng(7)
+    samples = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (24, 20, 20), (24, 160, 161)]
+    samples += [tuple(rng.integers(0, s) for s in (nz, ny, nx)) for _ in range(60)]
+    err, scale = 0.0, 0.0
+    for (z, yy, x) in samples:
+        src = np.array([z, yy, x]) - offs
+        ok = np.all((src >= 0) & (src < np.array([nz, ny, nx])), axis=1)
+        s_ = src[ok]
+        js = Jin[:, s_[:, 0], s_[:, 1], s_[:, 2]]                               # (3,m)
+        gj = np.einsum("mpq,qm->p", blks[ok], js)
+        e = eps[z, yy, x]
+        ref = 0.5 * e * Jin[:, z, yy, x] - (e - 1.0) * gj
+        err = max(err, np.abs(got[:, z, yy, x] - ref).max())
+        scale = max(scale, np.abs(ref).max())
+    assert err <= (1e-10 if dtype == "f64" else 1e-5) * scale
