@@ -27,26 +27,35 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int LDS_BUDGET = 81920;
 
+// LDS rows are padded to NPS = NP + 1 entries so that lanes walking along a
+// pencil (stride NPS) and the row stride of the Stockham writes spread over
+// the LDS banks instead of hitting the same ones.
 template <typename T, int M> struct XCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
   static constexpr int NP =
-      cmax(1, floor_pow2(cmin(256 / TJ, (LDS_BUDGET - (2 * M + 1) * SZ) / ((M + 1) * SZ))));
+      cmax(1, floor_pow2(cmin(256 / TJ, (LDS_BUDGET - (2 * M + 1) * SZ) / ((M + 1) * SZ) - 1)));
+  static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)((M + 1) * NPS + 2 * M + 1) * SZ;
 };
 template <typename T, int M> struct YCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
-  static constexpr int NP = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ))));
+  static constexpr int NP = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ) - 1)));
+  static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
 };
 template <typename T, int M, int NC> struct ZCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
   static constexpr int W =
-      cmax(1, floor_pow2(cmin(cmin(16, 1024 / (NC * TJ)), (LDS_BUDGET - M * SZ) / (NC * M * SZ))));
+      cmax(1, floor_pow2(cmin(cmin(16, 1024 / (NC * TJ)), (LDS_BUDGET - 2 * M * SZ) / (NC * M * SZ))));
   static constexpr int NP = NC * W;
+  static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
 };
 
 template <typename T, int M>
@@ -66,10 +75,10 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __r
                                                                   const cpx<T>* __restrict__ tw_g,
                                                                   const cpx<T>* __restrict__ tw2_g) {
   using C = XCfg<T, M>;
-  constexpr int NP = C::NP;
+  constexpr int NP = C::NP, NPS = C::NPS;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + (M + 1) * NP;
+  cpx<T>* tw = lds + (M + 1) * NPS;
   cpx<T>* tw2 = tw + M;
   load_table<T, M>(tw, tw_g, M);
   load_table<T, M>(tw2, tw2_g, M + 1);
@@ -83,21 +92,21 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __r
       V2 pr = *reinterpret_cast<const V2*>(in + (size_t)grow * row_len + 2 * n);
       val = cpx<T>{(T)pr.x, (T)pr.y};
     }
-    lds[n * NP + row] = val;
+    lds[n * NPS + row] = val;
   }
   __syncthreads();
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NP + pp]; });
+  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NPS + pp]; });
   __syncthreads();
-  run_fft<T, M, false>(v, lds, tw, p, jt, NP, [&](int pp, int e, cpx<T> val) { lds[e * NP + pp] = val; });
+  run_fft<T, M, false>(v, lds, tw, p, jt, NPS, [&](int pp, int e, cpx<T> val) { lds[e * NPS + pp] = val; });
   __syncthreads();
   for (int idx = threadIdx.x; idx < NP * (M + 1); idx += blockDim.x) {
     const int row = idx / (M + 1), k = idx - row * (M + 1);
     const int grow = row0 + row;
     if (grow >= nrows) continue;
-    const cpx<T> zk = lds[(k == M ? 0 : k) * NP + row];
-    const cpx<T> zm = lds[(k == 0 ? 0 : M - k) * NP + row];
+    const cpx<T> zk = lds[(k == M ? 0 : k) * NPS + row];
+    const cpx<T> zm = lds[(k == 0 ? 0 : M - k) * NPS + row];
     // E = (zk + conj zm)/2, O = -i/2 (zk - conj zm)
     const cpx<T> e{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
     const cpx<T> o{(T)0.5 * (zk.y + zm.y), (T)-0.5 * (zk.x - zm.x)};
@@ -111,10 +120,10 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
     const double* __restrict__ eps, Epilogue ep, int nrows, int rows_per_comp, int row_len, int n_out,
     int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g) {
   using C = XCfg<T, M>;
-  constexpr int NP = C::NP;
+  constexpr int NP = C::NP, NPS = C::NPS;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + (M + 1) * NP;
+  cpx<T>* tw = lds + (M + 1) * NPS;
   cpx<T>* tw2 = tw + M;
   load_table<T, M>(tw, tw_g, M);
   load_table<T, M>(tw2, tw2_g, M + 1);
@@ -122,15 +131,15 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
   for (int idx = threadIdx.x; idx < NP * (M + 1); idx += blockDim.x) {
     const int row = idx / (M + 1), k = idx - row * (M + 1);
     const int grow = row0 + row;
-    lds[k * NP + row] = grow < nrows ? in[(size_t)grow * kxs + k] : cpx<T>{(T)0, (T)0};
+    lds[k * NPS + row] = grow < nrows ? in[(size_t)grow * kxs + k] : cpx<T>{(T)0, (T)0};
   }
   __syncthreads();
   constexpr int H = M / 2 + 1;
   for (int idx = threadIdx.x; idx < NP * H; idx += blockDim.x) {
     const int row = idx / H, k = idx - row * H;
     const int m = M - k;
-    const cpx<T> xk = lds[k * NP + row];
-    const cpx<T> xm = lds[m * NP + row];
+    const cpx<T> xk = lds[k * NPS + row];
+    const cpx<T> xm = lds[m * NPS + row];
     // Z[k] = (Xk + conj Xm) + i W^{-k} (Xk - conj Xm)
     const cpx<T> dk{xk.x - xm.x, xk.y + xm.y};
     const cpx<T> rk = cmulc(dk, tw2[k]);
@@ -138,15 +147,15 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
     const cpx<T> dm{xm.x - xk.x, xm.y + xk.y};
     const cpx<T> rm = cmulc(dm, tw2[m]);
     const cpx<T> zm{xm.x + xk.x - rm.y, xm.y - xk.y + rm.x};
-    lds[k * NP + row] = zk;
-    if (m < M && m != k) lds[m * NP + row] = zm;
+    lds[k * NPS + row] = zk;
+    if (m < M && m != k) lds[m * NPS + row] = zm;
   }
   __syncthreads();
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NP + pp]; });
+  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NPS + pp]; });
   __syncthreads();
-  run_fft<T, M, true>(v, lds, tw, p, jt, NP, [&](int pp, int e, cpx<T> val) { lds[e * NP + pp] = val; });
+  run_fft<T, M, true>(v, lds, tw, p, jt, NPS, [&](int pp, int e, cpx<T> val) { lds[e * NPS + pp] = val; });
   __syncthreads();
   using V2 = typename io2<IO>::t;
   const int half = n_out / 2;
@@ -154,7 +163,7 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
     const int row = idx / half, n = idx - row * half;
     const int grow = row0 + row;
     if (grow >= nrows) continue;
-    const cpx<T> z = lds[n * NP + row];
+    const cpx<T> z = lds[n * NPS + row];
     const size_t off = (size_t)grow * row_len + 2 * n;
     const size_t eoff = (size_t)(grow % rows_per_comp) * row_len + 2 * n;
     const double2 e2 = *reinterpret_cast<const double2*>(eps + eoff);
@@ -173,10 +182,10 @@ __global__ __launch_bounds__((YCfg<T, M>::BLOCK)) void k_y_pass(const cpx<T>* __
                                                                int rows_in, int n_in, int rows_out,
                                                                int n_out, const cpx<T>* __restrict__ tw_g) {
   using C = YCfg<T, M>;
-  constexpr int NP = C::NP;
+  constexpr int NP = C::NP, NPS = C::NPS;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + M * NP;
+  cpx<T>* tw = lds + M * NPS;
   load_table<T, M>(tw, tw_g, M);
   __syncthreads();
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
@@ -188,7 +197,7 @@ __global__ __launch_bounds__((YCfg<T, M>::BLOCK)) void k_y_pass(const cpx<T>* __
   load_first<T, M>(v, p, jt, [&](int, int e) {
     return (ok && e < n_in) ? src[(size_t)e * kxs] : cpx<T>{(T)0, (T)0};
   });
-  run_fft<T, M, INV>(v, lds, tw, p, jt, NP, [&](int, int e, cpx<T> val) {
+  run_fft<T, M, INV>(v, lds, tw, p, jt, NPS, [&](int, int e, cpx<T> val) {
     if (ok && e < n_out) dst[(size_t)e * kxs] = val;
   });
 }
@@ -199,10 +208,10 @@ __global__ __launch_bounds__((ZCfg<T, M, NC>::BLOCK)) void k_z_pass(
     const cpx<T>* in, cpx<T>* out, int kxn, int kxs, int ny, int rows_in,
     int n_in, int rows_out, int n_out, const T* __restrict__ lam, const cpx<T>* __restrict__ tw_g) {
   using C = ZCfg<T, M, NC>;
-  constexpr int W = C::W, NP = C::NP;
+  constexpr int W = C::W, NP = C::NP, NPS = C::NPS;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + M * NP;
+  cpx<T>* tw = lds + M * NPS;
   load_table<T, M>(tw, tw_g, M);
   __syncthreads();
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
@@ -219,11 +228,11 @@ __global__ __launch_bounds__((ZCfg<T, M, NC>::BLOCK)) void k_z_pass(
     return (ok && e < n_in) ? src[(size_t)e * plane] : cpx<T>{(T)0, (T)0};
   });
   if constexpr (MODE == Z_FWD || MODE == Z_INV) {
-    run_fft<T, M, MODE == Z_INV>(v, lds, tw, p, jt, NP, [&](int, int e, cpx<T> val) {
+    run_fft<T, M, MODE == Z_INV>(v, lds, tw, p, jt, NPS, [&](int, int e, cpx<T> val) {
       if (ok && e < n_out) dst[(size_t)e * plane] = val;
     });
   } else {
-    run_fft<T, M, false>(v, lds, tw, p, jt, NP, [&](int pp, int e, cpx<T> val) { lds[e * NP + pp] = val; });
+    run_fft<T, M, false>(v, lds, tw, p, jt, NPS, [&](int pp, int e, cpx<T> val) { lds[e * NPS + pp] = val; });
     __syncthreads();
     // spectral 3x3 multiply, Lambda octant-compressed with reflection signs
     const int kyc = ky <= ny / 2 ? ky : ny - ky;
@@ -239,16 +248,16 @@ __global__ __launch_bounds__((ZCfg<T, M, NC>::BLOCK)) void k_z_pass(
       const T* L = lam + (size_t)kzc * lky + (size_t)kyc * kxs + kxx;
       const T lxx = L[0], lyy = L[lcomp], lzz = L[2 * lcomp];
       const T lxy = sy * L[3 * lcomp], lxz = sz * L[4 * lcomp], lyz = sy * sz * L[5 * lcomp];
-      cpx<T>* q = lds + kz * NP + cc;
+      cpx<T>* q = lds + kz * NPS + cc;
       const cpx<T> jx = q[0], jy = q[W], jz = q[2 * W];
       q[0] = cpx<T>{lxx * jx.x + lxy * jy.x + lxz * jz.x, lxx * jx.y + lxy * jy.y + lxz * jz.y};
       q[W] = cpx<T>{lxy * jx.x + lyy * jy.x + lyz * jz.x, lxy * jx.y + lyy * jy.y + lyz * jz.y};
       q[2 * W] = cpx<T>{lxz * jx.x + lyz * jy.x + lzz * jz.x, lxz * jx.y + lyz * jy.y + lzz * jz.y};
     }
     __syncthreads();
-    load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NP + pp]; });
+    load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NPS + pp]; });
     __syncthreads();
-    run_fft<T, M, true>(v, lds, tw, p, jt, NP, [&](int, int e, cpx<T> val) {
+    run_fft<T, M, true>(v, lds, tw, p, jt, NPS, [&](int, int e, cpx<T> val) {
       if (ok && e < n_out) dst[(size_t)e * plane] = val;
     });
   }
@@ -273,7 +282,7 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int row_len, int
 #define X(m)                                                                                          \
   case m: {                                                                                           \
     using C = XCfg<T, m>;                                                                             \
-    const size_t sh = (size_t)((m + 1) * C::NP + 2 * m + 1) * sizeof(cpx<T>);                         \
+    const size_t sh = C::LDS;                                                                         \
     hipLaunchKernelGGL((k_x_forward<T, IO, m>), dim3((nrows + C::NP - 1) / C::NP), dim3(C::BLOCK), sh, \
                        s, in, (cpx<T>*)out, nrows, row_len, n_in, kxs, (const cpx<T>*)tw,              \
                        (const cpx<T>*)tw2);                                                           \
@@ -294,7 +303,7 @@ hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epil
 #define X(m)                                                                                          \
   case m: {                                                                                           \
     using C = XCfg<T, m>;                                                                             \
-    const size_t sh = (size_t)((m + 1) * C::NP + 2 * m + 1) * sizeof(cpx<T>);                         \
+    const size_t sh = C::LDS;                                                                         \
     hipLaunchKernelGGL((k_x_inverse<T, IO, m>), dim3((nrows + C::NP - 1) / C::NP), dim3(C::BLOCK), sh, \
                        s, (const cpx<T>*)in, y, J, eps, ep, nrows, rows_per_comp, row_len, n_out, kxs, \
                        (const cpx<T>*)tw, (const cpx<T>*)tw2);                                        \
@@ -314,7 +323,7 @@ hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kx
 #define X(m)                                                                                       \
   case m: {                                                                                        \
     using C = YCfg<T, m>;                                                                          \
-    const size_t sh = (size_t)(m * C::NP + m) * sizeof(cpx<T>);                                    \
+    const size_t sh = C::LDS;                                                                      \
     dim3 g((kx + C::NP - 1) / C::NP, planes);                                                      \
     if (inverse)                                                                                   \
       hipLaunchKernelGGL((k_y_pass<T, m, true>), g, dim3(C::BLOCK), sh, s, (const cpx<T>*)in,      \
@@ -335,7 +344,7 @@ template <typename T, int M, int NC>
 static hipError_t z_launch(const void* in, void* out, int mode, int kx, int kxs, int ny, int rows_in,
                            int n_in, int rows_out, int n_out, const T* lam, const void* tw, hipStream_t s) {
   using C = ZCfg<T, M, NC>;
-  const size_t sh = (size_t)(M * C::NP + M) * sizeof(cpx<T>);
+  const size_t sh = C::LDS;
   dim3 g((kx + C::W - 1) / C::W, ny);
   const cpx<T>* i_ = (const cpx<T>*)in;
   cpx<T>* o_ = (cpx<T>*)out;

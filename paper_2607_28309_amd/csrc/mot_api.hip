@@ -43,7 +43,8 @@ struct mot_ctx {
   long long nstep;
   int head;
   double* hrhs;
-  double* kv[13];
+  double* kv[13];      // FP64 Krylov vectors
+  float* kf[11];       // FP32 Krylov vectors (FP32 and refined modes)
   double* partials;
   double* scal;
   double* hscal;       // pinned host mirror
@@ -320,12 +321,6 @@ const motfft::Epilogue EP_Z0{0.5, 0.0, -1.0, 1.0};      // D J - X (G J)
 const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};        // G J
 const motfft::Epilogue EP_HIST{-0.5, 0.0, 1.0, -1.0};   // -(eps/2) J + X (G J)
 
-// Z0 product on FP64 vectors in the requested compute precision.
-int apply_z0(mot_ctx* c, const double* in, double* out, bool f64) {
-  if (f64) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0);
-  return green_product<float, double>(c, in, out, c->lam0_32, EP_Z0);
-}
-
 int reduce_sync(mot_ctx* c) {
   HT(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->stream));
   HT(hipStreamSynchronize(c->stream));
@@ -337,46 +332,61 @@ struct SolveOut {
   double relres = 0.0;
 };
 
-// TFQMR for Z0 x = b from x = 0 (b, x: FP64 device vectors; x may not alias b).
-int tfqmr(mot_ctx* c, bool f64, const double* b, double* x, double tol, int max_iter, SolveOut* so) {
+// Z0 product in the precision of the vectors: FP64 vectors -> FP64 FFTs,
+// FP32 vectors -> FP32 FFTs.
+int apply_z0(mot_ctx* c, const double* in, double* out) {
+  return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0);
+}
+int apply_z0(mot_ctx* c, const float* in, float* out) {
+  return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0);
+}
+
+template <typename V> struct KV;
+template <> struct KV<double> {
+  static double** get(mot_ctx* c) { return c->kv; }
+};
+template <> struct KV<float> {
+  static float** get(mot_ctx* c) { return c->kf; }
+};
+
+// TFQMR for Z0 x = b from x = 0 (b, x: device vectors of type V, distinct from
+// the work vectors).  One host synchronization per iteration (convergence test).
+template <typename V>
+int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) {
   hipStream_t s = c->stream;
   const long long n = c->n3;
-  double** v = c->kv;
+  V** v = KV<V>::get(c);
   double* P = c->partials;
-  HTP(K_KRY, true, dot_partial(b, b, n, P, s));
-  HTP(K_KRY, true, reduce_to(P, c->scal, S_B2, 0, s));
+  const bool f64 = sizeof(V) == 8;
+  HTP(K_KRY, f64, dot_partial<V>(b, b, n, P, s));
+  HTP(K_KRY, f64, reduce_post(P, c->scal, S_B2, POST_INIT, s));
   TRY(reduce_sync(c));
   const double b2 = c->hscal[S_B2];
   if (!std::isfinite(b2)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
   if (b2 == 0.0) {
-    HTP(K_KRY, true, vec_zero(x, n, s));
+    HTP(K_KRY, f64, vec_zero<V>(x, n, s));
     so->relres = 0.0;
     return MOT_OK;
   }
   const double bnorm = sqrt(b2);
-  auto mv = [&](const double* in, double* out) {
+  auto mv = [&](const V* in, V* out) {
     so->matvecs++;
     if (f64) so->matvecs64++;
-    return apply_z0(c, in, out, f64);
+    return apply_z0(c, in, out);
   };
-  HTP(K_KRY, true, tfqmr_init(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));
+  HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));
   TRY(mv(v[V_U], v[V_AU]));
-  HTP(K_KRY, true, tfqmr_v0(v[V_V], v[V_AU], v[V_RT], n, P, s));
-  HTP(K_KRY, true, reduce_to(P, c->scal, S_SIGMA, 0, s));
-  HTP(K_KRY, true, sc_init(c->scal, s));
+  HTP(K_KRY, f64, tfqmr_v0<V>(v[V_V], v[V_AU], v[V_RT], n, P, s));
+  HTP(K_KRY, f64, reduce_post(P, c->scal, S_SIGMA, POST_ALPHA, s));
   for (int it = 1; it <= max_iter; ++it) {
     so->iters = it;
-    HTP(K_KRY, true, sc_alpha(c->scal, s));
-    HTP(K_KRY, true, tfqmr_half0(x, v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], c->scal, false, n, P, s));
-    HTP(K_KRY, true, reduce_to(P, c->scal, S_W2, 0, s));
-    HTP(K_KRY, true, sc_half(c->scal, true, s));
+    HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], c->scal, n, P, s));
+    HTP(K_KRY, f64, reduce_post(P, c->scal, S_W2, POST_HALF0, s));
     TRY(mv(v[V_U2], v[V_AU2]));
-    HTP(K_KRY, true, tfqmr_half1(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], c->scal, n, P, s));
-    HTP(K_KRY, true, reduce_to(P, c->scal, S_W2, 0, s));
-    HTP(K_KRY, true, sc_half(c->scal, false, s));
-    HTP(K_KRY, true, tfqmr_rho(x, v[V_D], v[V_W], v[V_RT], c->scal, n, P, s));
-    HTP(K_KRY, true, reduce_to(P, c->scal, S_RHONEW, 0, s));
-    HTP(K_KRY, true, sc_beta(c->scal, s));
+    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], c->scal, n, P, s));
+    HTP(K_KRY, f64, reduce_post(P, c->scal, S_W2, POST_HALF1, s));
+    HTP(K_KRY, f64, tfqmr_rho<V>(x, v[V_D], v[V_W], v[V_RT], c->scal, n, P, s));
+    HTP(K_KRY, f64, reduce_post(P, c->scal, S_RHONEW, POST_BETA, s));
     TRY(reduce_sync(c));
     const double* h = c->hscal;
     const bool breakdown = h[S_FLAG] != 0.0;
@@ -385,8 +395,8 @@ int tfqmr(mot_ctx* c, bool f64, const double* b, double* x, double tol, int max_
     if (bound <= tol * bnorm || breakdown || it == max_iter) {
       // true residual with the solver's own operator
       TRY(mv(x, v[V_TMP]));
-      HTP(K_KRY, true, vec_sub(b, v[V_TMP], v[V_TMP], n, P, s));
-      HTP(K_KRY, true, reduce_to(P, c->scal, S_R2, 0, s));
+      HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s));
+      HTP(K_KRY, f64, reduce_post(P, c->scal, S_R2, POST_NONE, s));
       TRY(reduce_sync(c));
       so->relres = sqrt(c->hscal[S_R2]) / bnorm;
       if (!std::isfinite(so->relres)) return set_err(c, MOT_ENONFINITE, "TFQMR residual is not finite%s%d");
@@ -394,37 +404,44 @@ int tfqmr(mot_ctx* c, bool f64, const double* b, double* x, double tol, int max_
       if (breakdown) return set_err(c, MOT_EBREAKDOWN, "TFQMR breakdown (rho or sigma = 0)%s%d");
       if (it == max_iter) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
     }
-    HTP(K_KRY, true, tfqmr_u(v[V_U], v[V_W], v[V_U2], c->scal, n, s));
+    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], c->scal, n, s));
     TRY(mv(v[V_U], v[V_AU]));
-    HTP(K_KRY, true, tfqmr_v(v[V_V], v[V_AU], v[V_AU2], v[V_RT], c->scal, n, P, s));
-    HTP(K_KRY, true, reduce_to(P, c->scal, S_SIGMA, 0, s));
+    HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], c->scal, n, P, s));
+    HTP(K_KRY, f64, reduce_post(P, c->scal, S_SIGMA, POST_ALPHA, s));
   }
   return set_err(c, MOT_ENOCONV, "TFQMR did not converge (max_iter < 1)%s%d");
 }
 
-// Solve Z0 x = b in the context precision; result in x.
+// Solve Z0 x = b (FP64 b, x) in the context precision.
+//   MOT_F64:         FP64 TFQMR, FP64 FFTs.
+//   MOT_F32:         FP32 TFQMR (FP64 inner products), FP32 FFTs.
+//   MOT_F32_REFINED: repeated FP32 inner solves of Z0 e = r on the FP64
+//                    residual r = b - Z0 x (FP64 FFT product), x += e.
 int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_stats* st) {
   SolveOut so;
   int rc = MOT_OK;
   int refinements = 0;
-  if (c->prec == MOT_F64 || c->prec == MOT_F32) {
-    rc = tfqmr(c, c->prec == MOT_F64, b, x, tol, max_iter, &so);
+  hipStream_t s = c->stream;
+  const long long n = c->n3;
+  double* P = c->partials;
+  if (c->prec == MOT_F64) {
+    rc = tfqmr<double>(c, b, x, tol, max_iter, &so);
+  } else if (c->prec == MOT_F32) {
+    HTP(K_KRY, false, vec_d2f(b, c->kf[V_B], n, P, s));
+    rc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tol, max_iter, &so);
+    HTP(K_KRY, false, vec_f2d(c->kf[V_X], x, n, s));
   } else {
-    // FP32 inner TFQMR inside an FP64 residual-correction loop
-    hipStream_t s = c->stream;
-    const long long n = c->n3;
     double** v = c->kv;
-    double* P = c->partials;
-    HTP(K_KRY, true, dot_partial(b, b, n, P, s));
-    HTP(K_KRY, true, reduce_to(P, c->scal, S_B2, 0, s));
+    HTP(K_KRY, true, dot_partial<double>(b, b, n, P, s));
+    HTP(K_KRY, true, reduce_post(P, c->scal, S_B2, POST_NONE, s));
     TRY(reduce_sync(c));
     const double bnorm = sqrt(c->hscal[S_B2]);
     if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
-    HTP(K_KRY, true, vec_zero(x, n, s));
+    HTP(K_KRY, true, vec_zero<double>(x, n, s));
     if (bnorm == 0.0) {
       so.relres = 0.0;
     } else {
-      HTP(K_KRY, true, vec_copy_scale(b, 1.0, v[V_RO], n, s));
+      const double* r = b;  // residual of x = 0
       double rnorm = bnorm;
       const int max_ref = 12;
       while (true) {
@@ -432,18 +449,20 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
         double tin = 0.5 * tol * bnorm / rnorm;
         if (tin < 2e-6) tin = 2e-6;
         SolveOut inner;
-        int irc = tfqmr(c, false, v[V_RO], v[V_XO], tin, max_iter, &inner);
+        HTP(K_KRY, false, vec_d2f(r, c->kf[V_B], n, P, s));
+        int irc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tin, max_iter, &inner);
         so.iters += inner.iters;
         so.matvecs += inner.matvecs;
         if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
-        HTP(K_KRY, true, vec_add(x, v[V_XO], x, n, P, s));  // x += correction
-        TRY(apply_z0(c, x, v[V_TMP], true));
+        HTP(K_KRY, true, vec_acc_f2d(x, c->kf[V_X], n, s));
+        TRY(apply_z0(c, x, v[V_TMP]));
         so.matvecs++;
         so.matvecs64++;
-        HTP(K_KRY, true, vec_sub(b, v[V_TMP], v[V_RO], n, P, s));
-        HTP(K_KRY, true, reduce_to(P, c->scal, S_R2, 0, s));
+        HTP(K_KRY, true, vec_sub<double>(b, v[V_TMP], v[V_RO], n, P, s));
+        HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s));
         TRY(reduce_sync(c));
         rnorm = sqrt(c->hscal[S_R2]);
+        r = v[V_RO];
         so.relres = rnorm / bnorm;
         if (!std::isfinite(rnorm)) return set_err(c, MOT_ENONFINITE, "refined residual is not finite%s%d");
         if (so.relres <= tol) break;
@@ -610,6 +629,9 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if ((rc = dmalloc(c, (void**)&c->hrhs, sizeof(double) * c->n3)) != MOT_OK) return fail(rc);
   for (int i = 0; i < 13; ++i)
     if ((rc = dmalloc(c, (void**)&c->kv[i], sizeof(double) * c->n3)) != MOT_OK) return fail(rc);
+  if (prec != MOT_F64)
+    for (int i = 0; i < 11; ++i)
+      if ((rc = dmalloc(c, (void**)&c->kf[i], sizeof(float) * c->n3)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * RED_BLOCKS)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->scal, sizeof(double) * S_NSLOT)) != MOT_OK) return fail(rc);
   if (hipHostMalloc((void**)&c->hscal, sizeof(double) * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
@@ -635,6 +657,8 @@ int mot_destroy(mot_ctx* c) {
     if (b) (void)hipFree(b);
   for (int i = 0; i < 13; ++i)
     if (c->kv[i]) (void)hipFree(c->kv[i]);
+  for (int i = 0; i < 11; ++i)
+    if (c->kf[i]) (void)hipFree(c->kf[i]);
   for (int t = 0; t < 2; ++t) {
     void* tb[] = {c->twx[t], c->tw2x[t], c->twy[t], c->twz[t]};
     for (void* b : tb)
@@ -847,7 +871,7 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
   double* b = c->kv[V_B];
   double* x = c->kv[V_X];
   if (st) HT(hipEventRecord(c->ev[0], s));
-  HTP(K_KRY, true, vec_add(einc, c->hrhs, b, c->n3, c->partials, s));
+  HTP(K_KRY, true, vec_add64(einc, c->hrhs, b, c->n3, c->partials, s));
   int rc = solve(c, b, x, tol, max_iter, st);
   if (rc != MOT_OK && rc != MOT_ENOCONV && rc != MOT_EBREAKDOWN) return rc;
   if (c->prec == MOT_F32_REFINED || rc == MOT_OK || rc == MOT_ENOCONV || rc == MOT_EBREAKDOWN)

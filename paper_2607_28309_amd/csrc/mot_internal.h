@@ -41,37 +41,33 @@ int compress_blocks(int nx, int ny, int nz);
 hipError_t launch_compress(const void* spec, double* lam64, float* lam32, double* imax, int comp, int nx,
                            int ny, int nz, int kxs, double scale, hipStream_t s);
 
-// ---- krylov.hip (all vectors FP64, length n)
-hipError_t dot_partial(const double* a, const double* b, long long n, double* partials, hipStream_t s);
-hipError_t reduce_to(const double* partials, double* scal, int slot, int mode, hipStream_t s);  // mode 0 sum, 1 max
-hipError_t vec_add(const double* a, const double* b, double* out, long long n, double* partials,
-                   hipStream_t s);  // out = a + b, partials of |out|^2
-hipError_t vec_copy_scale(const double* a, double alpha, double* out, long long n, hipStream_t s);
-hipError_t vec_sub(const double* a, const double* b, double* out, long long n, double* partials,
-                   hipStream_t s);  // out = a - b, partials of |out|^2
-hipError_t vec_axpy_inplace(double* x, const double* d, const double* scal, int slot, long long n,
-                            hipStream_t s);  // x += scal[slot] d
-hipError_t vec_zero(double* a, long long n, hipStream_t s);
-hipError_t tfqmr_init(const double* r0, double* w, double* u, double* rt, double* d, double* x, long long n,
-                      hipStream_t s);
-hipError_t tfqmr_half0(double* x, double* u2, const double* u, const double* v, double* w, const double* au,
-                       double* d, const double* scal, bool apply_x, long long n, double* partials,
-                       hipStream_t s);
-hipError_t tfqmr_half1(double* x, double* w, const double* au2, double* d, const double* u2,
-                       const double* scal, long long n, double* partials, hipStream_t s);
-hipError_t tfqmr_rho(double* x, const double* d, const double* w, const double* rt, const double* scal,
-                     long long n, double* partials, hipStream_t s);
-hipError_t tfqmr_u(double* u, const double* w, const double* u2, const double* scal, long long n,
-                   hipStream_t s);
-hipError_t tfqmr_v(double* v, const double* au, const double* au2, const double* rt, const double* scal,
-                   long long n, double* partials, hipStream_t s);
-hipError_t tfqmr_v0(double* v, const double* au, const double* rt, long long n, double* partials,
-                    hipStream_t s);
-hipError_t sc_init(double* scal, hipStream_t s);     // rho = sigma... set from S_B2 etc.
-hipError_t sc_alpha(double* scal, hipStream_t s);
-hipError_t sc_half(double* scal, bool record_tau0, hipStream_t s);
-hipError_t sc_beta(double* scal, hipStream_t s);
-hipError_t vec_finite_check(const double* a, long long n, double* partials, hipStream_t s);
+// ---- krylov.hip (vectors of length n, element type V = float or double)
+// Scalar recurrence applied by the reduction that produced scal[slot].
+enum Post { POST_NONE = 0, POST_INIT, POST_ALPHA, POST_HALF0, POST_HALF1, POST_BETA };
+hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s);
+template <typename V> hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s);
+template <typename V> hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials,
+                                         hipStream_t s);  // out = a - b, partials of |out|^2
+template <typename V> hipError_t vec_zero(V* a, long long n, hipStream_t s);
+hipError_t vec_add64(const double* a, const double* b, double* out, long long n, double* partials,
+                     hipStream_t s);  // out = a + b, partials of |out|^2
+hipError_t vec_acc_f2d(double* x, const float* d, long long n, hipStream_t s);  // x += d
+hipError_t vec_d2f(const double* in, float* out, long long n, double* partials, hipStream_t s);
+hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s);
+hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s);
+template <typename V> hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, hipStream_t s);
+template <typename V> hipError_t tfqmr_half0(V* u2, const V* u, const V* v, V* w, const V* au, V* d,
+                                             const double* scal, long long n, double* partials, hipStream_t s);
+template <typename V> hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const double* scal,
+                                             long long n, double* partials, hipStream_t s);
+template <typename V> hipError_t tfqmr_rho(V* x, const V* d, const V* w, const V* rt, const double* scal,
+                                           long long n, double* partials, hipStream_t s);
+template <typename V> hipError_t tfqmr_u(V* u, const V* w, const V* u2, const double* scal, long long n,
+                                         hipStream_t s);
+template <typename V> hipError_t tfqmr_v(V* v, const V* au, const V* au2, const V* rt, const double* scal,
+                                         long long n, double* partials, hipStream_t s);
+template <typename V> hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials,
+                                          hipStream_t s);
 
 // ---- mot_api.hip: history MAC and excitation
 hipError_t launch_mac(const void* ring, const void* lamh, void* out, int f64, int nl, int nvalid, int head,

@@ -97,7 +97,7 @@ def test_z0_matvec(gpu_lib, n, alpha):
 def test_z0_matvec_direct_sum_and_dense(gpu_lib):
     # tiny grid: library vs the dense matrix and the direct Toeplitz sum
     import torch
-    n, alpha = (8, 4, 2), 8
+    n, alpha = (8, 4, 4), 8
     eps = _eps(n, 3)
     c = _ctx(gpu_lib, n, alpha, "f64", eps)
     J = W.random_current(n, seed=9)
