@@ -164,6 +164,12 @@ int mot_step(mot_ctx* ctx, const double* einc, double* J_n, double tol, int32_t 
 /* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
 int mot_reset(mot_ctx* ctx);
 
+/* Set the step counter to n >= 0 without touching the history ring or the
+ * history right-hand side.  After mot_reset this starts the march at step n
+ * with J_m = 0 for every m < n (all ell ring slots count as filled), which
+ * is the steady-state cost of every later step. */
+int mot_set_step(mot_ctx* ctx, int64_t n);
+
 /* Evaluate G_k on the octant of offsets into `out` ([6][nz][ny][nx] FP64,
  * device), exactly as build_green_spectra does.  Entries outside the causal
  * region of lag k are exact zeros. */

@@ -84,21 +84,20 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __r
   load_table<T, M>(tw2, tw2_g, M + 1);
   const int row0 = blockIdx.x * NP;
   using V2 = typename io2<IO>::t;
-  for (int idx = threadIdx.x; idx < NP * M; idx += blockDim.x) {
-    const int row = idx / M, n = idx - row * M;
-    const int grow = row0 + row;
-    cpx<T> val{(T)0, (T)0};
-    if (grow < nrows && n < n_in) {
-      V2 pr = *reinterpret_cast<const V2*>(in + (size_t)grow * row_len + 2 * n);
-      val = cpx<T>{(T)pr.x, (T)pr.y};
-    }
-    lds[n * NPS + row] = val;
-  }
   __syncthreads();
-  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
+  // lanes walk along a row (jt fastest): the first stage loads its inputs
+  // straight from the contiguous row, 2 reals per complex element
+  const int jt = threadIdx.x % C::TJ, p = threadIdx.x / C::TJ;
+  const int grow_p = row0 + p;
+  const IO* src = in + (size_t)grow_p * row_len;
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NPS + pp]; });
-  __syncthreads();
+  load_first<T, M>(v, p, jt, [&](int, int e) {
+    if (grow_p < nrows && e < n_in) {
+      const V2 pr = *reinterpret_cast<const V2*>(src + 2 * e);
+      return cpx<T>{(T)pr.x, (T)pr.y};
+    }
+    return cpx<T>{(T)0, (T)0};
+  });
   run_fft<T, M, false>(v, lds, tw, p, jt, NPS, [&](int pp, int e, cpx<T> val) { lds[e * NPS + pp] = val; });
   __syncthreads();
   for (int idx = threadIdx.x; idx < NP * (M + 1); idx += blockDim.x) {
@@ -151,28 +150,26 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
     if (m < M && m != k) lds[m * NPS + row] = zm;
   }
   __syncthreads();
-  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
+  const int jt = threadIdx.x % C::TJ, p = threadIdx.x / C::TJ;
   cpx<T> v[PlanInfo<M>::E];
   load_first<T, M>(v, p, jt, [&](int pp, int e) { return lds[e * NPS + pp]; });
   __syncthreads();
-  run_fft<T, M, true>(v, lds, tw, p, jt, NPS, [&](int pp, int e, cpx<T> val) { lds[e * NPS + pp] = val; });
-  __syncthreads();
+  // the last stage hands z[n] = (x[2n], x[2n+1]) to the epilogue directly
   using V2 = typename io2<IO>::t;
+  const int grow_p = row0 + p;
   const int half = n_out / 2;
-  for (int idx = threadIdx.x; idx < NP * half; idx += blockDim.x) {
-    const int row = idx / half, n = idx - row * half;
-    const int grow = row0 + row;
-    if (grow >= nrows) continue;
-    const cpx<T> z = lds[n * NPS + row];
-    const size_t off = (size_t)grow * row_len + 2 * n;
-    const size_t eoff = (size_t)(grow % rows_per_comp) * row_len + 2 * n;
-    const double2 e2 = *reinterpret_cast<const double2*>(eps + eoff);
+  const size_t roff = (size_t)grow_p * row_len;
+  const size_t eoff0 = (size_t)(grow_p % rows_per_comp) * row_len;
+  run_fft<T, M, true>(v, lds, tw, p, jt, NPS, [&](int, int n, cpx<T> z) {
+    if (grow_p >= nrows || n >= half) return;
+    const size_t off = roff + 2 * n;
+    const double2 e2 = *reinterpret_cast<const double2*>(eps + eoff0 + 2 * n);
     const V2 j2 = *reinterpret_cast<const V2*>(J + off);
     V2 r;
     r.x = (IO)(((T)(ep.ca * e2.x + ep.c0)) * (T)j2.x + ((T)(ep.cb * e2.x + ep.cb0)) * z.x);
     r.y = (IO)(((T)(ep.ca * e2.y + ep.c0)) * (T)j2.y + ((T)(ep.cb * e2.y + ep.cb0)) * z.y);
     *reinterpret_cast<V2*>(y + off) = r;
-  }
+  });
 }
 
 // ------------------------------------------------------------------ y pass

@@ -864,6 +864,13 @@ int mot_reset(mot_ctx* c) {
   return MOT_OK;
 }
 
+int mot_set_step(mot_ctx* c, int64_t n) {
+  if (!c || n < 0) return MOT_EINVAL;
+  c->nstep = n;
+  c->head = (int)((n + c->nl - 1) % c->nl);
+  return MOT_OK;
+}
+
 int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t max_iter, mot_stats* st) {
   if (!c || !einc || !J_n || einc == J_n || !(tol > 0.0) || max_iter < 1) return MOT_EINVAL;
   if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");

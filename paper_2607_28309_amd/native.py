@@ -22,6 +22,7 @@ EXPORTS = (
     "mot_set_material", "z0_matvec", "gk_matvec", "history_update", "mot_get_history_rhs",
     "mot_excitation", "mot_step", "mot_reset", "mot_green_table", "mot_nlags", "mot_zk_nnz",
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
+    "mot_set_step",
 )
 PROF_NCLASS = 20
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
@@ -67,6 +68,7 @@ def _load():
         "mot_excitation": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp]),
         "mot_step": (ctypes.c_int, [vp, vp, vp, dbl, i32, ctypes.POINTER(MotStats)]),
         "mot_reset": (ctypes.c_int, [vp]),
+        "mot_set_step": (ctypes.c_int, [vp, i64]),
         "mot_green_table": (ctypes.c_int, [vp, i32, vp]),
         "mot_nlags": (i32, [ctypes.POINTER(MotGrid)]),
         "mot_zk_nnz": (i64, [ctypes.POINTER(MotGrid), i32]),
@@ -205,6 +207,9 @@ class Context:
 
     def reset(self):
         self._check(LIB.mot_reset(self.h), "mot_reset")
+
+    def set_step(self, n):
+        self._check(LIB.mot_set_step(self.h, int(n)), "mot_set_step")
 
     def profile(self, enable=True):
         self._check(LIB.mot_profile(self.h, 1 if enable else 0), "mot_profile")
