@@ -69,6 +69,22 @@ def cpu_baseline(w, eps, log_fn):
             "cpu": _cpu_name()}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter runs, or None when the
+    kernel's source changed since they were taken (or none were taken)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def _cpu_name():
     try:
         for line in open("/proc/cpuinfo"):
@@ -193,7 +209,7 @@ def main():
     avg_s = ms / cnt / 1e3
     achieved = alg / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": f"{kind}.{prec}", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{kind}.{prec}"),
                 "algorithmic_bytes_per_launch": alg, "avg_launch_ms": ms / cnt}
     # Z0 pipeline as a whole (five passes)
     pipe_bytes = sum(algorithmic_bytes(k, n, 4, 4, nl) for k in
