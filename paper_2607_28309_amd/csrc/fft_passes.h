@@ -22,18 +22,20 @@ struct Epilogue {
 
 // x pass, forward: `nrows` rows of `row_len` reals (row stride row_len) ->
 // rows of Nx+1 complex (stride kxs).  M = complex FFT length (= Nx), the
-// first n_in complex pairs of each row are read, the rest are zero.
+// first n_in complex pairs of each row are read, the rest are zero.  With
+// ncomp = 3 the rows are three components of rows_per_comp rows each and a
+// workgroup takes the same voxel rows of all three.
 template <typename T, typename IO>
-hipError_t x_forward(const IO* in, void* out, int M, int nrows, int row_len, int n_in, int kxs,
-                     const void* tw, const void* tw2, hipStream_t s);
+hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
+                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s);
 
 // x pass, inverse with epilogue: rows of M+1 complex -> first n_out reals of
 // a length-2M real signal; y/J rows of row_len reals, eps indexed by
 // (row mod rows_per_comp) * row_len + x.
 template <typename T, typename IO>
 hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
-                     int nrows, int rows_per_comp, int row_len, int n_out, int kxs, const void* tw,
-                     const void* tw2, hipStream_t s);
+                     int nrows, int rows_per_comp, int ncomp, int row_len, int n_out, int kxs,
+                     const void* tw, const void* tw2, hipStream_t s);
 
 // y pass: `planes` planes; input rows_in rows (first n_in read), output
 // rows_out rows (first n_out written).
@@ -42,8 +44,9 @@ hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kx
                   int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s);
 
 // z pass over `nc` (1 or 3) components; ny = number of ky rows.
-// FUSED multiplies by Lambda (6 real components, octant-compressed
-// [6][M/2+1][ny/2+1][kxs]) between the forward and inverse transforms.
+// FUSED (nc = 3) multiplies by Lambda between the forward and inverse
+// transforms; Lambda is octant-compressed in the tile layout
+// [ny/2+1][kx][M/2+1][6] (component order xx, yy, zz, xy, xz, yz).
 template <typename T>
 hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
                   int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,

@@ -226,13 +226,15 @@ __global__ void k_embed(const double* __restrict__ goct, double* __restrict__ E,
   E[id] = v;
 }
 
-// Octant compression of the real spectrum, scaled by 1/(Px Py Pz):
-// lam[comp][kzc][kyc][kx] for kx <= Nx, kyc <= Ny, kzc <= Nz.  The largest
+// Octant compression of the real spectrum, scaled by 1/(Px Py Pz), for
+// kx <= Nx, kyc <= Ny, kzc <= Nz: layout [comp][kzc][kyc][kxs] (tile = 0, read
+// by the history multiply-accumulate) or [kyc][kx][kzc][comp] (tile = 1, read
+// by the fused z pass, one contiguous range per kx tile).  The largest
 // |imaginary part| of each block goes to imax[block] (the embedded kernels
 // are even or odd-odd per axis, so the spectra are real up to rounding).
 __global__ void k_compress(const double2* __restrict__ spec, double* __restrict__ lam64,
                            float* __restrict__ lam32, double* __restrict__ imax, int comp, int nx, int ny,
-                           int nz, int kxs, double scale) {
+                           int nz, int kxs, double scale, int tile) {
   const int py = 2 * ny;
   const long long cnt = (long long)(nx + 1) * (ny + 1) * (nz + 1);
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,7 +243,8 @@ __global__ void k_compress(const double2* __restrict__ spec, double* __restrict_
     const int kx = (int)(id % (nx + 1)), ky = (int)((id / (nx + 1)) % (ny + 1)),
               kz = (int)(id / ((long long)(nx + 1) * (ny + 1)));
     const double2 v = spec[((long long)kz * py + ky) * kxs + kx];
-    const long long o = (((long long)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx;
+    const long long o = tile ? (((long long)ky * (nx + 1) + kx) * (nz + 1) + kz) * 6 + comp
+                             : (((long long)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx;
     const double r = v.x * scale;
     if (lam64) lam64[o] = r;
     if (lam32) lam32[o] = (float)r;
@@ -317,9 +320,9 @@ int compress_blocks(int nx, int ny, int nz) {
 }
 
 hipError_t launch_compress(const void* spec, double* lam64, float* lam32, double* imax, int comp, int nx,
-                           int ny, int nz, int kxs, double scale, hipStream_t s) {
+                           int ny, int nz, int kxs, double scale, int tile, hipStream_t s) {
   hipLaunchKernelGGL(motgreen::k_compress, dim3(compress_blocks(nx, ny, nz)), dim3(256), 0, s,
-                     (const double2*)spec, lam64, lam32, imax, comp, nx, ny, nz, kxs, scale);
+                     (const double2*)spec, lam64, lam32, imax, comp, nx, ny, nz, kxs, scale, tile);
   return hipGetLastError();
 }
 

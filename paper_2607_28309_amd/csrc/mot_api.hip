@@ -56,6 +56,7 @@ struct mot_ctx {
   double prof_ms[MOT_PROF_NCLASS];
   long long prof_cnt[MOT_PROF_NCLASS];
   double spectra_imag;
+  void* lam_tile;      // scratch: one history lag in the z-pass layout (gk_matvec)
   size_t bytes;
   char err[512];
 };
@@ -272,6 +273,20 @@ __global__ void k_einc(mot_pulse p, double t, const double* __restrict__ eps, do
   out[2 * N + m] = a * p.e[2];
 }
 
+// [6][nz+1][ny+1][kxs] -> [ny+1][nx+1][nz+1][6]
+template <typename T>
+__global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int kxs) {
+  const long long cnt = 6LL * (nx + 1) * (ny + 1) * (nz + 1);
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= cnt) return;
+  const int comp = (int)(id % 6);
+  long long r = id / 6;
+  const int kz = (int)(r % (nz + 1));
+  r /= (nz + 1);
+  const int kx = (int)(r % (nx + 1)), ky = (int)(r / (nx + 1));
+  dst[id] = src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
+}
+
 }  // namespace
 
 namespace motimpl {
@@ -305,14 +320,15 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
   hipStream_t s = c->stream;
   const int rows = 3 * c->nz * c->ny;
   const bool d = ti == 1;
-  HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nx, c->nx / 2, c->kxs, c->twx[ti], c->tw2x[ti], s)));
+  HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
+                                         c->twx[ti], c->tw2x[ti], s)));
   HTP(K_YF, d, motfft::y_pass<T>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py, c->py,
                                  c->twy[ti], s));
   HTP(K_ZFUSED, d, motfft::z_pass<T>(c->wsB, c->wsB, c->pz, motfft::Z_FUSED, 3, c->kx, c->kxs, c->py, c->nz, c->nz,
                                      c->nz, c->nz, lam, c->twz[ti], s));
   HTP(K_YI, d, motfft::y_pass<T>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny, c->ny,
                                  c->twy[ti], s));
-  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, J, c->eps, ep, c->nx, rows, c->nz * c->ny, c->nx, c->nx,
+  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, J, c->eps, ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
                                          c->kxs, c->twx[ti], c->tw2x[ti], s)));
   return MOT_OK;
 }
@@ -491,8 +507,8 @@ int history_update_t(mot_ctx* c, const double* J) {
   const int slot = (int)(c->nstep % c->nl);
   cpx<Tr>* dst = (cpx<Tr>*)c->ring + (size_t)slot * c->slot_elems;
   const bool d = ti == 1;
-  HTP(K_XF, d, (motfft::x_forward<Tr, double>(J, c->wsA, c->nx, rows, c->nx, c->nx / 2, c->kxs, c->twx[ti],
-                                              c->tw2x[ti], s)));
+  HTP(K_XF, d, (motfft::x_forward<Tr, double>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
+                                              c->twx[ti], c->tw2x[ti], s)));
   HTP(K_YF, d, motfft::y_pass<Tr>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py,
                                   c->py, c->twy[ti], s));
   HTP(K_ZF, d, motfft::z_pass<Tr>(c->wsB, dst, c->pz, motfft::Z_FWD, 3, c->kx, c->kxs, c->py, c->nz, c->nz, c->pz,
@@ -504,7 +520,7 @@ int history_update_t(mot_ctx* c, const double* J) {
                                   c->nz, c->nz, nullptr, c->twz[ti], s));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
                                   c->ny, c->twy[ti], s));
-  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, EP_HIST, c->nx, rows, c->nz * c->ny,
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, EP_HIST, c->nx, rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s)));
   c->head = slot;
   c->nstep += 1;
@@ -652,7 +668,7 @@ int mot_destroy(mot_ctx* c) {
   if (!c) return MOT_OK;
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->eps, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
-                  c->partials, c->scal};
+                  c->partials, c->scal, c->lam_tile};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 13; ++i)
@@ -736,8 +752,8 @@ int build_green_spectra(mot_ctx* c) {
     hipError_t e = launch_green(goct, c->nx, c->ny, c->nz, k, c->alpha, c->L, c->nq, s);
     for (int comp = 0; comp < 6 && e == hipSuccess; ++comp) {
       if ((e = launch_embed(goct, E, comp, c->nx, c->ny, c->nz, s)) != hipSuccess) break;
-      if ((e = motfft::x_forward<double, double>(E, T1, c->nx, c->pz * c->py, c->px, c->nx, c->kxs, c->twx[1],
-                                                 c->tw2x[1], s)) != hipSuccess)
+      if ((e = motfft::x_forward<double, double>(E, T1, c->nx, c->pz * c->py, c->pz * c->py, 1, c->px, c->nx,
+                                                 c->kxs, c->twx[1], c->tw2x[1], s)) != hipSuccess)
         break;
       if ((e = motfft::y_pass<double>(T1, T2, c->py, false, c->kx, c->kxs, c->pz, c->py, c->py, c->py, c->py,
                                       c->twy[1], s)) != hipSuccess)
@@ -756,7 +772,8 @@ int build_green_spectra(mot_ctx* c) {
       } else {
         l32 = (float*)c->lamh + (size_t)(k - 1) * 6 * c->lam_comp;
       }
-      if ((e = launch_compress(T1, l64, l32, imax, comp, c->nx, c->ny, c->nz, c->kxs, scale, s)) != hipSuccess)
+      if ((e = launch_compress(T1, l64, l32, imax, comp, c->nx, c->ny, c->nz, c->kxs, scale, k == 0 ? 1 : 0, s)) !=
+          hipSuccess)
         break;
       if ((e = hipMemcpyAsync(hmax.data(), imax, sizeof(double) * nblk, hipMemcpyDeviceToHost, s)) != hipSuccess)
         break;
@@ -797,15 +814,25 @@ int gk_matvec(mot_ctx* c, int32_t k, const void* J, void* y, mot_precision dtype
       return green_product<float, double>(c, (const double*)J, (double*)y, c->lam0_32, EP_G);
     return MOT_EINVAL;
   }
+  if (c->ring_f64 ? dtype != MOT_F64 : (dtype != MOT_F32 && dtype != MOT_F32_REFINED)) return MOT_EINVAL;
+  // history spectra are stored for the multiply-accumulate; copy lag k into
+  // the z-pass layout first
   const size_t off = (size_t)(k - 1) * 6 * c->lam_comp;
+  const size_t cnt = (size_t)6 * (c->nx + 1) * (c->ny + 1) * (c->nz + 1);
+  if (!c->lam_tile) TRY(dmalloc(c, &c->lam_tile, cnt * sizeof(double)));
+  dim3 g((unsigned)((cnt + 255) / 256));
   if (c->ring_f64) {
-    if (dtype != MOT_F64) return MOT_EINVAL;
-    return green_product<double, double>(c, (const double*)J, (double*)y, (const double*)c->lamh + off, EP_G);
+    hipLaunchKernelGGL(k_relayout<double>, g, dim3(256), 0, c->stream, (const double*)c->lamh + off,
+                       (double*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs);
+    HT(hipGetLastError());
+    return green_product<double, double>(c, (const double*)J, (double*)y, (const double*)c->lam_tile, EP_G);
   }
-  if (dtype == MOT_F32) return green_product<float, float>(c, (const float*)J, (float*)y, (const float*)c->lamh + off, EP_G);
-  if (dtype == MOT_F32_REFINED)
-    return green_product<float, double>(c, (const double*)J, (double*)y, (const float*)c->lamh + off, EP_G);
-  return MOT_EINVAL;
+  hipLaunchKernelGGL(k_relayout<float>, g, dim3(256), 0, c->stream, (const float*)c->lamh + off,
+                     (float*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs);
+  HT(hipGetLastError());
+  if (dtype == MOT_F32)
+    return green_product<float, float>(c, (const float*)J, (float*)y, (const float*)c->lam_tile, EP_G);
+  return green_product<float, double>(c, (const double*)J, (double*)y, (const float*)c->lam_tile, EP_G);
 }
 
 int history_update(mot_ctx* c, const double* J_n) {
