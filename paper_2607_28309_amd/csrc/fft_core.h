@@ -198,7 +198,9 @@ struct Stages<T, M, TJ, INV, NS, RadixList<R, Rest...>> {
   }
 };
 
-// Plan of radices per supported length.
+// Plan of radices per supported length.  Radices are chosen so that every
+// M/R shares a large common factor: more threads per pencil, fewer values
+// per thread, more waves per CU for the same LDS footprint.
 template <int M> struct Plan;
 #define MOT_PLAN(M_, ...) \
   template <> struct Plan<M_> { using list = RadixList<__VA_ARGS__>; };
@@ -209,19 +211,19 @@ MOT_PLAN(20, 4, 5)
 MOT_PLAN(24, 4, 6)
 MOT_PLAN(32, 8, 4)
 MOT_PLAN(40, 4, 10)
-MOT_PLAN(48, 8, 6)
+MOT_PLAN(48, 4, 4, 3)
 MOT_PLAN(64, 8, 8)
-MOT_PLAN(80, 8, 10)
-MOT_PLAN(96, 8, 4, 3)
+MOT_PLAN(80, 4, 4, 5)
+MOT_PLAN(96, 4, 4, 6)
 MOT_PLAN(120, 2, 2, 6, 5)
 MOT_PLAN(128, 8, 4, 4)
-MOT_PLAN(160, 8, 4, 5)
+MOT_PLAN(160, 4, 4, 10)
 MOT_PLAN(180, 6, 6, 5)
 MOT_PLAN(192, 8, 8, 3)
 MOT_PLAN(240, 2, 2, 6, 10)
-MOT_PLAN(320, 8, 8, 5)
+MOT_PLAN(320, 4, 4, 4, 5)
 MOT_PLAN(480, 2, 2, 2, 6, 10)
-MOT_PLAN(640, 8, 8, 10)
+MOT_PLAN(640, 4, 4, 4, 10)
 #undef MOT_PLAN
 
 // Supported transform lengths, for host-side dispatch.

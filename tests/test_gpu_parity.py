@@ -20,7 +20,8 @@ from oracle import basis, green, march, masks, operators
 
 pytestmark = pytest.mark.gpu
 
-GRIDS = [((8, 8, 8), 4), ((16, 16, 16), 1), ((24, 20, 12), 8), ((16, 6, 4), 16), ((40, 12, 6), 2)]
+GRIDS = [((8, 8, 8), 4), ((16, 16, 16), 1), ((24, 20, 12), 8), ((16, 6, 4), 16), ((40, 12, 6), 2),
+         ((48, 40, 24), 2), ((80, 24, 10), 4)]
 
 
 @functools.lru_cache(maxsize=None)
