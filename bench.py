@@ -29,7 +29,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid):
+def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid, blk=1):
     """Minimal HBM bytes of one launch of a pass (roofline)."""
     nx, ny, nz = n
     kx, py, pz = nx + 1, 2 * ny, 2 * nz
@@ -46,7 +46,7 @@ def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid):
         "y_inverse": b + a,
         "x_inverse_epilogue": a + 3 * N * io_bytes + N * 8 + 3 * N * io_bytes,
         "z_forward": b + f,
-        "history_mac": nvalid * (f + lam) + f,
+        "history_mac": nvalid * (f + lam) + blk * f,
         "z_inverse": f + b,
     }.get(kind)
 
@@ -205,7 +205,8 @@ def main():
     tb = 8 if prec == "f64" else 4
     if kind == "history_mac":
         tb = ring_t
-    alg = algorithmic_bytes(kind, n, tb, tb, nl)
+    # the history pass at a block start writes the partial sums of 4 (FP32 ring) or 2 (FP64) steps
+    alg = algorithmic_bytes(kind, n, tb, tb, nl, blk=4 if ring_t == 4 else 2)
     avg_s = ms / cnt / 1e3
     achieved = alg / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": f"{kind}.{prec}", "achieved": achieved, "peak": HBM_PEAK_GBS,

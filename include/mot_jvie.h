@@ -143,7 +143,10 @@ int gk_matvec(mot_ctx* ctx, int32_t k, const void* J, void* y, mot_precision dty
  *   h_{n+1} = -sum_{k=1..ell} Z_k J_{n+1-k}
  *           = -(eps_r/2) J_n + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
  * using the spectra of past currents (each current is transformed once).
- * Errors: MOT_ESTATE, MOT_EHIP. */
+ * The spectral sums are blocked in time: every B steps (B = 4 for an FP32
+ * ring, 2 for FP64) one pass over the ring accumulates the contributions of
+ * all stored currents to the next B right-hand sides; the steps in between
+ * add only their newest lags.  Errors: MOT_ESTATE, MOT_EHIP. */
 int history_update(mot_ctx* ctx, const double* J_n);
 
 /* Copy the prepared history right-hand side (FP64, 3N) to `out` (device). */
@@ -180,13 +183,14 @@ int mot_green_table(mot_ctx* ctx, int32_t k, double* out);
  * one of MOT_PROF_NCLASS classes:
  *   class = 2*kind + (FP64 ? 1 : 0), kind: 0 x forward, 1 y forward,
  *   2 z fused (forward, Lambda, inverse), 3 y inverse, 4 x inverse + Eq. 12
- *   epilogue, 5 z forward (history spectra), 6 history multiply-accumulate,
- *   7 z inverse (history), 8 Krylov vector/reduction kernels (FP64: odd class),
- *   9 excitation.
+ *   epilogue, 5 z forward (history spectra), 6 history multiply-accumulate
+ *   over all old slots (start of a block of steps), 7 z inverse (history),
+ *   8 Krylov vector/reduction kernels (FP64: odd class), 9 excitation,
+ *   10 history multiply-accumulate of the newest lags inside a block.
  * mot_profile_read copies the accumulated milliseconds and launch counts of
  * the n = MOT_PROF_NCLASS classes to host arrays, then clears them (it
  * waits for the stream).  Timing adds a few microseconds per launch. */
-#define MOT_PROF_NCLASS 20
+#define MOT_PROF_NCLASS 22
 int mot_profile(mot_ctx* ctx, int32_t enable);
 int mot_profile_read(mot_ctx* ctx, double* ms, int64_t* counts, int32_t n);
 

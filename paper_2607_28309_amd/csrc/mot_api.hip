@@ -40,6 +40,9 @@ struct mot_ctx {
   void* spec;          // MAC output, ring precision, 3*pz*py*kxs complex
   void* ring;
   size_t slot_elems;   // complex elements per ring slot
+  int blk_B;           // steps per history block (temporal blocking)
+  long long blk_n0;    // step that started the current block, -1 = none
+  void* pblk;          // partial sums P_2..P_B of the current block
   long long nstep;
   int head;
   double* hrhs;
@@ -86,7 +89,7 @@ int fail_hip(mot_ctx* c, hipError_t e, const char* what, int line) {
 
 long long round_up(long long v, long long m) { return (v + m - 1) / m * m; }
 
-enum Kind { K_XF = 0, K_YF, K_ZFUSED, K_YI, K_XI, K_ZF, K_MAC, K_ZI, K_KRY, K_EINC };
+enum Kind { K_XF = 0, K_YF, K_ZFUSED, K_YI, K_XI, K_ZF, K_MAC, K_ZI, K_KRY, K_EINC, K_MACR };
 
 int prof_flush(mot_ctx* c) {
   if (c->prof_used == 0) return MOT_OK;
@@ -193,68 +196,6 @@ int make_twiddles(mot_ctx* c, int M, int count, void** out) {
   return MOT_OK;
 }
 
-// ---------------------------------------------------------------- history MAC
-// S(k) = sum_{j=1..nvalid} Lambda_j(k) J^_{n+1-j}(k): one thread per octant
-// frequency (kx, kyc, kzc); its (up to) four mirror points ky in {kyc, Py-kyc},
-// kz in {kzc, Pz-kzc} share the six Lambda_j values read once per lag.
-template <typename T>
-__global__ __launch_bounds__(256) void k_mac(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
-                                             cpx<T>* __restrict__ out, int nl, int nvalid, int head, int nx,
-                                             int ny, int nz, int kxs) {
-  const long long cnt = (long long)(nx + 1) * (ny + 1) * (nz + 1);
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= cnt) return;
-  const int kx = (int)(id % (nx + 1)), kyc = (int)((id / (nx + 1)) % (ny + 1)),
-            kzc = (int)(id / ((long long)(nx + 1) * (ny + 1)));
-  const int py = 2 * ny, pz = 2 * nz;
-  const size_t plane = (size_t)py * kxs;          // one kz plane of one component
-  const size_t comp = (size_t)pz * plane;         // one component
-  const size_t slot = 3 * comp;
-  const size_t lcomp = (size_t)(nz + 1) * (ny + 1) * kxs;
-  const size_t lo = ((size_t)kzc * (ny + 1) + kyc) * kxs + kx;
-  // mirror points (a: kz side, b: ky side); a duplicate of point 0 on the
-  // kyc in {0, Ny} or kzc in {0, Nz} planes is computed but not stored
-  const bool dupy = (kyc == 0 || kyc == ny), dupz = (kzc == 0 || kzc == nz);
-  size_t off[4];
-  bool keep[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int a = i >> 1, b = i & 1;
-    const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
-    off[i] = (size_t)(kz % pz) * plane + (size_t)(ky % py) * kxs + kx;
-    keep[i] = !((a && dupz) || (b && dupy));
-  }
-  cpx<T> acc[4][3];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) acc[i][q] = cpx<T>{(T)0, (T)0};
-  for (int j = 1; j <= nvalid; ++j) {
-    const int s = (head - (j - 1) + nl) % nl;
-    const T* L = lamh + (size_t)(j - 1) * 6 * lcomp + lo;
-    const T lxx = L[0], lyy = L[lcomp], lzz = L[2 * lcomp], lxy = L[3 * lcomp], lxz = L[4 * lcomp],
-            lyz = L[5 * lcomp];
-    const cpx<T>* R = ring + (size_t)s * slot;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const T sy = (i & 1) ? (T)-1 : (T)1, sz = (i >> 1) ? (T)-1 : (T)1;
-      const cpx<T> jx = R[off[i]], jy = R[comp + off[i]], jz = R[2 * comp + off[i]];
-      const T xy = sy * lxy, xz = sz * lxz, yz = sy * sz * lyz;
-      acc[i][0].x += lxx * jx.x + xy * jy.x + xz * jz.x;
-      acc[i][0].y += lxx * jx.y + xy * jy.y + xz * jz.y;
-      acc[i][1].x += xy * jx.x + lyy * jy.x + yz * jz.x;
-      acc[i][1].y += xy * jx.y + lyy * jy.y + yz * jz.y;
-      acc[i][2].x += xz * jx.x + yz * jy.x + lzz * jz.x;
-      acc[i][2].y += xz * jx.y + yz * jy.y + lzz * jz.y;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (keep[i])
-#pragma unroll
-      for (int q = 0; q < 3; ++q) out[q * comp + off[i]] = acc[i][q];
-}
-
 // ---------------------------------------------------------------- excitation
 __global__ void k_einc(mot_pulse p, double t, const double* __restrict__ eps, double* __restrict__ out, int nx,
                        int ny, int nz) {
@@ -290,18 +231,6 @@ __global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int n
 }  // namespace
 
 namespace motimpl {
-hipError_t launch_mac(const void* ring, const void* lamh, void* out, int f64, int nl, int nvalid, int head, int nx,
-                      int ny, int nz, int kxs, hipStream_t s) {
-  const long long cnt = (long long)(nx + 1) * (ny + 1) * (nz + 1);
-  dim3 g((unsigned)((cnt + 255) / 256));
-  if (f64)
-    hipLaunchKernelGGL(k_mac<double>, g, dim3(256), 0, s, (const cpx<double>*)ring, (const double*)lamh,
-                       (cpx<double>*)out, nl, nvalid, head, nx, ny, nz, kxs);
-  else
-    hipLaunchKernelGGL(k_mac<float>, g, dim3(256), 0, s, (const cpx<float>*)ring, (const float*)lamh,
-                       (cpx<float>*)out, nl, nvalid, head, nx, ny, nz, kxs);
-  return hipGetLastError();
-}
 hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* out, int nx, int ny, int nz,
                        hipStream_t s) {
   const long long N = (long long)nx * ny * nz;
@@ -513,9 +442,21 @@ int history_update_t(mot_ctx* c, const double* J) {
                                   c->py, c->twy[ti], s));
   HTP(K_ZF, d, motfft::z_pass<Tr>(c->wsB, dst, c->pz, motfft::Z_FWD, 3, c->kx, c->kxs, c->py, c->nz, c->nz, c->pz,
                                   c->pz, nullptr, c->twz[ti], s));
-  const long long nvalid = c->nstep + 1 < c->nl ? c->nstep + 1 : c->nl;
-  HTP(K_MAC, d, launch_mac(c->ring, c->lamh, c->spec, sizeof(Tr) == 8, c->nl, (int)nvalid, slot, c->nx, c->ny,
-                           c->nz, c->kxs, s));
+  const long long n = c->nstep;
+  if (c->blk_n0 < 0 || n - c->blk_n0 >= c->blk_B) {
+    // block start: contributions of every slot <= n to the next B right-hand sides
+    c->blk_n0 = n;
+    const int nold = (int)(n + 1 < c->nl ? n + 1 : c->nl);
+    HTP(K_MAC, d, launch_mac_block(c->ring, c->lamh, c->spec, c->pblk, sizeof(Tr) == 8, c->blk_B, c->nl, n, nold,
+                                   c->nx, c->ny, c->nz, c->kxs, s));
+  } else {
+    // inside a block: P_b plus the r = n - n0 newest lags
+    const int r = (int)(n - c->blk_n0);
+    const size_t bytes_per_slot = (c->ring_f64 ? 16 : 8) * c->slot_elems;
+    const void* init = (const char*)c->pblk + (size_t)(r - 1) * bytes_per_slot;
+    HTP(K_MACR, d, launch_mac_recent(c->ring, c->lamh, init, c->spec, sizeof(Tr) == 8, c->nl, n, r, c->nx, c->ny,
+                                     c->nz, c->kxs, s));
+  }
   HTP(K_ZI, d, motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz,
                                   c->nz, c->nz, nullptr, c->twz[ti], s));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
@@ -641,6 +582,11 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if ((rc = dmalloc(c, (void**)&c->lam0_32, sizeof(float) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->lamh, rsz * 6 * c->lam_comp * c->nl)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->spec, rsz * 2 * c->slot_elems)) != MOT_OK) return fail(rc);
+  c->blk_B = c->ring_f64 ? 2 : 4;
+  if (c->blk_B > c->nl) c->blk_B = c->nl >= 4 && !c->ring_f64 ? 4 : (c->nl >= 2 ? 2 : 1);
+  c->blk_n0 = -1;
+  if (c->blk_B > 1 && (rc = dmalloc(c, &c->pblk, rsz * 2 * c->slot_elems * (c->blk_B - 1))) != MOT_OK)
+    return fail(rc);
   if ((rc = dmalloc(c, &c->ring, rsz * 2 * c->slot_elems * c->nl)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->hrhs, sizeof(double) * c->n3)) != MOT_OK) return fail(rc);
   for (int i = 0; i < 13; ++i)
@@ -668,7 +614,7 @@ int mot_destroy(mot_ctx* c) {
   if (!c) return MOT_OK;
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->eps, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
-                  c->partials, c->scal, c->lam_tile};
+                  c->partials, c->scal, c->lam_tile, c->pblk};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 13; ++i)
@@ -888,6 +834,7 @@ int mot_reset(mot_ctx* c) {
   TRY(zero_bytes(c, c->hrhs, sizeof(double) * c->n3));
   c->nstep = 0;
   c->head = 0;
+  c->blk_n0 = -1;
   return MOT_OK;
 }
 
@@ -895,6 +842,7 @@ int mot_set_step(mot_ctx* c, int64_t n) {
   if (!c || n < 0) return MOT_EINVAL;
   c->nstep = n;
   c->head = (int)((n + c->nl - 1) % c->nl);
+  c->blk_n0 = -1;
   return MOT_OK;
 }
 

@@ -24,9 +24,9 @@ EXPORTS = (
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
     "mot_set_step",
 )
-PROF_NCLASS = 20
+PROF_NCLASS = 22
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
-              "history_mac", "z_inverse", "krylov", "excitation")
+              "history_mac", "z_inverse", "krylov", "excitation", "history_mac_recent")
 
 
 class MotGrid(ctypes.Structure):
