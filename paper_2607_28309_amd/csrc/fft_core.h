@@ -8,12 +8,15 @@
 // that lanes with consecutive pencil indices touch consecutive addresses.
 // The first stage's loads and the last stage's stores go through caller
 // functors (global memory for strided pencils, LDS for contiguous rows).
+// Both receive the element as jt + u with u a compile-time offset, so that
+// callers can address memory from one per-thread base.
 //
-// Stockham autosort, decimation in time: with span Ns (product of the radices
-// already applied), butterfly j of a stage with radix R reads elements
-// j + r*M/R, multiplies element r by W_{Ns R}^{(j mod Ns) r}, applies the
-// length-R DFT and writes element (j/Ns)*Ns*R + (j mod Ns) + r*Ns.  The
-// twiddles come from a table tw[q] = exp(-2 pi i q / M) held in LDS.
+// Zero-padded transforms: with HIN the upper half of the inputs is known to
+// be zero (the doubled grid of the circulant embedding) and is neither loaded
+// nor added; with HOUT only the lower half of the outputs is stored (the
+// truncation back to the physical grid) and the arithmetic that only feeds
+// the discarded half is dead code.
+//
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -53,20 +56,24 @@ __host__ __device__ constexpr double rot_sin(int R, int j) {
        : (j == 0 ? 0.0 : (j == 1 || j == 4) ? 0.58778525229247312917 : 0.95105651629515357212);
 }
 
+// d * exp(-+2 pi i j / R) for a compile-time j (after unrolling): no
+// arithmetic for j = 0, a swap for the quarter turn.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ cpx<T> rotate(cpx<T> d, int j) {
+  if (j == 0) return d;
+  if (4 * j == R) return mul_i<INV>(d);
+  const T c = (T)rot_cos(R, j);
+  const T s = INV ? (T)rot_sin(R, j) : -(T)rot_sin(R, j);
+  return cpx<T>{d.x * c - d.y * s, d.x * s + d.y * c};
+}
+
 // In-register DFT of length R: v[k] <- sum_j v[j] exp(-+2 pi i jk/R).
+// run_half: the same with v[R/2..R-1] = 0 (those registers are not read).
 template <int R, bool INV, typename T> struct Dft {
   // even composite radix R = 2Q: radix-2 split, rotate the odd half, two DFT_Q
-  static __device__ __forceinline__ void run(cpx<T>* v) {
-    constexpr int Q = R / 2;
-    cpx<T> a[Q], b[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      a[j] = cadd(v[j], v[j + Q]);
-      cpx<T> d = csub(v[j], v[j + Q]);
-      const T c = (T)rot_cos(R, j);
-      const T s = INV ? (T)rot_sin(R, j) : -(T)rot_sin(R, j);
-      b[j] = cpx<T>{d.x * c - d.y * s, d.x * s + d.y * c};
-    }
+  static_assert(R % 2 == 0, "composite radices are even");
+  static constexpr int Q = R / 2;
+  static __device__ __forceinline__ void finish(cpx<T>* v, cpx<T>* a, cpx<T>* b) {
     Dft<Q, INV, T>::run(a);
     Dft<Q, INV, T>::run(b);
 #pragma unroll
@@ -75,6 +82,24 @@ template <int R, bool INV, typename T> struct Dft {
       v[2 * m + 1] = b[m];
     }
   }
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a[Q], b[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      a[j] = cadd(v[j], v[j + Q]);
+      b[j] = rotate<R, INV, T>(csub(v[j], v[j + Q]), j);
+    }
+    finish(v, a, b);
+  }
+  static __device__ __forceinline__ void run_half(cpx<T>* v) {
+    cpx<T> a[Q], b[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      a[j] = v[j];
+      b[j] = rotate<R, INV, T>(v[j], j);
+    }
+    finish(v, a, b);
+  }
 };
 template <bool INV, typename T> struct Dft<2, INV, T> {
   static __device__ __forceinline__ void run(cpx<T>* v) {
@@ -82,6 +107,7 @@ template <bool INV, typename T> struct Dft<2, INV, T> {
     v[0] = cadd(a, v[1]);
     v[1] = csub(a, v[1]);
   }
+  static __device__ __forceinline__ void run_half(cpx<T>* v) { v[1] = v[0]; }
 };
 template <bool INV, typename T> struct Dft<3, INV, T> {
   static __device__ __forceinline__ void run(cpx<T>* v) {
@@ -105,6 +131,13 @@ template <bool INV, typename T> struct Dft<4, INV, T> {
     v[2] = csub(t0, t2);
     v[1] = cadd(t1, t3);
     v[3] = csub(t1, t3);
+  }
+  static __device__ __forceinline__ void run_half(cpx<T>* v) {
+    const cpx<T> a = v[0], b = v[1], bi = mul_i<INV>(v[1]);
+    v[0] = cadd(a, b);
+    v[2] = csub(a, b);
+    v[1] = cadd(a, bi);
+    v[3] = csub(a, bi);
   }
 };
 template <bool INV, typename T> struct Dft<5, INV, T> {
@@ -144,17 +177,19 @@ template <int M, typename L> struct FirstRadix;
 template <int M, int R, int... Rest> struct FirstRadix<M, RadixList<R, Rest...>> { static constexpr int value = R; };
 
 // Run the stages of RadixList on registers v (inputs of the first remaining
-// stage already loaded).  `store(p, element, value)` receives the outputs of
-// the last stage.
-template <typename T, int M, int TJ, bool INV, int NS, typename L> struct Stages;
+// stage already loaded).  `store(p, jt, u, value)` receives the outputs of
+// the last stage, element jt + u.
+template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, typename L> struct Stages;
 
-template <typename T, int M, int TJ, bool INV, int NS, int R, int... Rest>
-struct Stages<T, M, TJ, INV, NS, RadixList<R, Rest...>> {
+template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, int R, int... Rest>
+struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>> {
   template <typename Store>
   static __device__ __forceinline__ void run(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt,
                                              int np, Store&& store) {
     constexpr int B = M / (R * TJ);
     constexpr int TWS = M / (NS * R);
+    constexpr bool half_in = HIN && NS == 1;
+    static_assert(!half_in || R % 2 == 0, "a zero-padded transform needs an even first radix");
 #pragma unroll
     for (int t = 0; t < B; ++t) {
       const int j = jt + t * TJ;
@@ -166,16 +201,24 @@ struct Stages<T, M, TJ, INV, NS, RadixList<R, Rest...>> {
           v[t * R + r] = INV ? cmulc(v[t * R + r], w) : cmul(v[t * R + r], w);
         }
       }
-      Dft<R, INV, T>::run(&v[t * R]);
+      if constexpr (half_in)
+        Dft<R, INV, T>::run_half(&v[t * R]);
+      else
+        Dft<R, INV, T>::run(&v[t * R]);
     }
     if constexpr (sizeof...(Rest) == 0) {
+      // last stage: NS * R = M, butterfly j < NS, outputs j + r NS
 #pragma unroll
-      for (int t = 0; t < B; ++t) {
-        const int j = jt + t * TJ;
-        const int base = (j / NS) * NS * R + (j % NS);
+      for (int t = 0; t < B; ++t)
 #pragma unroll
-        for (int r = 0; r < R; ++r) store(p, base + r * NS, v[t * R + r]);
-      }
+        for (int r = 0; r < R; ++r) {
+          const int u = t * TJ + r * NS;
+          // element jt + u with 0 <= jt < TJ: decided at compile time unless
+          // the lane band [u, u + TJ) straddles M/2
+          if (HOUT && u >= M / 2) continue;
+          if (HOUT && u + TJ > M / 2 && jt + u >= M / 2) continue;
+          store(p, jt, u, v[t * R + r]);
+        }
     } else {
 #pragma unroll
       for (int t = 0; t < B; ++t) {
@@ -193,7 +236,7 @@ struct Stages<T, M, TJ, INV, NS, RadixList<R, Rest...>> {
 #pragma unroll
         for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[(jt + t * TJ + r * MR2) * np + p];
       __syncthreads();
-      Stages<T, M, TJ, INV, NS * R, RadixList<Rest...>>::run(v, lds, tw, p, jt, np, store);
+      Stages<T, M, TJ, INV, NS * R, false, HOUT, RadixList<Rest...>>::run(v, lds, tw, p, jt, np, store);
     }
   }
 };
@@ -238,8 +281,11 @@ template <int M> struct PlanInfo {
   static constexpr int R0 = FirstRadix<M, list>::value;
 };
 
-// Load the first stage's inputs for pencil p: element(e) returns value e.
-template <typename T, int M, typename Load>
+// Load the first stage's inputs for pencil p: elem(p, jt, u) returns element
+// jt + u.  The elements a thread loads are jt + TJ i, i < E, register
+// t R0 + r holding i = t + r M/(R0 TJ).  With HIN only the lower half
+// (r < R0/2, exactly the elements below M/2) is loaded.
+template <typename T, int M, bool HIN, typename Load>
 __device__ __forceinline__ void load_first(cpx<T>* v, int p, int jt, Load&& elem) {
   using PI = PlanInfo<M>;
   constexpr int R = PI::R0;
@@ -247,14 +293,14 @@ __device__ __forceinline__ void load_first(cpx<T>* v, int p, int jt, Load&& elem
 #pragma unroll
   for (int t = 0; t < B; ++t)
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[t * R + r] = elem(p, jt + t * PI::TJ + r * (M / R));
+    for (int r = 0; r < (HIN ? R / 2 : R); ++r) v[t * R + r] = elem(p, jt, t * PI::TJ + r * (M / R));
 }
 
-template <typename T, int M, bool INV, typename Store>
+template <typename T, int M, bool INV, bool HIN, bool HOUT, typename Store>
 __device__ __forceinline__ void run_fft(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt, int np,
                                         Store&& store) {
   using PI = PlanInfo<M>;
-  Stages<T, M, PI::TJ, INV, 1, typename PI::list>::run(v, lds, tw, p, jt, np, store);
+  Stages<T, M, PI::TJ, INV, 1, HIN, HOUT, typename PI::list>::run(v, lds, tw, p, jt, np, store);
 }
 
 }  // namespace motfft

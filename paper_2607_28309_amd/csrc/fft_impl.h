@@ -1,0 +1,98 @@
+// Shared configuration of the FFT pass kernels (x, y and z passes live in
+// their own translation units so that they compile in parallel).
+//
+// Workgroups of the y and z passes are issued in an XCD-aware order: the
+// hardware hands consecutive workgroup ids to the eight XCDs in turn, each
+// with its own L2, so logical tile t is given to id (t mod Q) * 8 + t / Q
+// (Q = ceil(tiles/8)); neighbouring kx tiles of one row then share an L2 and
+// the 128-byte lines they split are fetched from HBM once.
+#pragma once
+
+#include "fft_core.h"
+#include "fft_passes.h"
+
+namespace motfft {
+
+constexpr int floor_pow2(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int LDS_BUDGET = 81920;
+
+// LDS rows are padded to NPS = NP + 1 entries so that lanes walking along a
+// pencil (stride NPS) and the row stride of the Stockham writes spread over
+// the LDS banks instead of hitting the same ones.
+template <typename T, int M> struct XCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int NP =
+      cmax(1, floor_pow2(cmin(256 / TJ, (LDS_BUDGET - (2 * M + 1) * SZ) / ((M + 1) * SZ) - 1)));
+  static constexpr int NPS = NP + 1;
+  static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)((M + 1) * NPS + 2 * M + 1) * SZ;
+};
+template <typename T, int M> struct YCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int NP = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ) - 1)));
+  static constexpr int NPS = NP + 1;
+  static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
+};
+template <typename T, int M, int NC> struct ZCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int W =
+      cmax(1, floor_pow2(cmin(cmin(16, 1024 / (NC * TJ)), (LDS_BUDGET - 2 * M * SZ) / (NC * M * SZ))));
+  static constexpr int NP = NC * W;
+  static constexpr int NPS = NP + 1;
+  static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
+};
+
+// z pass with the spectral multiply: W kx columns x 3 components x 2 ky rows.
+template <typename T, int M> struct ZFCfg {
+  static constexpr int TJ = PlanInfo<M>::TJ;
+  static constexpr int SZ = (int)sizeof(cpx<T>);
+  static constexpr int W =
+      cmax(1, floor_pow2(cmin(cmin(16, 1024 / (6 * TJ)), (LDS_BUDGET - 2 * M * SZ) / (6 * M * SZ))));
+  static constexpr int NP = 6 * W;
+  static constexpr int NPS = NP + 1;
+  static constexpr int BLOCK = NP * TJ;
+  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
+};
+
+constexpr int NXCD = 8;
+// logical tile of workgroup id b; tiles >= nlog are idle
+__device__ __forceinline__ int xcd_tile(int b, int nlog) {
+  const int q = (nlog + NXCD - 1) / NXCD;
+  return (b % NXCD) * q + b / NXCD;
+}
+inline int xcd_grid(int nlog) { return ((nlog + NXCD - 1) / NXCD) * NXCD; }
+
+// Copy a table of N entries into LDS: all loads of a thread are issued
+// before its LDS writes.
+template <typename C, int N, int BLOCK>
+__device__ __forceinline__ void load_table(C* dst, const C* __restrict__ src) {
+  constexpr int IT = (N + BLOCK - 1) / BLOCK;
+  C tmp[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int idx = (int)threadIdx.x + i * BLOCK;
+    tmp[i] = src[idx < N ? idx : N - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int idx = (int)threadIdx.x + i * BLOCK;
+    if (idx < N) dst[idx] = tmp[i];
+  }
+}
+
+template <typename IO> struct io2;
+template <> struct io2<float> { using t = float2; };
+template <> struct io2<double> { using t = double2; };
+
+}  // namespace motfft

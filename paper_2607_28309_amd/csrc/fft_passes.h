@@ -45,13 +45,25 @@ hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kx
 
 // z pass over `nc` (1 or 3) components; ny = number of ky rows.
 // FUSED (nc = 3) multiplies by Lambda between the forward and inverse
-// transforms; Lambda is octant-compressed in the tile layout
-// [ny/2+1][kx][M/2+1][6] (component order xx, yy, zz, xy, xz, yz).
+// transforms; Lambda is octant-compressed in the tile layout of
+// lam_tile_offset with W = z_fused_width(M, T is double).
 template <typename T>
 hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
                   int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,
                   hipStream_t s);
 
 bool length_supported(int M);
+
+// kx columns per workgroup of the fused z pass (0 for an unsupported length).
+int z_fused_width(int M, bool f64);
+
+// Offset of the octant spectrum value of component comp (order xx, yy, zz,
+// xy, xz, yz) at (kx, kyc, kzc) in the fused z pass's tile layout
+// [kyc][kx / W][kzc][comp][kx % W]: one workgroup's values are one contiguous
+// range, and lanes of consecutive kx read consecutive words.
+__host__ __device__ inline size_t lam_tile_offset(int kx, int kyc, int kzc, int comp, int kxn, int nzc, int W) {
+  const int ntile = (kxn + W - 1) / W;
+  return ((((size_t)kyc * ntile + kx / W) * nzc + kzc) * 6 + comp) * W + kx % W;
+}
 
 }  // namespace motfft

@@ -20,6 +20,7 @@
 // integrated by Gauss-Legendre.  Phi = f for A_pp, Phi = K (K' = H/R^2) for B.
 #include <hip/hip_runtime.h>
 
+#include "fft_passes.h"
 #include "mot_internal.h"
 
 namespace motgreen {
@@ -234,7 +235,7 @@ __global__ void k_embed(const double* __restrict__ goct, double* __restrict__ E,
 // are even or odd-odd per axis, so the spectra are real up to rounding).
 __global__ void k_compress(const double2* __restrict__ spec, double* __restrict__ lam64,
                            float* __restrict__ lam32, double* __restrict__ imax, int comp, int nx, int ny,
-                           int nz, int kxs, double scale, int tile) {
+                           int nz, int kxs, double scale, int w64, int w32) {
   const int py = 2 * ny;
   const long long cnt = (long long)(nx + 1) * (ny + 1) * (nz + 1);
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,11 +244,11 @@ __global__ void k_compress(const double2* __restrict__ spec, double* __restrict_
     const int kx = (int)(id % (nx + 1)), ky = (int)((id / (nx + 1)) % (ny + 1)),
               kz = (int)(id / ((long long)(nx + 1) * (ny + 1)));
     const double2 v = spec[((long long)kz * py + ky) * kxs + kx];
-    const long long o = tile ? (((long long)ky * (nx + 1) + kx) * (nz + 1) + kz) * 6 + comp
-                             : (((long long)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx;
+    // w > 0: tile layout of the fused z pass; w = 0: [comp][kz][ky][kxs]
+    const size_t plain = (((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx;
     const double r = v.x * scale;
-    if (lam64) lam64[o] = r;
-    if (lam32) lam32[o] = (float)r;
+    if (lam64) lam64[w64 ? motfft::lam_tile_offset(kx, ky, kz, comp, nx + 1, nz + 1, w64) : plain] = r;
+    if (lam32) lam32[w32 ? motfft::lam_tile_offset(kx, ky, kz, comp, nx + 1, nz + 1, w32) : plain] = (float)r;
     im = fabs(v.y) * scale;
   }
   __shared__ double red[256];
@@ -320,9 +321,9 @@ int compress_blocks(int nx, int ny, int nz) {
 }
 
 hipError_t launch_compress(const void* spec, double* lam64, float* lam32, double* imax, int comp, int nx,
-                           int ny, int nz, int kxs, double scale, int tile, hipStream_t s) {
+                           int ny, int nz, int kxs, double scale, int w64, int w32, hipStream_t s) {
   hipLaunchKernelGGL(motgreen::k_compress, dim3(compress_blocks(nx, ny, nz)), dim3(256), 0, s,
-                     (const double2*)spec, lam64, lam32, imax, comp, nx, ny, nz, kxs, scale, tile);
+                     (const double2*)spec, lam64, lam32, imax, comp, nx, ny, nz, kxs, scale, w64, w32);
   return hipGetLastError();
 }
 

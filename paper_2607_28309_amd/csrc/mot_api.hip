@@ -214,18 +214,19 @@ __global__ void k_einc(mot_pulse p, double t, const double* __restrict__ eps, do
   out[2 * N + m] = a * p.e[2];
 }
 
-// [6][nz+1][ny+1][kxs] -> [ny+1][nx+1][nz+1][6]
+// [6][nz+1][ny+1][kxs] -> tile layout of the fused z pass (tiles of w columns)
 template <typename T>
-__global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int kxs) {
+__global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int kxs, int w) {
   const long long cnt = 6LL * (nx + 1) * (ny + 1) * (nz + 1);
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= cnt) return;
-  const int comp = (int)(id % 6);
-  long long r = id / 6;
-  const int kz = (int)(r % (nz + 1));
-  r /= (nz + 1);
-  const int kx = (int)(r % (nx + 1)), ky = (int)(r / (nx + 1));
-  dst[id] = src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
+  const int kx = (int)(id % (nx + 1));
+  long long r = id / (nx + 1);
+  const int ky = (int)(r % (ny + 1));
+  r /= (ny + 1);
+  const int kz = (int)(r % (nz + 1)), comp = (int)(r / (nz + 1));
+  dst[motfft::lam_tile_offset(kx, ky, kz, comp, nx + 1, nz + 1, w)] =
+      src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
 }
 
 }  // namespace
@@ -718,7 +719,9 @@ int build_green_spectra(mot_ctx* c) {
       } else {
         l32 = (float*)c->lamh + (size_t)(k - 1) * 6 * c->lam_comp;
       }
-      if ((e = launch_compress(T1, l64, l32, imax, comp, c->nx, c->ny, c->nz, c->kxs, scale, k == 0 ? 1 : 0, s)) !=
+      const int w64 = k == 0 ? motfft::z_fused_width(c->pz, true) : 0;
+      const int w32 = k == 0 ? motfft::z_fused_width(c->pz, false) : 0;
+      if ((e = launch_compress(T1, l64, l32, imax, comp, c->nx, c->ny, c->nz, c->kxs, scale, w64, w32, s)) !=
           hipSuccess)
         break;
       if ((e = hipMemcpyAsync(hmax.data(), imax, sizeof(double) * nblk, hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -765,16 +768,17 @@ int gk_matvec(mot_ctx* c, int32_t k, const void* J, void* y, mot_precision dtype
   // the z-pass layout first
   const size_t off = (size_t)(k - 1) * 6 * c->lam_comp;
   const size_t cnt = (size_t)6 * (c->nx + 1) * (c->ny + 1) * (c->nz + 1);
-  if (!c->lam_tile) TRY(dmalloc(c, &c->lam_tile, cnt * sizeof(double)));
+  // the tile layout pads kx to whole tiles, which never exceeds kxs columns
+  if (!c->lam_tile) TRY(dmalloc(c, &c->lam_tile, 6 * c->lam_comp * sizeof(double)));
   dim3 g((unsigned)((cnt + 255) / 256));
   if (c->ring_f64) {
     hipLaunchKernelGGL(k_relayout<double>, g, dim3(256), 0, c->stream, (const double*)c->lamh + off,
-                       (double*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs);
+                       (double*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs, motfft::z_fused_width(c->pz, true));
     HT(hipGetLastError());
     return green_product<double, double>(c, (const double*)J, (double*)y, (const double*)c->lam_tile, EP_G);
   }
   hipLaunchKernelGGL(k_relayout<float>, g, dim3(256), 0, c->stream, (const float*)c->lamh + off,
-                     (float*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs);
+                     (float*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs, motfft::z_fused_width(c->pz, false));
   HT(hipGetLastError());
   if (dtype == MOT_F32)
     return green_product<float, float>(c, (const float*)J, (float*)y, (const float*)c->lam_tile, EP_G);

@@ -38,9 +38,10 @@ hipError_t launch_green(double* out, int nx, int ny, int nz, int k, int alpha, d
                         hipStream_t s);
 hipError_t launch_embed(const double* goct, double* E, int comp, int nx, int ny, int nz, hipStream_t s);
 int compress_blocks(int nx, int ny, int nz);
-// tile = 0: [comp][kzc][kyc][kxs] (history lags); tile = 1: [kyc][kx][kzc][6] (z-pass layout)
+// w64 / w32 = 0: [comp][kzc][kyc][kxs] (history lags); > 0: the fused z
+// pass's tile layout (motfft::lam_tile_offset) with tiles of that many columns
 hipError_t launch_compress(const void* spec, double* lam64, float* lam32, double* imax, int comp, int nx,
-                           int ny, int nz, int kxs, double scale, int tile, hipStream_t s);
+                           int ny, int nz, int kxs, double scale, int w64, int w32, hipStream_t s);
 
 // ---- krylov.hip (vectors of length n, element type V = float or double)
 // Scalar recurrence applied by the reduction that produced scal[slot].
