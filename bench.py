@@ -51,36 +51,104 @@ def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid, blk=1):
     }.get(kind)
 
 
-def cpu_baseline(w, eps, log_fn):
-    """Oracle FP64 Z0 product (FFT form, NumPy) at the benchmark size."""
+def cpu_baseline(w, eps, mv_per_step, nl, log_fn):
+    """The FP64 oracle's MOT step rate at the benchmark size, from a bounded
+    sample: two oracle Z0 products, one spectral lag multiply-accumulate and
+    the transforms of one step, each timed once.  A step of the oracle's march
+    is mv_per_step Z0 products (the count the GPU run measured) plus nl lag
+    multiply-accumulates, one inverse and one forward transform of the
+    history (oracle.march.Mot.step)."""
     import numpy as np
     import workloads as W
-    from oracle import green, operators
+    from oracle import green, march
+    log_fn("cpu baseline: oracle spectra of G_0 (untimed set-up)")
     g0 = green.green_octant(*w.n, 0, alpha=w.alpha)
-    lam, _ = operators.embed_spectra(g0)
+    mot = march.Mot(eps, [g0], w.alpha / math.sqrt(3.0))
     J = W.random_current(w.n, seed=1)
-    log_fn("cpu baseline: timing one oracle Z0 product at full size")
+    log_fn("cpu baseline: timing the oracle sample")
     t = time.perf_counter()
-    operators.z0_apply(g0, eps, J, lam=lam)
-    dt = time.perf_counter() - t
-    return {"value": 1.0 / dt, "unit": "Z0 matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": "one FP64 Z0 product (Eq. 11/12, numpy.fft, spectra precomputed) at "
-                      f"{w.n[0]}x{w.n[1]}x{w.n[2]}; {dt:.1f} s",
-            "cpu": _cpu_name()}
+    mot.z0(J)
+    mot.z0(J)
+    t_z0 = (time.perf_counter() - t) / 2
+    t = time.perf_counter()
+    Jh = mot._spec(J)
+    t_spec = time.perf_counter() - t
+    t = time.perf_counter()
+    S = mot._apply_spec(mot.lams[0], Jh)
+    t_mac = time.perf_counter() - t
+    t = time.perf_counter()
+    mot._back(S)
+    t_back = time.perf_counter() - t
+    t_step = mv_per_step * t_z0 + nl * t_mac + t_back + t_spec
+    sample_s = 2 * t_z0 + t_spec + t_mac + t_back
+    return {"value": 1.0 / t_step, "unit": "MOT steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 (NumPy, one thread) at {w.n[0]}x{w.n[1]}x{w.n[2]}: 2 Z0 products "
+                      f"({t_z0:.2f} s each), one lag multiply-accumulate ({t_mac:.2f} s), forward and inverse "
+                      f"transforms ({t_spec:.2f} s, {t_back:.2f} s), {sample_s:.1f} s in all; a step = "
+                      f"{mv_per_step:.1f} Z0 products + {nl} lag MACs + 2 transforms = {t_step:.0f} s",
+            "z0_matvecs_per_s": 1.0 / t_z0, "cpu": _cpu_name()}
+
+
+def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
+    """The same march in FP64 (FP64 FFT products and Krylov vectors) from the
+    same state: steps/s over its last f64_steps steps, and the field error of
+    the main run, max_n |J_n - J64_n| / max_n |J64_n| over the kept steps."""
+    import torch
+    from paper_2607_28309_amd import native
+    n = w.n
+    N = n[0] * n[1] * n[2]
+    c = native.Context(*n, alpha=w.alpha, precision="f64")
+    c.set_material(torch.from_numpy(eps.ravel()).cuda())
+    c.build_green_spectra()
+    nl = c.info()["nlags"]
+    c.reset()
+    c.set_step(nl)
+    J64 = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    einc = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    err_num, ref_max, st64 = 0.0, 0.0, []
+    t = None
+    for s in range(n_keep):
+        if s == args.warmup:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+        c.excitation(pulse, (args.start_step + s) * L, einc)
+        st = c.step(einc, J64, tol=args.tol, stats=True)[1]
+        if s >= args.warmup:
+            st64.append(st)
+        err_num = max(err_num, float(torch.linalg.vector_norm(Js[s] - J64)))
+        ref_max = max(ref_max, float(torch.linalg.vector_norm(J64)))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    k = n_keep - args.warmup
+    c.close()
+    res = {"mot_steps_per_s_f64": k / el, "ms_per_step_f64": 1e3 * el / k,
+           "iters_per_step_f64": sum(x["iters"] for x in st64) / k,
+           "field_err_vs_f64": err_num / ref_max if ref_max > 0 else 0.0,
+           "field_err_steps": n_keep}
+    log_fn(f"FP64 march: {res['ms_per_step_f64']:.1f} ms/step, field error of {args.precision} vs FP64 "
+           f"{res['field_err_vs_f64']:.2e} over {n_keep} steps")
+    return res
+
+
+def sources_sha256(paths):
+    """sha256 over the concatenated contents of the given repository files."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed counter runs, or None when the
-    kernel's source changed since they were taken (or none were taken)."""
-    import hashlib
+    kernel's sources changed since they were taken (or none were taken)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
-    src = os.path.join(ROOT, rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+    if sources_sha256(rec["sources"]) != rec["sources_sha256"]:
         return None
     return rec["bytes_per_launch"]
 
@@ -101,7 +169,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f32_refined", choices=["f32_refined", "f64", "f32"])
-    ap.add_argument("--matvec-reps", type=int, default=30)
+    ap.add_argument("--matvec-reps", type=int, default=60, help="timed Z0 products per precision (median reported)")
+    ap.add_argument("--f64-steps", type=int, default=3,
+                    help="steps of the FP64 march timed after the main run (0 = skip); its currents also give "
+                         "the field error of the main run against FP64")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
@@ -149,14 +220,17 @@ def main():
     p = W.pulse(w.ppw)
     L = w.alpha / math.sqrt(3.0)
     einc = torch.empty(3 * N, dtype=torch.float64, device="cuda")
-    J = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    # one output vector per step, so that the currents can be compared with an FP64 march afterwards
+    n_keep = args.warmup + min(args.steps, args.f64_steps)
+    Js = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(n_keep)]
+    J_spare = torch.empty(3 * N, dtype=torch.float64, device="cuda")
 
-    def one_step(s):
-        ctx.excitation(p, (args.start_step + s) * L, einc)
-        return ctx.step(einc, J, tol=args.tol, stats=True)[1]
+    def one_step(c, s):
+        c.excitation(p, (args.start_step + s) * L, einc)
+        return c.step(einc, Js[s] if s < n_keep else J_spare, tol=args.tol, stats=True)[1]
 
     for s in range(args.warmup):
-        st = one_step(s)
+        st = one_step(ctx, s)
         log(f"warm-up step {s}: {st['iters']} iterations, relres {st['relres']:.2e}")
     ctx.profile(True)
     ctx.profile_read()
@@ -164,7 +238,7 @@ def main():
     t = time.perf_counter()
     stats = []
     for s in range(args.steps):
-        stats.append(one_step(args.warmup + s))
+        stats.append(one_step(ctx, args.warmup + s))
         log(f"step {s}: {stats[-1]['iters']} it, {stats[-1]['matvecs']} mv "
             f"({stats[-1]['matvecs_f64']} f64), relres {stats[-1]['relres']:.2e}, "
             f"lhs {stats[-1]['ms_lhs']:.1f} ms, rhs {stats[-1]['ms_rhs']:.1f} ms")
@@ -174,22 +248,25 @@ def main():
     ctx.profile(False)
     ms_per_step = 1e3 * elapsed / args.steps
 
-    # Z0 product throughput (FP32 and FP64), events on torch's current stream
+    # Z0 product throughput (FP32 and FP64): one event pair per product on the
+    # context's stream (torch's current stream), median over the repetitions
     mv = {}
+    reps = max(args.matvec_reps, 1)
     for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
         Jm = torch.randn(3 * N, dtype=tdt, device="cuda")
         ym = torch.empty_like(Jm)
-        for _ in range(3):
+        for _ in range(5):
             ctx.z0_matvec(Jm, ym, dt_name)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.matvec_reps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
             ctx.z0_matvec(Jm, ym, dt_name)
-        e1.record()
+            e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.matvec_reps
-        mv[dt_name] = {"ms": ms, "per_s": 1e3 / ms}
-        log(f"z0_matvec {dt_name}: {ms:.3f} ms")
+        times = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        ms = times[len(times) // 2]
+        mv[dt_name] = {"ms": ms, "per_s": 1e3 / ms, "mean_ms": sum(times) / len(times), "reps": reps}
+        log(f"z0_matvec {dt_name}: median {ms:.3f} ms over {reps}")
         del Jm, ym
 
     # roofline of the kernel with the largest share of the timed region among
@@ -244,10 +321,13 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, eps, log)
-    print(json.dumps(out), flush=True)
     ctx.close()
+    del ctx
+    if args.f64_steps > 0:
+        out.update(f64_march(args, w, eps, p, L, Js, n_keep, log))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, eps, out["matvecs_per_step"], nl, log)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
