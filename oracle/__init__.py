@@ -19,10 +19,14 @@ Volume Integral Equation for Dielectric Scattering"):
 * ``krylov``    -- Freund's TFQMR (Sec. II, solver paragraph), real arithmetic.
 * ``march``     -- plane-wave excitation (Eq. 7, Eq. 8) and the MOT recursion
                    of Eq. 3.
+* ``adjoint``   -- the transposed operators Z_k^T (contrast on the input), the
+                   far-field signature of the current history and its energy,
+                   the time-reversed adjoint march and the gradient of the
+                   energy with respect to eps_r.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by ``tests/test_oracle_*.py`` against values the paper prints, closed
 forms or invariants, unless it says "parity unpinned".
 """
 
-from . import basis, masks, green, operators, krylov, march  # noqa: F401
+from . import basis, masks, green, operators, krylov, march, adjoint  # noqa: F401
