@@ -194,6 +194,68 @@ int mot_green_table(mot_ctx* ctx, int32_t k, double* out);
 int mot_profile(mot_ctx* ctx, int32_t enable);
 int mot_profile_read(mot_ctx* ctx, double* ms, int64_t* counts, int32_t n);
 
+/* ---- Adjoint march and permittivity gradient (Eq. 1, Eq. 10 structure).
+ *
+ * Every G_k is a symmetric matrix (G_k(-d) = G_k(d), symmetric 3x3 blocks),
+ * so the transposed interaction matrices are
+ *   Z_k^T = T(k dt) diag(eps_r) - G_k diag(eps_r - 1):
+ * the contrast acts on the input.  The transpose of the march
+ * sum_k Z_k J_{n-k} = E_n is solved backwards in time,
+ *   Z0^T lam_n = g_n - (eps_r/2) lam_{n+1} + sum_{k>=1} G_k ((eps_r - 1) lam_{n+k}),
+ * with the same ring, blocking and solver as the forward march.
+ *
+ * Far field (reading; not in the paper): the current radiates through the
+ * retarded potential of Eq. 1; in the unit direction r, with the factor
+ * 1/(4 pi R) and the delay R dropped and samples at tau_j = j dt,
+ *   e_j = -(1/(4 pi dt)) (I - r r^T) sum_m sum_n J_{m,n} T'(j - n + r . r_m / dt),
+ * r_m the voxel centre relative to the grid centre, T' the derivative of the
+ * temporal basis in step units.  For W = dt sum_j |e_j|^2 the adjoint sources
+ * are g_n = mot_farfield_adjoint(2 dt e) and
+ *   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - (J_n(m) + J_{n-1}(m))/2 + u_n(m)),
+ * u_n = sum_{k=0..ell} G_k J_{n-k} = (mot_history_gfield read just before
+ * step n) + gk_matvec(0, J_n). */
+
+/* on = 1: the context's solver and history use Z_k^T (mot_step then takes
+ * an adjoint step: einc is g_n, J_n receives lam_n, steps run backwards in
+ * time); on = 0: the forward operators.  Call mot_reset after switching.
+ * Errors: MOT_EINVAL. */
+int mot_set_adjoint(mot_ctx* ctx, int32_t on);
+
+/* y = Z0^T v = (eps_r/2) v - G_0 ((eps_r - 1) v), dtypes as z0_matvec.
+ * Errors: MOT_EINVAL, MOT_ESTATE, MOT_EHIP. */
+int z0t_matvec(mot_ctx* ctx, const void* v, void* y, mot_precision dtype);
+
+/* out (FP64 device, 3N, not the context's own buffers) = the Green part of
+ * the prepared history for the coming step n: sum_{k>=1} G_k J_{n-k}
+ * (adjoint context: sum_{k>=1} G_k ((eps_r - 1) lam_{n+k})).  Zero after
+ * mot_reset.  Errors: MOT_EINVAL, MOT_ESTATE, MOT_EHIP. */
+int mot_history_gfield(mot_ctx* ctx, double* out);
+
+/* e (FP64 device, [nj][3]) = far-field samples j = j0 .. j0+nj-1 of the
+ * current history Jhist (FP64 device, [nsteps][3N], step n at n*3N) and, if
+ * `energy` (FP64 device scalar) is not NULL, energy = dt sum_j |e_j|^2.
+ * rhat: host array of 3 (normalized by the library; zero is an error).
+ * Deterministic (fixed partial sums).  1 <= nj <= 65535.
+ * Errors: MOT_EINVAL, MOT_ENOMEM, MOT_EHIP. */
+int mot_farfield(mot_ctx* ctx, const double* Jhist, int32_t nsteps, const double* rhat, int32_t j0, int32_t nj,
+                 double* e, double* energy);
+
+/* g_n (FP64 device, 3N) = scale * (transpose of mot_farfield applied to the
+ * weights w (FP64 device, [nj][3]) for step n): scale times the derivative
+ * of sum_j w_j . e_j with respect to J_n (w = e, scale = 2 dt gives
+ * dW/dJ_n).  Errors: MOT_EINVAL, MOT_EHIP. */
+int mot_farfield_adjoint(mot_ctx* ctx, const double* w, int32_t j0, int32_t nj, const double* rhat, double scale,
+                         int64_t n, double* g_n);
+
+/* grad[m] += sum_p lam_n[p,m] (d_t E^i_p(r_m, t) - (J_n[p,m] + J_prev[p,m])/2 + uh_n[p,m] + u0_n[p,m])
+ * for every voxel m: the step-n term of dW/d eps with u_n = uh_n + u0_n split
+ * into its history part (mot_history_gfield before step n) and its present
+ * part (gk_matvec(0, J_n)).  FP64 device vectors: lam_n, J_n, J_prev, uh_n,
+ * u0_n of 3N, grad of N; J_prev may be NULL for n = 0.
+ * Errors: MOT_EINVAL, MOT_EHIP. */
+int mot_adjoint_gradient(mot_ctx* ctx, const mot_pulse* pulse, double t, const double* lam_n, const double* J_n,
+                         const double* J_prev, const double* uh_n, const double* u0_n, double* grad);
+
 /* Host helpers (no GPU needed). */
 int32_t mot_nlags(const mot_grid* grid);           /* ell of Eq. 4 (reading above), or < 0 */
 int64_t mot_zk_nnz(const mot_grid* grid, int32_t k); /* nonzeros of Z_k with dyad weights 3/3/5/9, or < 0 */

@@ -24,10 +24,13 @@ struct Epilogue {
 // rows of Nx+1 complex (stride kxs).  M = complex FFT length (= Nx), the
 // first n_in complex pairs of each row are read, the rest are zero.  With
 // ncomp = 3 the rows are three components of rows_per_comp rows each and a
-// workgroup takes the same voxel rows of all three.
+// workgroup takes the same voxel rows of all three.  pre (optional, n_in =
+// M/2 only): per-voxel values indexed like the inverse pass's eps; the input
+// is multiplied by (pre - 1) on load.
 template <typename T, typename IO>
 hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
-                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s);
+                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s,
+                     const double* pre = nullptr);
 
 // x pass, inverse with epilogue: rows of M+1 complex -> first n_out reals of
 // a length-2M real signal; y/J rows of row_len reals, eps indexed by

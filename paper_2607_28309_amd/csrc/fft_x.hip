@@ -29,12 +29,16 @@ __device__ __forceinline__ int xrow(int p, int ncomp, int rows_per_comp, int nro
   return r < nrows ? r : nrows;
 }
 
+// pre (optional, per voxel row like the epilogue's permittivity): the input
+// is multiplied by (pre - 1) as it is loaded, i.e. the contrast applied on the
+// input for the transposed operators.
 template <typename T, typename IO, int M, bool HIN>
 __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __restrict__ in,
                                                                   cpx<T>* __restrict__ out, int nrows,
                                                                   int rows_per_comp, int ncomp, int row_len,
                                                                   int kxs, const cpx<T>* __restrict__ tw_g,
-                                                                  const cpx<T>* __restrict__ tw2_g) {
+                                                                  const cpx<T>* __restrict__ tw2_g,
+                                                                  const double* __restrict__ pre) {
   using C = XCfg<T, M>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
   extern __shared__ unsigned char smem_raw[];
@@ -46,9 +50,14 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __r
   const int grow = xrow<NP>(p, ncomp, rows_per_comp, nrows);
   const bool valid = grow < nrows;
   const IO* src = in + (size_t)(valid ? grow : 0) * row_len + 2 * jt;
+  const double* prow = pre ? pre + (size_t)((valid ? grow : 0) % rows_per_comp) * row_len + 2 * jt : nullptr;
   cpx<T> v[E];
   load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) {
     const V2 pr = *reinterpret_cast<const V2*>(src + 2 * u);
+    if (prow) {
+      const double2 x2 = *reinterpret_cast<const double2*>(prow + 2 * u);
+      return cpx<T>{(T)((double)pr.x * (x2.x - 1.0)), (T)((double)pr.y * (x2.y - 1.0))};
+    }
     return cpx<T>{(T)pr.x, (T)pr.y};
   });
   load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
@@ -148,9 +157,10 @@ static int x_blocks(int nrows, int rows_per_comp, int ncomp) {
 // only, spectra precompute: rows of 2M reals).
 template <typename T, typename IO>
 hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
-                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s) {
+                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s, const double* pre) {
   const bool half = 2 * n_in == M;
-  if ((!half && n_in != M) || (!half && sizeof(T) != 8) || 2 * n_in > row_len || kxs < M + 1)
+  if ((!half && n_in != M) || (!half && sizeof(T) != 8) || 2 * n_in > row_len || kxs < M + 1 ||
+      (pre && !half))
     return hipErrorInvalidValue;
   switch (M) {
 #define X(m)                                                                                              \
@@ -159,10 +169,10 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
     const dim3 g(x_blocks<C::NP>(nrows, rows_per_comp, ncomp));                                           \
     if (half)                                                                                             \
       hipLaunchKernelGGL((k_x_forward<T, IO, m, true>), g, dim3(C::BLOCK), C::LDS, s, in, (cpx<T>*)out,    \
-                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2); \
+                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, pre); \
     else if constexpr (sizeof(T) == 8 && sizeof(IO) == 8)                                                \
       hipLaunchKernelGGL((k_x_forward<T, IO, m, false>), g, dim3(C::BLOCK), C::LDS, s, in, (cpx<T>*)out,   \
-                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2); \
+                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, nullptr); \
     return hipGetLastError();                                                                             \
   }
     MOT_FOR_EACH_LEN(X)
@@ -196,7 +206,7 @@ hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epil
 
 #define XINST(T, IO)                                                                                      \
   template hipError_t x_forward<T, IO>(const IO*, void*, int, int, int, int, int, int, int, const void*,    \
-                                       const void*, hipStream_t);                                          \
+                                       const void*, hipStream_t, const double*);                           \
   template hipError_t x_inverse<T, IO>(const void*, IO*, const IO*, const double*, Epilogue, int, int, int, \
                                        int, int, int, int, const void*, const void*, hipStream_t);
 XINST(float, float)

@@ -60,6 +60,9 @@ struct mot_ctx {
   long long prof_cnt[MOT_PROF_NCLASS];
   double spectra_imag;
   void* lam_tile;      // scratch: one history lag in the z-pass layout (gk_matvec)
+  int adjoint;         // 1: transposed operators Z_k^T (adjoint march)
+  double* ffpart;      // scratch: far-field block partials
+  size_t ffpart_n;
   size_t bytes;
   char err[512];
 };
@@ -202,13 +205,9 @@ __global__ void k_einc(mot_pulse p, double t, const double* __restrict__ eps, do
   const long long N = (long long)nx * ny * nz;
   const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= N) return;
-  const int ix = (int)(m % nx), iy = (int)((m / nx) % ny), iz = (int)(m / ((long long)nx * ny));
-  const double x = ix + 0.5 - 0.5 * nx, y = iy + 0.5 - 0.5 * ny, z = iz + 0.5 - 0.5 * nz;
-  const double tau = t - p.t0 - (p.k[0] * x + p.k[1] * y + p.k[2] * z);
-  const double w = 2.0 * 3.14159265358979323846 * p.f0;
-  const double env = exp(-tau * tau / (2.0 * p.sigma * p.sigma));
-  const double dg = env * (-(tau / (p.sigma * p.sigma)) * cos(w * tau) - w * sin(w * tau));
-  const double a = (eps[m] - 1.0) * p.amp * dg;
+  double x, y, z;
+  voxel_centre(m, nx, ny, nz, x, y, z);
+  const double a = (eps[m] - 1.0) * incident_dt(p, t, x, y, z);
   out[m] = a * p.e[0];
   out[N + m] = a * p.e[1];
   out[2 * N + m] = a * p.e[2];
@@ -245,13 +244,13 @@ namespace {
 // ---------------------------------------------------------------- Green product
 // y = epilogue(J, G J) with spectra `lam` (precision T) through the five passes.
 template <typename T, typename IO>
-int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue ep) {
+int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue ep, const double* pre = nullptr) {
   const int ti = sizeof(T) == 8 ? 1 : 0;
   hipStream_t s = c->stream;
   const int rows = 3 * c->nz * c->ny;
   const bool d = ti == 1;
   HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
-                                         c->twx[ti], c->tw2x[ti], s)));
+                                         c->twx[ti], c->tw2x[ti], s, pre)));
   HTP(K_YF, d, motfft::y_pass<T>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py, c->py,
                                  c->twy[ti], s));
   HTP(K_ZFUSED, d, motfft::z_pass<T>(c->wsB, c->wsB, c->pz, motfft::Z_FUSED, 3, c->kx, c->kxs, c->py, c->nz, c->nz,
@@ -266,6 +265,9 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
 const motfft::Epilogue EP_Z0{0.5, 0.0, -1.0, 1.0};      // D J - X (G J)
 const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};        // G J
 const motfft::Epilogue EP_HIST{-0.5, 0.0, 1.0, -1.0};   // -(eps/2) J + X (G J)
+// transposed operators (contrast on the input, applied by the forward x pass)
+const motfft::Epilogue EP_Z0T{0.5, 0.0, 0.0, -1.0};     // (eps/2) v - G (X v)
+const motfft::Epilogue EP_ADJ_HIST{-0.5, 0.0, 0.0, 1.0}; // -(eps/2) v + G (X v)
 
 int reduce_sync(mot_ctx* c) {
   HT(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->stream));
@@ -280,10 +282,13 @@ struct SolveOut {
 
 // Z0 product in the precision of the vectors: FP64 vectors -> FP64 FFTs,
 // FP32 vectors -> FP32 FFTs.
+// In an adjoint context the solver's operator is Z0^T.
 int apply_z0(mot_ctx* c, const double* in, double* out) {
+  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0T, c->eps);
   return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0);
 }
 int apply_z0(mot_ctx* c, const float* in, float* out) {
+  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0T, c->eps);
   return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0);
 }
 
@@ -437,8 +442,9 @@ int history_update_t(mot_ctx* c, const double* J) {
   const int slot = (int)(c->nstep % c->nl);
   cpx<Tr>* dst = (cpx<Tr>*)c->ring + (size_t)slot * c->slot_elems;
   const bool d = ti == 1;
+  // the adjoint march transforms (eps - 1) lam: Z_k^T = T(k) diag(eps) - G_k X
   HTP(K_XF, d, (motfft::x_forward<Tr, double>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
-                                              c->twx[ti], c->tw2x[ti], s)));
+                                              c->twx[ti], c->tw2x[ti], s, c->adjoint ? c->eps : nullptr)));
   HTP(K_YF, d, motfft::y_pass<Tr>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py,
                                   c->py, c->twy[ti], s));
   HTP(K_ZF, d, motfft::z_pass<Tr>(c->wsB, dst, c->pz, motfft::Z_FWD, 3, c->kx, c->kxs, c->py, c->nz, c->nz, c->pz,
@@ -462,10 +468,30 @@ int history_update_t(mot_ctx* c, const double* J) {
                                   c->nz, c->nz, nullptr, c->twz[ti], s));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
                                   c->ny, c->twy[ti], s));
-  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, EP_HIST, c->nx, rows, c->nz * c->ny, 3,
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, c->adjoint ? EP_ADJ_HIST : EP_HIST, c->nx,
+                                              rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s)));
   c->head = slot;
   c->nstep += 1;
+  return MOT_OK;
+}
+
+// T{F^-1 S} of the prepared history spectrum S (held in spec until the next
+// history update): sum_{k>=1} G_k J_{n-k} for the coming step n, or
+// sum_{k>=1} G_k (eps - 1) lam_{n+k} in an adjoint context.
+template <typename Tr>
+int history_gfield_t(mot_ctx* c, double* out) {
+  const int ti = sizeof(Tr) == 8 ? 1 : 0;
+  hipStream_t s = c->stream;
+  const int rows = 3 * c->nz * c->ny;
+  const bool d = ti == 1;
+  HTP(K_ZI, d, motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz,
+                                  c->nz, c->nz, nullptr, c->twz[ti], s));
+  HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
+                                  c->ny, c->twy[ti], s));
+  // EP_G ignores its current argument; hrhs is passed as a valid vector
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, out, c->hrhs, c->eps, EP_G, c->nx, rows, c->nz * c->ny, 3,
+                                              c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s)));
   return MOT_OK;
 }
 
@@ -615,7 +641,7 @@ int mot_destroy(mot_ctx* c) {
   if (!c) return MOT_OK;
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->eps, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
-                  c->partials, c->scal, c->lam_tile, c->pblk};
+                  c->partials, c->scal, c->lam_tile, c->pblk, c->ffpart};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 13; ++i)
@@ -836,6 +862,7 @@ int mot_reset(mot_ctx* c) {
   const size_t rsz = c->ring_f64 ? sizeof(double) : sizeof(float);
   TRY(zero_bytes(c, c->ring, rsz * 2 * c->slot_elems * c->nl));
   TRY(zero_bytes(c, c->hrhs, sizeof(double) * c->n3));
+  TRY(zero_bytes(c, c->spec, rsz * 2 * c->slot_elems));
   c->nstep = 0;
   c->head = 0;
   c->blk_n0 = -1;
@@ -875,6 +902,84 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
     st->ms_rhs = bms;
   }
   return rc;
+}
+
+int mot_set_adjoint(mot_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
+  c->adjoint = on;
+  return MOT_OK;
+}
+
+int z0t_matvec(mot_ctx* c, const void* v, void* y, mot_precision dtype) {
+  if (!c || !v || !y || v == y) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  switch (dtype) {
+    case MOT_F64:
+      return green_product<double, double>(c, (const double*)v, (double*)y, c->lam0_64, EP_Z0T, c->eps);
+    case MOT_F32:
+      return green_product<float, float>(c, (const float*)v, (float*)y, c->lam0_32, EP_Z0T, c->eps);
+    case MOT_F32_REFINED:
+      return green_product<float, double>(c, (const double*)v, (double*)y, c->lam0_32, EP_Z0T, c->eps);
+    default:
+      return MOT_EINVAL;
+  }
+}
+
+int mot_history_gfield(mot_ctx* c, double* out) {
+  if (!c || !out || out == c->hrhs) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  return c->ring_f64 ? history_gfield_t<double>(c, out) : history_gfield_t<float>(c, out);
+}
+
+namespace {
+int far_geom(mot_ctx* c, const double* rhat, FarGeom* g) {
+  if (!rhat) return MOT_EINVAL;
+  const double n2 = rhat[0] * rhat[0] + rhat[1] * rhat[1] + rhat[2] * rhat[2];
+  if (!(n2 > 0.0) || !std::isfinite(n2)) return set_err(c, MOT_EINVAL, "far-field direction is zero or not finite%s%d");
+  const double inv = 1.0 / std::sqrt(n2);
+  for (int i = 0; i < 3; ++i) g->r[i] = rhat[i] * inv;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) g->P[3 * i + k] = (i == k ? 1.0 : 0.0) - g->r[i] * g->r[k];
+  g->dt = c->L;
+  return MOT_OK;
+}
+}  // namespace
+
+int mot_farfield(mot_ctx* c, const double* Jhist, int32_t nsteps, const double* rhat, int32_t j0, int32_t nj,
+                 double* e, double* energy) {
+  if (!c || !Jhist || !e || nsteps < 1 || nj < 1 || nj > 65535) return MOT_EINVAL;
+  FarGeom g;
+  TRY(far_geom(c, rhat, &g));
+  const size_t need = farfield_partials(c->N, nj);
+  if (need > c->ffpart_n) {
+    if (c->ffpart) {
+      HT(hipStreamSynchronize(c->stream));
+      HT(hipFree(c->ffpart));
+      c->bytes -= sizeof(double) * c->ffpart_n;
+      c->ffpart = nullptr;
+      c->ffpart_n = 0;
+    }
+    TRY(dmalloc(c, (void**)&c->ffpart, sizeof(double) * need));
+    c->ffpart_n = need;
+  }
+  HT(launch_farfield(Jhist, nsteps, c->nx, c->ny, c->nz, g, j0, nj, c->ffpart, e, energy, c->stream));
+  return MOT_OK;
+}
+
+int mot_farfield_adjoint(mot_ctx* c, const double* w, int32_t j0, int32_t nj, const double* rhat, double scale,
+                         int64_t n, double* g_n) {
+  if (!c || !w || !g_n || nj < 1 || n < 0) return MOT_EINVAL;
+  FarGeom g;
+  TRY(far_geom(c, rhat, &g));
+  HT(launch_farfield_adjoint(w, j0, nj, n, c->nx, c->ny, c->nz, g, scale, g_n, c->stream));
+  return MOT_OK;
+}
+
+int mot_adjoint_gradient(mot_ctx* c, const mot_pulse* p, double t, const double* lam_n, const double* J_n,
+                         const double* J_prev, const double* uh_n, const double* u0_n, double* grad) {
+  if (!c || !p || !lam_n || !J_n || !uh_n || !u0_n || !grad) return MOT_EINVAL;
+  HT(launch_adjoint_grad(p, t, lam_n, J_n, J_prev, uh_n, u0_n, grad, c->nx, c->ny, c->nz, c->stream));
+  return MOT_OK;
 }
 
 }  // extern "C"

@@ -83,4 +83,42 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
 hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* out, int nx, int ny, int nz,
                        hipStream_t s);
 
+// Centre of voxel m ([z][y][x], x fastest) relative to the grid centre, units of h.
+__device__ __forceinline__ void voxel_centre(long long m, int nx, int ny, int nz, double& x, double& y, double& z) {
+  const int ix = (int)(m % nx), iy = (int)((m / nx) % ny), iz = (int)(m / ((long long)nx * ny));
+  x = ix + 0.5 - 0.5 * nx;
+  y = iy + 0.5 - 0.5 * ny;
+  z = iz + 0.5 - 0.5 * nz;
+}
+
+// Scalar factor of d/dt E^i at (x, y, z), time t (Eq. 7, Eq. 8): the field
+// derivative is this times the polarization p.e.
+__device__ __forceinline__ double incident_dt(const mot_pulse& p, double t, double x, double y, double z) {
+  const double tau = t - p.t0 - (p.k[0] * x + p.k[1] * y + p.k[2] * z);
+  const double w = 2.0 * 3.14159265358979323846 * p.f0;
+  const double env = exp(-tau * tau / (2.0 * p.sigma * p.sigma));
+  return p.amp * env * (-(tau / (p.sigma * p.sigma)) * cos(w * tau) - w * sin(w * tau));
+}
+
+// ---- adjoint.hip: far field of a current history, its transpose, gradient
+// Far-field geometry: unit direction r, projection P = I - r r^T, step dt.
+struct FarGeom {
+  double r[3];
+  double P[9];
+  double dt;
+};
+// e[nj][3] = far-field samples j0 .. j0+nj-1 of Jhist[nsteps][3N] and, if W is
+// not null, W[0] = dt sum_j |e_j|^2; partials: scratch of farfield_partials(N, nj) doubles.
+size_t farfield_partials(long long N, int nj);
+hipError_t launch_farfield(const double* Jhist, int nsteps, int nx, int ny, int nz, const FarGeom& g, int j0, int nj,
+                           double* partials, double* e, double* W, hipStream_t s);
+// g_n[3N] = scale * (transpose of the far field applied to the weights w[nj][3]), step n.
+hipError_t launch_farfield_adjoint(const double* w, int j0, int nj, long long n, int nx, int ny, int nz,
+                                   const FarGeom& g, double scale, double* g_n, hipStream_t s);
+// grad[m] += sum_p lam[p,m] (d_t E^i_p(r_m, t) - (J[p,m] + Jprev[p,m])/2 + uh[p,m] + u0[p,m]);
+// Jprev may be null.
+hipError_t launch_adjoint_grad(const mot_pulse* p, double t, const double* lam, const double* J,
+                               const double* Jprev, const double* uh, const double* u0, double* grad, int nx, int ny,
+                               int nz, hipStream_t s);
+
 }  // namespace motimpl

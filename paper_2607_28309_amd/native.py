@@ -22,7 +22,8 @@ EXPORTS = (
     "mot_set_material", "z0_matvec", "gk_matvec", "history_update", "mot_get_history_rhs",
     "mot_excitation", "mot_step", "mot_reset", "mot_green_table", "mot_nlags", "mot_zk_nnz",
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
-    "mot_set_step",
+    "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
+    "mot_farfield_adjoint", "mot_adjoint_gradient",
 )
 PROF_NCLASS = 22
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
@@ -77,6 +78,12 @@ def _load():
         "mot_profile": (ctypes.c_int, [vp, i32]),
         "mot_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "mot_last_error": (ctypes.c_char_p, [vp]),
+        "mot_set_adjoint": (ctypes.c_int, [vp, i32]),
+        "z0t_matvec": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "mot_history_gfield": (ctypes.c_int, [vp, vp]),
+        "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
+        "mot_farfield_adjoint": (ctypes.c_int, [vp, vp, i32, i32, ctypes.POINTER(dbl), dbl, i64, vp]),
+        "mot_adjoint_gradient": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -92,6 +99,13 @@ class MotError(RuntimeError):
     def __init__(self, status, detail):
         self.status = status
         super().__init__(f"{LIB.mot_strerror(status).decode()} ({status}): {detail}")
+
+
+def make_pulse(pulse):
+    """MotPulse from a dict with keys e, k, f0, sigma, t0 (and amp, default 1)."""
+    return MotPulse((ctypes.c_double * 3)(*[float(v) for v in pulse["e"]]),
+                    (ctypes.c_double * 3)(*[float(v) for v in pulse["k"]]),
+                    float(pulse["f0"]), float(pulse["sigma"]), float(pulse["t0"]), float(pulse.get("amp", 1.0)))
 
 
 def make_grid(nx, ny, nz, alpha=0, cdt=0.0, nlags=0, quad=0):
@@ -190,11 +204,48 @@ class Context:
 
     def excitation(self, pulse, t, out):
         import torch
-        p = MotPulse((ctypes.c_double * 3)(*[float(v) for v in pulse["e"]]),
-                     (ctypes.c_double * 3)(*[float(v) for v in pulse["k"]]),
-                     float(pulse["f0"]), float(pulse["sigma"]), float(pulse["t0"]), float(pulse.get("amp", 1.0)))
+        p = make_pulse(pulse)
         self._check(LIB.mot_excitation(self.h, ctypes.byref(p), float(t), _ptr(out, torch.float64, 3 * self.N)),
                     "mot_excitation")
+
+    def set_adjoint(self, on=True):
+        self._check(LIB.mot_set_adjoint(self.h, 1 if on else 0), "mot_set_adjoint")
+
+    def z0t_matvec(self, v, y, dtype="f64"):
+        import torch
+        tdt = torch.float32 if dtype == "f32" else torch.float64
+        self._check(LIB.z0t_matvec(self.h, _ptr(v, tdt, 3 * self.N), _ptr(y, tdt, 3 * self.N), PRECISIONS[dtype]),
+                    "z0t_matvec")
+
+    def history_gfield(self, out):
+        import torch
+        self._check(LIB.mot_history_gfield(self.h, _ptr(out, torch.float64, 3 * self.N)), "mot_history_gfield")
+
+    def farfield(self, Jhist, rhat, j0, nj, e, energy=None):
+        import torch
+        nsteps = Jhist.numel() // (3 * self.N)
+        r = (ctypes.c_double * 3)(*[float(v) for v in rhat])
+        en = _ptr(energy, torch.float64, 1) if energy is not None else None
+        self._check(LIB.mot_farfield(self.h, _ptr(Jhist, torch.float64, nsteps * 3 * self.N), int(nsteps), r,
+                                     int(j0), int(nj), _ptr(e, torch.float64, 3 * int(nj)), en), "mot_farfield")
+
+    def farfield_adjoint(self, w, j0, rhat, n, g_n, scale=1.0):
+        import torch
+        nj = w.numel() // 3
+        r = (ctypes.c_double * 3)(*[float(v) for v in rhat])
+        self._check(LIB.mot_farfield_adjoint(self.h, _ptr(w, torch.float64, 3 * nj), int(j0), int(nj), r,
+                                             float(scale), int(n), _ptr(g_n, torch.float64, 3 * self.N)),
+                    "mot_farfield_adjoint")
+
+    def adjoint_gradient(self, pulse, t, lam_n, J_n, J_prev, uh_n, u0_n, grad):
+        import torch
+        p = make_pulse(pulse)
+        v3 = 3 * self.N
+        jp = _ptr(J_prev, torch.float64, v3) if J_prev is not None else None
+        self._check(LIB.mot_adjoint_gradient(self.h, ctypes.byref(p), float(t), _ptr(lam_n, torch.float64, v3),
+                                             _ptr(J_n, torch.float64, v3), jp, _ptr(uh_n, torch.float64, v3),
+                                             _ptr(u0_n, torch.float64, v3), _ptr(grad, torch.float64, self.N)),
+                    "mot_adjoint_gradient")
 
     def step(self, einc, J, tol=1e-6, max_iter=1000, stats=True, allow=()):
         """One MOT step; returns (status, stats dict or None)."""
