@@ -193,6 +193,11 @@ int mot_green_table(mot_ctx* ctx, int32_t k, double* out);
 #define MOT_PROF_NCLASS 22
 int mot_profile(mot_ctx* ctx, int32_t enable);
 int mot_profile_read(mot_ctx* ctx, double* ms, int64_t* counts, int32_t n);
+/* Restrict timing to the kinds whose bit is set in kind_mask (bit k = kind
+ * k above; default: all).  Untimed launches carry no events, so a narrow
+ * mask keeps the timing overhead off the rest of the step.
+ * Errors: MOT_EINVAL (negative mask). */
+int mot_profile_kinds(mot_ctx* ctx, int32_t kind_mask);
 
 /* ---- Adjoint march and permittivity gradient (Eq. 1, Eq. 10 structure).
  *

@@ -17,6 +17,21 @@ struct Epilogue {
   double ca, c0, cb, cb0;
 };
 
+// Optional early exit of a whole launch on device flags, for work enqueued
+// ahead of a convergence test: f[0] != 0 means "done", f[1] != 0 "check
+// requested".  mode 0: always run; 1: run while not done; 2: run while not
+// done and a check is requested.  Every thread of the launch reads the same
+// flags, so a closed gate ends every workgroup before its first barrier.
+struct Gate {
+  const double* f = nullptr;
+  int mode = 0;
+};
+__device__ __forceinline__ bool gate_closed(const Gate& g) {
+  if (!g.f || g.mode == 0) return false;
+  if (g.f[0] != 0.0) return true;
+  return g.mode == 2 && g.f[1] == 0.0;
+}
+
 // Precision tags: T = compute type; IO = element type of real vectors.
 // Returns hipSuccess or an error; hipErrorInvalidValue for an unsupported length.
 
@@ -30,7 +45,7 @@ struct Epilogue {
 template <typename T, typename IO>
 hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
                      int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s,
-                     const double* pre = nullptr);
+                     const double* pre = nullptr, Gate g = Gate{});
 
 // x pass, inverse with epilogue: rows of M+1 complex -> first n_out reals of
 // a length-2M real signal; y/J rows of row_len reals, eps indexed by
@@ -38,13 +53,14 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
 template <typename T, typename IO>
 hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
                      int nrows, int rows_per_comp, int ncomp, int row_len, int n_out, int kxs,
-                     const void* tw, const void* tw2, hipStream_t s);
+                     const void* tw, const void* tw2, hipStream_t s, Gate g = Gate{});
 
 // y pass: `planes` planes; input rows_in rows (first n_in read), output
 // rows_out rows (first n_out written).
 template <typename T>
 hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kxs, int planes,
-                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s);
+                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s,
+                  Gate g = Gate{});
 
 // z pass over `nc` (1 or 3) components; ny = number of ky rows.
 // FUSED (nc = 3) multiplies by Lambda between the forward and inverse
@@ -53,7 +69,7 @@ hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kx
 template <typename T>
 hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
                   int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,
-                  hipStream_t s);
+                  hipStream_t s, Gate g = Gate{});
 
 bool length_supported(int M);
 

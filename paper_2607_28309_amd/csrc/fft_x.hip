@@ -38,9 +38,10 @@ __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_forward(const IO* __r
                                                                   int rows_per_comp, int ncomp, int row_len,
                                                                   int kxs, const cpx<T>* __restrict__ tw_g,
                                                                   const cpx<T>* __restrict__ tw2_g,
-                                                                  const double* __restrict__ pre) {
+                                                                  const double* __restrict__ pre, Gate gate) {
   using C = XCfg<T, M>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
+  if (gate_closed(gate)) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = lds + (M + 1) * NPS;
@@ -88,9 +89,10 @@ template <typename T, typename IO, int M>
 __global__ __launch_bounds__((XCfg<T, M>::BLOCK)) void k_x_inverse(
     const cpx<T>* __restrict__ in, IO* __restrict__ y, const IO* __restrict__ J,
     const double* __restrict__ eps, Epilogue ep, int nrows, int rows_per_comp, int ncomp, int row_len,
-    int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g) {
+    int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g, Gate gate) {
   using C = XCfg<T, M>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
+  if (gate_closed(gate)) return;
   static_assert((M / 2) % TJ == 0, "the kept half of a row is whole columns of the lane layout");
   constexpr int EH = E / 2;
   extern __shared__ unsigned char smem_raw[];
@@ -157,7 +159,8 @@ static int x_blocks(int nrows, int rows_per_comp, int ncomp) {
 // only, spectra precompute: rows of 2M reals).
 template <typename T, typename IO>
 hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
-                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s, const double* pre) {
+                     int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s, const double* pre,
+                     Gate gg) {
   const bool half = 2 * n_in == M;
   if ((!half && n_in != M) || (!half && sizeof(T) != 8) || 2 * n_in > row_len || kxs < M + 1 ||
       (pre && !half))
@@ -169,10 +172,10 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
     const dim3 g(x_blocks<C::NP>(nrows, rows_per_comp, ncomp));                                           \
     if (half)                                                                                             \
       hipLaunchKernelGGL((k_x_forward<T, IO, m, true>), g, dim3(C::BLOCK), C::LDS, s, in, (cpx<T>*)out,    \
-                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, pre); \
+                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, pre, gg); \
     else if constexpr (sizeof(T) == 8 && sizeof(IO) == 8)                                                \
       hipLaunchKernelGGL((k_x_forward<T, IO, m, false>), g, dim3(C::BLOCK), C::LDS, s, in, (cpx<T>*)out,   \
-                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, nullptr); \
+                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, nullptr, gg); \
     return hipGetLastError();                                                                             \
   }
     MOT_FOR_EACH_LEN(X)
@@ -186,7 +189,7 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
 template <typename T, typename IO>
 hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M, int nrows,
                      int rows_per_comp, int ncomp, int row_len, int n_out, int kxs, const void* tw,
-                     const void* tw2, hipStream_t s) {
+                     const void* tw2, hipStream_t s, Gate gg) {
   if (n_out != M || row_len < M || kxs < M + 1) return hipErrorInvalidValue;
   switch (M) {
 #define X(m)                                                                                            \
@@ -194,7 +197,7 @@ hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epil
     using C = XCfg<T, m>;                                                                               \
     const dim3 g(x_blocks<C::NP>(nrows, rows_per_comp, ncomp));                                         \
     hipLaunchKernelGGL((k_x_inverse<T, IO, m>), g, dim3(C::BLOCK), C::LDS, s, (const cpx<T>*)in, y, J, eps, \
-                       ep, nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2); \
+                       ep, nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, gg); \
     return hipGetLastError();                                                                           \
   }
     MOT_FOR_EACH_LEN(X)
@@ -206,9 +209,9 @@ hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epil
 
 #define XINST(T, IO)                                                                                      \
   template hipError_t x_forward<T, IO>(const IO*, void*, int, int, int, int, int, int, int, const void*,    \
-                                       const void*, hipStream_t, const double*);                           \
+                                       const void*, hipStream_t, const double*, Gate);                     \
   template hipError_t x_inverse<T, IO>(const void*, IO*, const IO*, const double*, Epilogue, int, int, int, \
-                                       int, int, int, int, const void*, const void*, hipStream_t);
+                                       int, int, int, int, const void*, const void*, hipStream_t, Gate);
 XINST(float, float)
 XINST(float, double)
 XINST(double, double)

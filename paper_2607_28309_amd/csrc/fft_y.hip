@@ -10,9 +10,11 @@ template <typename T, int M, bool INV, bool HIN, bool HOUT>
 __global__ __launch_bounds__((YCfg<T, M>::BLOCK)) void k_y_pass(const cpx<T>* __restrict__ in,
                                                                cpx<T>* __restrict__ out, int kxn, int kxs,
                                                                int rows_in, int rows_out,
-                                                               const cpx<T>* __restrict__ tw_g, int ntx, int nlog) {
+                                                               const cpx<T>* __restrict__ tw_g, int ntx, int nlog,
+                                                               Gate gate) {
   using C = YCfg<T, M>;
   constexpr int NP = C::NP, NPS = C::NPS;
+  if (gate_closed(gate)) return;
   const int L = xcd_tile(blockIdx.x, nlog);
   if (L >= nlog) return;
   const int tile = L % ntx, plane = L / ntx;
@@ -47,11 +49,11 @@ bool length_supported(int M) {
 
 template <typename T, int M, bool INV, bool HIN, bool HOUT>
 static hipError_t y_launch(const void* in, void* out, int kx, int kxs, int planes, int rows_in, int rows_out,
-                           const void* tw, hipStream_t s) {
+                           const void* tw, hipStream_t s, Gate g) {
   using C = YCfg<T, M>;
   const int ntx = (kx + C::NP - 1) / C::NP, nlog = ntx * planes;
   hipLaunchKernelGGL((k_y_pass<T, M, INV, HIN, HOUT>), dim3(xcd_grid(nlog)), dim3(C::BLOCK), C::LDS, s,
-                     (const cpx<T>*)in, (cpx<T>*)out, kx, kxs, rows_in, rows_out, (const cpx<T>*)tw, ntx, nlog);
+                     (const cpx<T>*)in, (cpx<T>*)out, kx, kxs, rows_in, rows_out, (const cpx<T>*)tw, ntx, nlog, g);
   return hipGetLastError();
 }
 
@@ -59,7 +61,7 @@ static hipError_t y_launch(const void* in, void* out, int kx, int kxs, int plane
 // spectra precompute), both with n_out = M; inverse with n_in = M, n_out = M/2.
 template <typename T>
 hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kxs, int planes,
-                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s) {
+                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s, Gate g) {
   if (n_in > rows_in || n_out > rows_out) return hipErrorInvalidValue;
   const int form = !inverse && 2 * n_in == M && n_out == M   ? 0
                    : !inverse && n_in == M && n_out == M       ? 1
@@ -69,11 +71,11 @@ hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kx
   switch (M) {
 #define X(m)                                                                                     \
   case m:                                                                                        \
-    if (form == 0) return y_launch<T, m, false, true, false>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s); \
+    if (form == 0) return y_launch<T, m, false, true, false>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s, g); \
     if constexpr (sizeof(T) == 8)                                                                \
       if (form == 1)                                                                             \
-        return y_launch<T, m, false, false, false>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s);           \
-    return y_launch<T, m, true, false, true>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s);
+        return y_launch<T, m, false, false, false>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s, g);           \
+    return y_launch<T, m, true, false, true>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s, g);
     MOT_FOR_EACH_LEN(X)
 #undef X
     default:
@@ -82,8 +84,8 @@ hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kx
 }
 
 template hipError_t y_pass<float>(const void*, void*, int, bool, int, int, int, int, int, int, int,
-                                  const void*, hipStream_t);
+                                  const void*, hipStream_t, Gate);
 template hipError_t y_pass<double>(const void*, void*, int, bool, int, int, int, int, int, int, int,
-                                   const void*, hipStream_t);
+                                   const void*, hipStream_t, Gate);
 
 }  // namespace motfft

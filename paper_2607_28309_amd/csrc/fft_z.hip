@@ -10,9 +10,10 @@ namespace motfft {
 template <typename T, int M, int NC, bool INV, bool HIN, bool HOUT>
 __global__ __launch_bounds__((ZCfg<T, M, NC>::BLOCK)) void k_z_pass(
     const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxn, int kxs, int ny, int rows_in, int rows_out,
-    const cpx<T>* __restrict__ tw_g, int ntx, int nlog) {
+    const cpx<T>* __restrict__ tw_g, int ntx, int nlog, Gate gate) {
   using C = ZCfg<T, M, NC>;
   constexpr int W = C::W, NP = C::NP, NPS = C::NPS;
+  if (gate_closed(gate)) return;
   const int L = xcd_tile(blockIdx.x, nlog);
   if (L >= nlog) return;
   const int tile = L % ntx, ky = L / ntx;
@@ -48,10 +49,11 @@ __global__ __launch_bounds__((ZCfg<T, M, NC>::BLOCK)) void k_z_pass(
 template <typename T, int M>
 __global__ __launch_bounds__((ZFCfg<T, M>::BLOCK)) void k_z_fused(
     const cpx<T>* in, cpx<T>* out, int kxn, int kxs, int ny, int rows_in, int rows_out,
-    const T* __restrict__ lam, const cpx<T>* __restrict__ tw_g, int ntx, int nlog) {
+    const T* __restrict__ lam, const cpx<T>* __restrict__ tw_g, int ntx, int nlog, Gate gate) {
   using C = ZFCfg<T, M>;
   constexpr int W = C::W, NP = C::NP, NPS = C::NPS, KZC = M / 2 + 1, BLOCK = C::BLOCK;
   constexpr int NI = W * M, KI = (NI + BLOCK - 1) / BLOCK;
+  if (gate_closed(gate)) return;
   const int L = xcd_tile(blockIdx.x, nlog);
   if (L >= nlog) return;
   const int tile = L % ntx, kyc = L / ntx;
@@ -127,21 +129,21 @@ int z_fused_width(int M, bool f64) {
 
 template <typename T, int M, int NC, bool INV, bool HIN, bool HOUT>
 static hipError_t z_launch(const void* in, void* out, int kx, int kxs, int ny, int rows_in, int rows_out,
-                           const void* tw, hipStream_t s) {
+                           const void* tw, hipStream_t s, Gate g) {
   using C = ZCfg<T, M, NC>;
   const int ntx = (kx + C::W - 1) / C::W, nlog = ntx * ny;
   hipLaunchKernelGGL((k_z_pass<T, M, NC, INV, HIN, HOUT>), dim3(xcd_grid(nlog)), dim3(C::BLOCK), C::LDS, s,
-                     (const cpx<T>*)in, (cpx<T>*)out, kx, kxs, ny, rows_in, rows_out, (const cpx<T>*)tw, ntx, nlog);
+                     (const cpx<T>*)in, (cpx<T>*)out, kx, kxs, ny, rows_in, rows_out, (const cpx<T>*)tw, ntx, nlog, g);
   return hipGetLastError();
 }
 
 template <typename T, int M>
 static hipError_t z_fused_launch(const void* in, void* out, int kx, int kxs, int ny, int rows_in, int rows_out,
-                                 const T* lam, const void* tw, hipStream_t s) {
+                                 const T* lam, const void* tw, hipStream_t s, Gate g) {
   using C = ZFCfg<T, M>;
   const int ntx = (kx + C::W - 1) / C::W, nlog = ntx * (ny / 2 + 1);
   hipLaunchKernelGGL((k_z_fused<T, M>), dim3(xcd_grid(nlog)), dim3(C::BLOCK), C::LDS, s, (const cpx<T>*)in,
-                     (cpx<T>*)out, kx, kxs, ny, rows_in, rows_out, lam, (const cpx<T>*)tw, ntx, nlog);
+                     (cpx<T>*)out, kx, kxs, ny, rows_in, rows_out, lam, (const cpx<T>*)tw, ntx, nlog, g);
   return hipGetLastError();
 }
 
@@ -152,7 +154,7 @@ static hipError_t z_fused_launch(const void* in, void* out, int kx, int kxs, int
 template <typename T>
 hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
                   int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,
-                  hipStream_t s) {
+                  hipStream_t s, Gate g) {
   if (n_in > rows_in || n_out > rows_out) return hipErrorInvalidValue;
   int form = -1;
   if (mode == Z_FWD && nc == 3 && 2 * n_in == M && n_out == M) form = 0;
@@ -163,11 +165,11 @@ hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, in
   switch (M) {
 #define X(m)                                                                                             \
   case m:                                                                                                \
-    if (form == 0) return z_launch<T, m, 3, false, true, false>(in, out, kx, kxs, ny, rows_in, rows_out, tw, s); \
+    if (form == 0) return z_launch<T, m, 3, false, true, false>(in, out, kx, kxs, ny, rows_in, rows_out, tw, s, g); \
     if constexpr (sizeof(T) == 8)                                                                        \
-      if (form == 1) return z_launch<T, m, 1, false, false, false>(in, out, kx, kxs, ny, rows_in, rows_out, tw, s); \
-    if (form == 2) return z_launch<T, m, 3, true, false, true>(in, out, kx, kxs, ny, rows_in, rows_out, tw, s); \
-    return z_fused_launch<T, m>(in, out, kx, kxs, ny, rows_in, rows_out, lam, tw, s);
+      if (form == 1) return z_launch<T, m, 1, false, false, false>(in, out, kx, kxs, ny, rows_in, rows_out, tw, s, g); \
+    if (form == 2) return z_launch<T, m, 3, true, false, true>(in, out, kx, kxs, ny, rows_in, rows_out, tw, s, g); \
+    return z_fused_launch<T, m>(in, out, kx, kxs, ny, rows_in, rows_out, lam, tw, s, g);
     MOT_FOR_EACH_LEN(X)
 #undef X
     default:
@@ -176,8 +178,8 @@ hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, in
 }
 
 template hipError_t z_pass<float>(const void*, void*, int, int, int, int, int, int, int, int, int, int,
-                                  const float*, const void*, hipStream_t);
+                                  const float*, const void*, hipStream_t, Gate);
 template hipError_t z_pass<double>(const void*, void*, int, int, int, int, int, int, int, int, int, int,
-                                   const double*, const void*, hipStream_t);
+                                   const double*, const void*, hipStream_t, Gate);
 
 }  // namespace motfft

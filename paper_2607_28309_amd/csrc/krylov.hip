@@ -48,12 +48,21 @@ __global__ __launch_bounds__(RED_THREADS) void k_dot(const V* __restrict__ a, co
 __device__ void post_op(double* scal, int post) {
   switch (post) {
     case POST_INIT: {  // rho = |r0|^2 (r~ = r0), tau = |r0|, theta = eta = 0
-      scal[S_RHO] = scal[S_B2];
-      scal[S_TAU] = sqrt(scal[S_B2]);
+      const double b2 = scal[S_B2];
+      scal[S_RHO] = b2;
+      scal[S_TAU] = sqrt(b2);
+      scal[S_BNORM] = sqrt(b2);
       scal[S_THETA] = 0.0;
       scal[S_ETA] = 0.0;
       scal[S_FLAG] = 0.0;
       scal[S_DCOEF] = 0.0;
+      if (!isfinite(b2)) {  // nothing to iterate on
+        scal[S_STATUS] = (double)MOT_ENONFINITE;
+        scal[S_DONE] = 1.0;
+      } else if (b2 == 0.0) {  // x = 0 after 0 iterations
+        scal[S_RELRES] = 0.0;
+        scal[S_DONE] = 1.0;
+      }
       break;
     }
     case POST_ALPHA: {  // alpha = rho / sigma; d coefficient theta^2 eta / alpha
@@ -67,6 +76,7 @@ __device__ void post_op(double* scal, int post) {
       const double alpha = rho / sigma;
       scal[S_ALPHA] = alpha;
       scal[S_DCOEF] = scal[S_THETA] * scal[S_THETA] * scal[S_ETA] / alpha;
+      scal[S_NMV] += 1.0;  // the product A u that preceded this reduction
       break;
     }
     case POST_HALF0:
@@ -80,18 +90,52 @@ __device__ void post_op(double* scal, int post) {
       scal[S_TAU] = tau;
       scal[S_ETA] = eta;
       scal[S_DCOEF] = alpha != 0.0 ? theta * theta * eta / alpha : 0.0;
-      if (post == POST_HALF0) scal[S_TAU0] = tau;
+      if (post == POST_HALF0) {
+        scal[S_TAU0] = tau;
+        scal[S_NMV] += 1.0;  // the product A u2 that follows
+      }
       break;
     }
-    case POST_BETA: {  // beta = rho'/rho, rho = rho'
+    case POST_BETA: {  // beta = rho'/rho, rho = rho'; end of an iteration: convergence bound
       const double rn = scal[S_RHONEW], rho = scal[S_RHO];
       if (rho == 0.0) {
         scal[S_FLAG] = 1.0;
         scal[S_BETA] = 0.0;
-        break;
+      } else {
+        scal[S_BETA] = rn / rho;
+        scal[S_RHO] = rn;
       }
-      scal[S_BETA] = rn / rho;
-      scal[S_RHO] = rn;
+      const double it = scal[S_ITER] + 1.0;
+      scal[S_ITER] = it;
+      // quasi-residual bound tau sqrt(2m + 1); its passing, a breakdown or the
+      // last iteration ask for the true residual
+      const double bound = scal[S_TAU] * sqrt(2.0 * it + 1.0);
+      if (!isfinite(bound)) {
+        scal[S_STATUS] = (double)MOT_ENONFINITE;
+        scal[S_DONE] = 1.0;
+      } else if (bound <= scal[S_TOL] * scal[S_BNORM] || scal[S_FLAG] != 0.0 || it >= scal[S_MAXIT]) {
+        scal[S_CHECK] = 1.0;
+      }
+      break;
+    }
+    case POST_RESID: {  // true residual |b - A x|^2 in S_R2
+      const double rel = sqrt(scal[S_R2]) / scal[S_BNORM];
+      scal[S_RELRES] = rel;
+      scal[S_NMV] += 1.0;
+      if (!isfinite(rel)) {
+        scal[S_STATUS] = (double)MOT_ENONFINITE;
+        scal[S_DONE] = 1.0;
+      } else if (rel <= scal[S_TOL]) {
+        scal[S_DONE] = 1.0;
+      } else if (scal[S_FLAG] != 0.0) {
+        scal[S_STATUS] = (double)MOT_EBREAKDOWN;
+        scal[S_DONE] = 1.0;
+      } else if (scal[S_ITER] >= scal[S_MAXIT]) {
+        scal[S_STATUS] = (double)MOT_ENOCONV;
+        scal[S_DONE] = 1.0;
+      } else {
+        scal[S_CHECK] = 0.0;
+      }
       break;
     }
     default:
@@ -100,7 +144,8 @@ __device__ void post_op(double* scal, int post) {
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
-                                                        int slot, int post) {
+                                                        int slot, int post, Gate g) {
+  if (motfft::gate_closed(g)) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partials[i];
   __shared__ double red[RED_THREADS];
@@ -116,9 +161,22 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
   }
 }
 
+__global__ void k_solver_setup(double* scal, double tol, double max_iter) {
+  if (threadIdx.x != 0) return;
+  scal[S_TOL] = tol;
+  scal[S_MAXIT] = max_iter;
+  scal[S_ITER] = 0.0;
+  scal[S_DONE] = 0.0;
+  scal[S_CHECK] = 0.0;
+  scal[S_STATUS] = 0.0;
+  scal[S_RELRES] = 0.0;
+  scal[S_NMV] = 0.0;
+}
+
 template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_sub(const V* __restrict__ a, const V* __restrict__ b,
-                                                     V* __restrict__ out, long long n, double* partials) {
+                                                     V* __restrict__ out, long long n, double* partials, Gate g) {
+  if (motfft::gate_closed(g)) return;
   double acc = 0.0;
   GRID_STRIDE(i, n) {
     const V v = a[i] - b[i];
@@ -186,7 +244,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_half0(V* __restrict__ u2, const
                                                        const V* __restrict__ v, V* __restrict__ w,
                                                        const V* __restrict__ au, V* __restrict__ d,
                                                        const double* __restrict__ scal, long long n,
-                                                       double* partials) {
+                                                       double* partials, Gate g) {
+  if (motfft::gate_closed(g)) return;
   const V alpha = (V)scal[S_ALPHA], dc = (V)scal[S_DCOEF];
   double acc = 0.0;
   GRID_STRIDE(i, n) {
@@ -205,7 +264,8 @@ template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_half1(V* __restrict__ x, V* __restrict__ w,
                                                        const V* __restrict__ au2, V* __restrict__ d,
                                                        const V* __restrict__ u2, const double* __restrict__ scal,
-                                                       long long n, double* partials) {
+                                                       long long n, double* partials, Gate g) {
+  if (motfft::gate_closed(g)) return;
   const V alpha = (V)scal[S_ALPHA], dc = (V)scal[S_DCOEF], eta = (V)scal[S_ETA];
   double acc = 0.0;
   GRID_STRIDE(i, n) {
@@ -224,7 +284,8 @@ template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_rho(V* __restrict__ x, const V* __restrict__ d,
                                                      const V* __restrict__ w, const V* __restrict__ rt,
                                                      const double* __restrict__ scal, long long n,
-                                                     double* partials) {
+                                                     double* partials, Gate g) {
+  if (motfft::gate_closed(g)) return;
   const V eta = (V)scal[S_ETA];
   double acc = 0.0;
   GRID_STRIDE(i, n) {
@@ -236,7 +297,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_rho(V* __restrict__ x, const V*
 
 template <typename V>
 __global__ void k_u(V* __restrict__ u, const V* __restrict__ w, const V* __restrict__ u2,
-                    const double* __restrict__ scal, long long n) {
+                    const double* __restrict__ scal, long long n, Gate g) {
+  if (motfft::gate_closed(g)) return;
   const V beta = (V)scal[S_BETA];
   GRID_STRIDE(i, n) u[i] = w[i] + beta * u2[i];
 }
@@ -246,7 +308,8 @@ template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_v(V* __restrict__ v, const V* __restrict__ au,
                                                    const V* __restrict__ au2, const V* __restrict__ rt,
                                                    const double* __restrict__ scal, long long n,
-                                                   double* partials) {
+                                                   double* partials, Gate g) {
+  if (motfft::gate_closed(g)) return;
   const V beta = (V)scal[S_BETA];
   double acc = 0.0;
   GRID_STRIDE(i, n) {
@@ -260,7 +323,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_v(V* __restrict__ v, const V* _
 // v = au (start); v . rt
 template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_v0(V* __restrict__ v, const V* __restrict__ au,
-                                                    const V* __restrict__ rt, long long n, double* partials) {
+                                                    const V* __restrict__ rt, long long n, double* partials, Gate g) {
+  if (motfft::gate_closed(g)) return;
   double acc = 0.0;
   GRID_STRIDE(i, n) {
     const V vi = au[i];
@@ -282,13 +346,17 @@ template <typename V>
 hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s) {
   LAUNCH(k_dot<V>, a, b, n, partials);
 }
-hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), RB(), 0, s, partials, scal, slot, post);
+hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), RB(), 0, s, partials, scal, slot, post, g);
+  return hipGetLastError();
+}
+hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_solver_setup, dim3(1), dim3(64), 0, s, scal, tol, (double)max_iter);
   return hipGetLastError();
 }
 template <typename V>
-hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials, hipStream_t s) {
-  LAUNCH(k_sub<V>, a, b, out, n, partials);
+hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials, hipStream_t s, Gate g) {
+  LAUNCH(k_sub<V>, a, b, out, n, partials, g);
 }
 hipError_t vec_add64(const double* a, const double* b, double* out, long long n, double* partials, hipStream_t s) {
   LAUNCH(k_add64, a, b, out, n, partials);
@@ -309,48 +377,48 @@ hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, h
 }
 template <typename V>
 hipError_t tfqmr_half0(V* u2, const V* u, const V* v, V* w, const V* au, V* d, const double* scal, long long n,
-                       double* partials, hipStream_t s) {
-  LAUNCH(k_half0<V>, u2, u, v, w, au, d, scal, n, partials);
+                       double* partials, hipStream_t s, Gate g) {
+  LAUNCH(k_half0<V>, u2, u, v, w, au, d, scal, n, partials, g);
 }
 template <typename V>
 hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const double* scal, long long n,
-                       double* partials, hipStream_t s) {
-  LAUNCH(k_half1<V>, x, w, au2, d, u2, scal, n, partials);
+                       double* partials, hipStream_t s, Gate g) {
+  LAUNCH(k_half1<V>, x, w, au2, d, u2, scal, n, partials, g);
 }
 template <typename V>
 hipError_t tfqmr_rho(V* x, const V* d, const V* w, const V* rt, const double* scal, long long n, double* partials,
-                     hipStream_t s) {
-  LAUNCH(k_rho<V>, x, d, w, rt, scal, n, partials);
+                     hipStream_t s, Gate g) {
+  LAUNCH(k_rho<V>, x, d, w, rt, scal, n, partials, g);
 }
 template <typename V>
-hipError_t tfqmr_u(V* u, const V* w, const V* u2, const double* scal, long long n, hipStream_t s) {
-  LAUNCH(k_u<V>, u, w, u2, scal, n);
+hipError_t tfqmr_u(V* u, const V* w, const V* u2, const double* scal, long long n, hipStream_t s, Gate g) {
+  LAUNCH(k_u<V>, u, w, u2, scal, n, g);
 }
 template <typename V>
 hipError_t tfqmr_v(V* v, const V* au, const V* au2, const V* rt, const double* scal, long long n,
-                   double* partials, hipStream_t s) {
-  LAUNCH(k_v<V>, v, au, au2, rt, scal, n, partials);
+                   double* partials, hipStream_t s, Gate g) {
+  LAUNCH(k_v<V>, v, au, au2, rt, scal, n, partials, g);
 }
 template <typename V>
-hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials, hipStream_t s) {
-  LAUNCH(k_v0<V>, v, au, rt, n, partials);
+hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials, hipStream_t s, Gate g) {
+  LAUNCH(k_v0<V>, v, au, rt, n, partials, g);
 }
 
 #define INST(V)                                                                                              \
   template hipError_t dot_partial<V>(const V*, const V*, long long, double*, hipStream_t);                    \
-  template hipError_t vec_sub<V>(const V*, const V*, V*, long long, double*, hipStream_t);                    \
+  template hipError_t vec_sub<V>(const V*, const V*, V*, long long, double*, hipStream_t, Gate);              \
   template hipError_t vec_zero<V>(V*, long long, hipStream_t);                                                \
   template hipError_t tfqmr_init<V>(const V*, V*, V*, V*, V*, V*, long long, hipStream_t);                    \
   template hipError_t tfqmr_half0<V>(V*, const V*, const V*, V*, const V*, V*, const double*, long long,       \
-                                     double*, hipStream_t);                                                   \
+                                     double*, hipStream_t, Gate);                                             \
   template hipError_t tfqmr_half1<V>(V*, V*, const V*, V*, const V*, const double*, long long, double*,        \
-                                     hipStream_t);                                                            \
+                                     hipStream_t, Gate);                                                      \
   template hipError_t tfqmr_rho<V>(V*, const V*, const V*, const V*, const double*, long long, double*,        \
-                                   hipStream_t);                                                              \
-  template hipError_t tfqmr_u<V>(V*, const V*, const V*, const double*, long long, hipStream_t);               \
+                                   hipStream_t, Gate);                                                        \
+  template hipError_t tfqmr_u<V>(V*, const V*, const V*, const double*, long long, hipStream_t, Gate);         \
   template hipError_t tfqmr_v<V>(V*, const V*, const V*, const V*, const double*, long long, double*,          \
-                                 hipStream_t);                                                                \
-  template hipError_t tfqmr_v0<V>(V*, const V*, const V*, long long, double*, hipStream_t);
+                                 hipStream_t, Gate);                                                          \
+  template hipError_t tfqmr_v0<V>(V*, const V*, const V*, long long, double*, hipStream_t, Gate);
 INST(float)
 INST(double)
 #undef INST

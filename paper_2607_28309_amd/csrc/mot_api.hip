@@ -50,10 +50,12 @@ struct mot_ctx {
   float* kf[11];       // FP32 Krylov vectors (FP32 and refined modes)
   double* partials;
   double* scal;
-  double* hscal;       // pinned host mirror
+  double* hscal;       // pinned host mirror: [0] for synchronous reads, [1], [2] for the solver's queue
   hipEvent_t ev[3];
+  hipEvent_t evq[2];   // the solver's queue: scalars of iteration m copied to bank 1 + (m & 1)
   // kernel timing (mot_profile)
   int prof_on, prof_used, prof_cap;
+  int prof_mask;       // kinds timed while profiling is on (bit k = kind k)
   hipEvent_t* prof_ev;
   int* prof_cls;
   double prof_ms[MOT_PROF_NCLASS];
@@ -112,7 +114,7 @@ struct Prof {
   mot_ctx* c;
   int idx = -1;
   Prof(mot_ctx* c_, int kind, bool f64) : c(c_) {
-    if (!c->prof_on) return;
+    if (!c->prof_on || !((c->prof_mask >> kind) & 1)) return;
     if (c->prof_used == c->prof_cap && prof_flush(c) != MOT_OK) return;
     idx = c->prof_used++;
     c->prof_cls[idx] = 2 * kind + (f64 ? 1 : 0);
@@ -244,21 +246,22 @@ namespace {
 // ---------------------------------------------------------------- Green product
 // y = epilogue(J, G J) with spectra `lam` (precision T) through the five passes.
 template <typename T, typename IO>
-int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue ep, const double* pre = nullptr) {
+int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue ep, const double* pre = nullptr,
+                  motfft::Gate g = motfft::Gate{}) {
   const int ti = sizeof(T) == 8 ? 1 : 0;
   hipStream_t s = c->stream;
   const int rows = 3 * c->nz * c->ny;
   const bool d = ti == 1;
   HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
-                                         c->twx[ti], c->tw2x[ti], s, pre)));
+                                         c->twx[ti], c->tw2x[ti], s, pre, g)));
   HTP(K_YF, d, motfft::y_pass<T>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py, c->py,
-                                 c->twy[ti], s));
+                                 c->twy[ti], s, g));
   HTP(K_ZFUSED, d, motfft::z_pass<T>(c->wsB, c->wsB, c->pz, motfft::Z_FUSED, 3, c->kx, c->kxs, c->py, c->nz, c->nz,
-                                     c->nz, c->nz, lam, c->twz[ti], s));
+                                     c->nz, c->nz, lam, c->twz[ti], s, g));
   HTP(K_YI, d, motfft::y_pass<T>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny, c->ny,
-                                 c->twy[ti], s));
+                                 c->twy[ti], s, g));
   HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, J, c->eps, ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
-                                         c->kxs, c->twx[ti], c->tw2x[ti], s)));
+                                         c->kxs, c->twx[ti], c->tw2x[ti], s, g)));
   return MOT_OK;
 }
 
@@ -283,13 +286,13 @@ struct SolveOut {
 // Z0 product in the precision of the vectors: FP64 vectors -> FP64 FFTs,
 // FP32 vectors -> FP32 FFTs.
 // In an adjoint context the solver's operator is Z0^T.
-int apply_z0(mot_ctx* c, const double* in, double* out) {
-  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0T, c->eps);
-  return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0);
+int apply_z0(mot_ctx* c, const double* in, double* out, motfft::Gate g = motfft::Gate{}) {
+  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0T, c->eps, g);
+  return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0, nullptr, g);
 }
-int apply_z0(mot_ctx* c, const float* in, float* out) {
-  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0T, c->eps);
-  return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0);
+int apply_z0(mot_ctx* c, const float* in, float* out, motfft::Gate g = motfft::Gate{}) {
+  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0T, c->eps, g);
+  return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0, nullptr, g);
 }
 
 template <typename V> struct KV;
@@ -301,66 +304,97 @@ template <> struct KV<float> {
 };
 
 // TFQMR for Z0 x = b from x = 0 (b, x: device vectors of type V, distinct from
-// the work vectors).  One host synchronization per iteration (convergence test).
+// the work vectors).  The convergence test runs on the device: the reduction
+// that ends an iteration compares the quasi-residual bound with tol ||b|| and
+// asks for the true residual, whose reduction declares the solve done (or
+// failed).  Every launch of an iteration is gated on those flags, so the host
+// stays one iteration ahead: it enqueues iteration m, then waits only for the
+// scalars of iteration m-1 (copied to pinned memory behind an event); an
+// iteration enqueued after convergence does nothing.
 template <typename V>
 int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) {
   hipStream_t s = c->stream;
   const long long n = c->n3;
   V** v = KV<V>::get(c);
   double* P = c->partials;
+  double* sc = c->scal;
   const bool f64 = sizeof(V) == 8;
+  const motfft::Gate RUN{sc + S_DONE, 1}, CHK{sc + S_DONE, 2};
+  HTP(K_KRY, f64, solver_setup(sc, tol, max_iter, s));
   HTP(K_KRY, f64, dot_partial<V>(b, b, n, P, s));
-  HTP(K_KRY, f64, reduce_post(P, c->scal, S_B2, POST_INIT, s));
-  TRY(reduce_sync(c));
-  const double b2 = c->hscal[S_B2];
-  if (!std::isfinite(b2)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
-  if (b2 == 0.0) {
-    HTP(K_KRY, f64, vec_zero<V>(x, n, s));
-    so->relres = 0.0;
-    return MOT_OK;
-  }
-  const double bnorm = sqrt(b2);
-  auto mv = [&](const V* in, V* out) {
-    so->matvecs++;
-    if (f64) so->matvecs64++;
-    return apply_z0(c, in, out);
-  };
-  HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));
-  TRY(mv(v[V_U], v[V_AU]));
-  HTP(K_KRY, f64, tfqmr_v0<V>(v[V_V], v[V_AU], v[V_RT], n, P, s));
-  HTP(K_KRY, f64, reduce_post(P, c->scal, S_SIGMA, POST_ALPHA, s));
-  for (int it = 1; it <= max_iter; ++it) {
-    so->iters = it;
-    HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], c->scal, n, P, s));
-    HTP(K_KRY, f64, reduce_post(P, c->scal, S_W2, POST_HALF0, s));
-    TRY(mv(v[V_U2], v[V_AU2]));
-    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], c->scal, n, P, s));
-    HTP(K_KRY, f64, reduce_post(P, c->scal, S_W2, POST_HALF1, s));
-    HTP(K_KRY, f64, tfqmr_rho<V>(x, v[V_D], v[V_W], v[V_RT], c->scal, n, P, s));
-    HTP(K_KRY, f64, reduce_post(P, c->scal, S_RHONEW, POST_BETA, s));
-    TRY(reduce_sync(c));
-    const double* h = c->hscal;
-    const bool breakdown = h[S_FLAG] != 0.0;
-    const double bound = h[S_TAU] * sqrt(2.0 * it + 1.0);
-    if (!std::isfinite(bound)) return set_err(c, MOT_ENONFINITE, "TFQMR quasi-residual is not finite%s%d");
-    if (bound <= tol * bnorm || breakdown || it == max_iter) {
-      // true residual with the solver's own operator
-      TRY(mv(x, v[V_TMP]));
-      HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s));
-      HTP(K_KRY, f64, reduce_post(P, c->scal, S_R2, POST_NONE, s));
-      TRY(reduce_sync(c));
-      so->relres = sqrt(c->hscal[S_R2]) / bnorm;
-      if (!std::isfinite(so->relres)) return set_err(c, MOT_ENONFINITE, "TFQMR residual is not finite%s%d");
-      if (so->relres <= tol) return MOT_OK;
-      if (breakdown) return set_err(c, MOT_EBREAKDOWN, "TFQMR breakdown (rho or sigma = 0)%s%d");
-      if (it == max_iter) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
+  HTP(K_KRY, f64, reduce_post(P, sc, S_B2, POST_INIT, s));
+  HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));  // x = 0 also for b = 0
+  TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
+  HTP(K_KRY, f64, tfqmr_v0<V>(v[V_V], v[V_AU], v[V_RT], n, P, s, RUN));
+  HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, s, RUN));
+  const double* h = nullptr;
+  // host-side screen of the bound test, two iterations late: the true
+  // residual is enqueued only once the last known quasi-residual bound is
+  // within a factor 1000 of tol ||b|| (the device gate still decides; tau
+  // can stall for a half step and then drop by orders of magnitude, so the
+  // screen is wide: a check that finds nothing costs a few empty launches, a
+  // missed one a whole iteration)
+  double tau_last = -1.0, tolb = -1.0;
+  for (int it = 1; it <= max_iter + 1; ++it) {
+    HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], sc, n, P, s, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF0, s, RUN));
+    TRY(apply_z0(c, v[V_U2], v[V_AU2], RUN));
+    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], sc, n, P, s, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF1, s, RUN));
+    HTP(K_KRY, f64, tfqmr_rho<V>(x, v[V_D], v[V_W], v[V_RT], sc, n, P, s, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_RHONEW, POST_BETA, s, RUN));
+    // true residual with the solver's own operator, only when asked for
+    bool check = true;
+    if (tau_last > 0.0 && tolb > 0.0 && it < max_iter) check = tau_last * std::sqrt(2.0 * it + 1.0) <= 1e3 * tolb;
+    if (check) {
+      TRY(apply_z0(c, x, v[V_TMP], CHK));
+      HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s, CHK));
+      HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, s, CHK));
     }
-    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], c->scal, n, s));
-    TRY(mv(v[V_U], v[V_AU]));
-    HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], c->scal, n, P, s));
-    HTP(K_KRY, f64, reduce_post(P, c->scal, S_SIGMA, POST_ALPHA, s));
+    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], sc, n, s, RUN));
+    TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
+    HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], sc, n, P, s, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, s, RUN));
+    double* bank = c->hscal + (1 + (it & 1)) * S_NSLOT;
+    HT(hipMemcpyAsync(bank, sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, s));
+    HT(hipEventRecord(c->evq[it & 1], s));
+    if (it >= 2) {
+      HT(hipEventSynchronize(c->evq[(it - 1) & 1]));
+      const double* prev = c->hscal + (1 + ((it - 1) & 1)) * S_NSLOT;
+      if (prev[S_DONE] != 0.0) {
+        HT(hipEventSynchronize(c->evq[it & 1]));
+        h = bank;
+        break;
+      }
+      // a check the device asked for but the host did not enqueue: enqueue it now
+      if (prev[S_CHECK] != 0.0 && !check) {
+        TRY(apply_z0(c, x, v[V_TMP], CHK));
+        HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s, CHK));
+        HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, s, CHK));
+      }
+      tau_last = prev[S_TAU];
+      tolb = prev[S_TOL] * prev[S_BNORM];
+    }
+    if (it == max_iter + 1) {
+      HT(hipEventSynchronize(c->evq[it & 1]));
+      h = bank;
+    }
   }
-  return set_err(c, MOT_ENOCONV, "TFQMR did not converge (max_iter < 1)%s%d");
+  if (!h || h[S_DONE] == 0.0) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
+  so->iters = (int)h[S_ITER];
+  so->matvecs += (int)h[S_NMV];
+  if (f64) so->matvecs64 += (int)h[S_NMV];
+  so->relres = h[S_RELRES];
+  switch ((int)h[S_STATUS]) {
+    case MOT_OK:
+      return MOT_OK;
+    case MOT_ENONFINITE:
+      return set_err(c, MOT_ENONFINITE, "TFQMR: right-hand side or residual is not finite%s%d");
+    case MOT_EBREAKDOWN:
+      return set_err(c, MOT_EBREAKDOWN, "TFQMR breakdown (rho or sigma = 0)%s%d");
+    default:
+      return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
+  }
 }
 
 // Solve Z0 x = b (FP64 b, x) in the context precision.
@@ -570,6 +604,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   mot_ctx* c = new (std::nothrow) mot_ctx();
   if (!c) return MOT_ENOMEM;
   memset(c, 0, sizeof(*c));
+  c->prof_mask = (1 << (MOT_PROF_NCLASS / 2)) - 1;
   c->grid = *grid;
   c->nx = grid->nx;
   c->ny = grid->ny;
@@ -623,12 +658,14 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
       if ((rc = dmalloc(c, (void**)&c->kf[i], sizeof(float) * c->n3)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * RED_BLOCKS)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->scal, sizeof(double) * S_NSLOT)) != MOT_OK) return fail(rc);
-  if (hipHostMalloc((void**)&c->hscal, sizeof(double) * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 3 * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
     c->hscal = nullptr;
     return fail(MOT_ENOMEM);
   }
   for (int i = 0; i < 3; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) return fail(MOT_EHIP);
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&c->evq[i], hipEventDisableTiming) != hipSuccess) return fail(MOT_EHIP);
   if ((rc = mot_reset(c)) != MOT_OK) return fail(rc);
   if ((rc = zero_bytes(c, c->wsA, wsA)) != MOT_OK) return fail(rc);
   if ((rc = zero_bytes(c, c->wsB, wsB)) != MOT_OK) return fail(rc);
@@ -655,6 +692,8 @@ int mot_destroy(mot_ctx* c) {
   }
   for (int i = 0; i < 3; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 2; ++i)
+    if (c->evq[i]) (void)hipEventDestroy(c->evq[i]);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->prof_ev) {
     for (int i = 0; i < 2 * c->prof_cap; ++i) (void)hipEventDestroy(c->prof_ev[i]);
@@ -842,6 +881,12 @@ int mot_profile(mot_ctx* c, int32_t enable) {
   }
   if (!enable) TRY(prof_flush(c));
   c->prof_on = enable ? 1 : 0;
+  return MOT_OK;
+}
+
+int mot_profile_kinds(mot_ctx* c, int32_t kind_mask) {
+  if (!c || kind_mask < 0) return MOT_EINVAL;
+  c->prof_mask = kind_mask;
   return MOT_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/mot_jvie.h"
+#include "fft_passes.h"
 
 namespace motimpl {
 
@@ -27,8 +28,20 @@ enum Slot {
   S_R2,
   S_TAU0,
   S_X2,
+  // device-side convergence state of a solve (S_CHECK must follow S_DONE:
+  // the launch gates read the pair)
+  S_DONE,
+  S_CHECK,
+  S_ITER,
+  S_MAXIT,
+  S_TOL,
+  S_BNORM,
+  S_STATUS,
+  S_RELRES,
+  S_NMV,
   S_NSLOT
 };
+static_assert(S_CHECK == S_DONE + 1, "gates read done and check as a pair");
 
 constexpr int RED_BLOCKS = 1024;   // fixed partial count: deterministic reductions
 constexpr int RED_THREADS = 256;
@@ -44,12 +57,15 @@ hipError_t launch_compress(const void* spec, double* lam64, float* lam32, double
                            int ny, int nz, int kxs, double scale, int w64, int w32, hipStream_t s);
 
 // ---- krylov.hip (vectors of length n, element type V = float or double)
+using motfft::Gate;
 // Scalar recurrence applied by the reduction that produced scal[slot].
-enum Post { POST_NONE = 0, POST_INIT, POST_ALPHA, POST_HALF0, POST_HALF1, POST_BETA };
-hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s);
+enum Post { POST_NONE = 0, POST_INIT, POST_ALPHA, POST_HALF0, POST_HALF1, POST_BETA, POST_RESID };
+hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g = Gate{});
+// Start of a solve: tol, max_iter and the convergence state (iteration 0, not done).
+hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s);
 template <typename V> hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s);
 template <typename V> hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials,
-                                         hipStream_t s);  // out = a - b, partials of |out|^2
+                                         hipStream_t s, Gate g = Gate{});  // out = a - b, partials of |out|^2
 template <typename V> hipError_t vec_zero(V* a, long long n, hipStream_t s);
 hipError_t vec_add64(const double* a, const double* b, double* out, long long n, double* partials,
                      hipStream_t s);  // out = a + b, partials of |out|^2
@@ -59,17 +75,18 @@ hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s);
 hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s);
 template <typename V> hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, hipStream_t s);
 template <typename V> hipError_t tfqmr_half0(V* u2, const V* u, const V* v, V* w, const V* au, V* d,
-                                             const double* scal, long long n, double* partials, hipStream_t s);
+                                             const double* scal, long long n, double* partials, hipStream_t s,
+                                             Gate g);
 template <typename V> hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const double* scal,
-                                             long long n, double* partials, hipStream_t s);
+                                             long long n, double* partials, hipStream_t s, Gate g);
 template <typename V> hipError_t tfqmr_rho(V* x, const V* d, const V* w, const V* rt, const double* scal,
-                                           long long n, double* partials, hipStream_t s);
+                                           long long n, double* partials, hipStream_t s, Gate g);
 template <typename V> hipError_t tfqmr_u(V* u, const V* w, const V* u2, const double* scal, long long n,
-                                         hipStream_t s);
+                                         hipStream_t s, Gate g);
 template <typename V> hipError_t tfqmr_v(V* v, const V* au, const V* au2, const V* rt, const double* scal,
-                                         long long n, double* partials, hipStream_t s);
+                                         long long n, double* partials, hipStream_t s, Gate g);
 template <typename V> hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials,
-                                          hipStream_t s);
+                                          hipStream_t s, Gate g);
 
 // ---- history.hip: history multiply-accumulate (ring slot t mod nl holds J^_t)
 // out = init + sum_{j=1..nrec} Lambda_j J^_{n+1-j}   (init may be null)

@@ -23,7 +23,7 @@ EXPORTS = (
     "mot_excitation", "mot_step", "mot_reset", "mot_green_table", "mot_nlags", "mot_zk_nnz",
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
-    "mot_farfield_adjoint", "mot_adjoint_gradient",
+    "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds",
 )
 PROF_NCLASS = 22
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
@@ -79,6 +79,7 @@ def _load():
         "mot_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64), i32]),
         "mot_last_error": (ctypes.c_char_p, [vp]),
         "mot_set_adjoint": (ctypes.c_int, [vp, i32]),
+        "mot_profile_kinds": (ctypes.c_int, [vp, i32]),
         "z0t_matvec": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "mot_history_gfield": (ctypes.c_int, [vp, vp]),
         "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
@@ -264,6 +265,11 @@ class Context:
 
     def profile(self, enable=True):
         self._check(LIB.mot_profile(self.h, 1 if enable else 0), "mot_profile")
+
+    def profile_kinds(self, kinds=None):
+        """Time only the given kinds (names of PROF_KINDS); None = all."""
+        mask = (1 << len(PROF_KINDS)) - 1 if kinds is None else sum(1 << PROF_KINDS.index(k) for k in kinds)
+        self._check(LIB.mot_profile_kinds(self.h, int(mask)), "mot_profile_kinds")
 
     def profile_read(self):
         """{(kind, 'f32'|'f64'): (ms, launches)} accumulated since the last read."""
