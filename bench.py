@@ -6,10 +6,12 @@ products with FP64 Krylov vectors and FP64 iterative refinement, TFQMR
 tolerance 1e-6.  A "step" is one MOT step (Eq. 3): excitation, history
 right-hand side, the Z0 solve and the history update.
 
-Timed region: K steps after W warm-up steps, inputs resident in HBM; the
-march starts at step ell with zero currents before it, so the history ring
-counts as full and every timed step multiplies all ell lags.  Prints one JSON
-line.
+Timed region: K steps after W warm-up steps and 4 breakdown steps, inputs
+resident in HBM; the march starts at step ell with zero currents before it,
+so the history ring counts as full and every timed step multiplies all ell
+lags.  The breakdown steps (one history block, untimed) time every kernel and
+name the dominant one; inside the timed region only that kernel carries HIP
+timing events.  Prints one JSON line.
 """
 
 import argparse
@@ -24,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ROOFLINE_KINDS = ("history_mac", "z_fused", "y_forward", "y_inverse")
+BREAKDOWN_STEPS = 4
 
 
 def log(msg):
@@ -108,19 +111,19 @@ def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
     einc = torch.empty(3 * N, dtype=torch.float64, device="cuda")
     err_num, ref_max, st64 = 0.0, 0.0, []
     t = None
+    k = min(args.steps, args.f64_steps)
     for s in range(n_keep):
-        if s == args.warmup:
+        if s == n_keep - k:
             torch.cuda.synchronize()
             t = time.perf_counter()
         c.excitation(pulse, (args.start_step + s) * L, einc)
         st = c.step(einc, J64, tol=args.tol, stats=True)[1]
-        if s >= args.warmup:
+        if s >= n_keep - k:
             st64.append(st)
         err_num = max(err_num, float(torch.linalg.vector_norm(Js[s] - J64)))
         ref_max = max(ref_max, float(torch.linalg.vector_norm(J64)))
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    k = n_keep - args.warmup
     c.close()
     res = {"mot_steps_per_s_f64": k / el, "ms_per_step_f64": 1e3 * el / k,
            "iters_per_step_f64": sum(x["iters"] for x in st64) / k,
@@ -177,6 +180,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
+    ap.add_argument("--graphs", action="store_true", help="replay TFQMR iterations from HIP graphs")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="no timing events in the timed region (the roofline then uses the breakdown steps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy kernel three times "
                          "(reference for the HBM traffic counters) and exit")
@@ -221,8 +227,11 @@ def main():
     p = W.pulse(w.ppw)
     L = w.alpha / math.sqrt(3.0)
     einc = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    # step sequence: warm-up, breakdown (untimed, every kernel timed), timed region
+    nbd = BREAKDOWN_STEPS
+    first_timed = args.warmup + nbd
     # one output vector per step, so that the currents can be compared with an FP64 march afterwards
-    n_keep = args.warmup + min(args.steps, args.f64_steps)
+    n_keep = first_timed + min(args.steps, args.f64_steps)
     Js = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(n_keep)]
     J_spare = torch.empty(3 * N, dtype=torch.float64, device="cuda")
 
@@ -233,28 +242,37 @@ def main():
     for s in range(args.warmup):
         st = one_step(ctx, s)
         log(f"warm-up step {s}: {st['iters']} iterations, relres {st['relres']:.2e}")
-    # inside the timed region only the roofline candidates carry timing events
-    ctx.profile_kinds(ROOFLINE_KINDS)
+    # breakdown over one history block (B = 4 steps for an FP32 ring): every
+    # kernel timed; it names the dominant single kernel
+    ctx.profile_kinds(None)
     ctx.profile(True)
+    ctx.profile_read()
+    for s in range(nbd):
+        one_step(ctx, args.warmup + s)
+    breakdown = ctx.profile_read()
+    ctx.profile(False)
+    dom = max(((k, pr, ms, cnt) for (k, pr), (ms, cnt) in breakdown.items() if k in ROOFLINE_KINDS),
+              key=lambda r: r[2])
+    log(f"dominant kernel over {nbd} steps: {dom[0]}.{dom[1]} ({dom[2] / nbd:.2f} ms/step)")
+    if args.graphs:
+        ctx.set_graphs(True)
+    # inside the timed region only the dominant kernel carries timing events
+    ctx.profile_kinds([dom[0]])
+    ctx.profile(not args.no_kernel_timing)
     ctx.profile_read()
     torch.cuda.synchronize()
     t = time.perf_counter()
     stats = []
     for s in range(args.steps):
-        stats.append(one_step(ctx, args.warmup + s))
+        stats.append(one_step(ctx, first_timed + s))
         log(f"step {s}: {stats[-1]['iters']} it, {stats[-1]['matvecs']} mv "
             f"({stats[-1]['matvecs_f64']} f64), relres {stats[-1]['relres']:.2e}, "
             f"lhs {stats[-1]['ms_lhs']:.1f} ms, rhs {stats[-1]['ms_rhs']:.1f} ms")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     prof = ctx.profile_read()
-    ms_per_step = 1e3 * elapsed / args.steps
-    # breakdown of every kind over two more (untimed) steps
-    ctx.profile_kinds(None)
-    for s in range(2):
-        one_step(ctx, args.warmup + args.steps + s)
-    breakdown = ctx.profile_read()
     ctx.profile(False)
+    ms_per_step = 1e3 * elapsed / args.steps
 
     # Z0 product throughput (FP32 and FP64): one event pair per product on the
     # context's stream (torch's current stream), median over the repetitions
@@ -277,18 +295,29 @@ def main():
         log(f"z0_matvec {dt_name}: median {ms:.3f} ms over {reps}")
         del Jm, ym
 
-    # roofline of the kernel with the largest share of the timed region among
-    # the passes whose launches are all the same kernel (same precision class)
+    # roofline of the dominant kernel (the largest share of a history block
+    # among the passes whose launches are all the same kernel), timed live in
+    # the timed region
     ring_t = 8 if args.precision == "f64" else 4
     kernels = {}
     for (kind, prec), (ms, cnt) in breakdown.items():
-        kernels[f"{kind}.{prec}"] = {"ms_per_step": round(ms / 2, 3), "launches_per_step": cnt / 2,
-                                     "ms_avg": round(ms / cnt, 4)}
-    best = None
-    for (kind, prec), (ms, cnt) in prof.items():
-        if kind in ROOFLINE_KINDS and (best is None or ms > best[2]):
-            best = (kind, prec, ms, cnt)
-    kind, prec, ms, cnt = best
+        # enqueued launches include those behind a closed convergence gate
+        kernels[f"{kind}.{prec}"] = {"ms_per_step": round(ms / nbd, 3), "enqueued_per_step": cnt / nbd}
+    if args.no_kernel_timing:
+        kind, prec, ms, cnt = dom
+        steps_counted, st_counted = nbd, None
+    else:
+        (kind, prec), (ms, cnt) = max(((k, v) for k, v in prof.items() if k[0] == dom[0]), key=lambda r: r[1][0])
+        steps_counted, st_counted = args.steps, stats
+    # Launches of the product passes behind a closed convergence gate end at
+    # once; the device counts the products that ran (one launch of each pass
+    # each), so the average is the class's whole time over those.
+    if st_counted is not None and kind in ("z_fused", "y_forward", "y_inverse"):
+        ran = sum(x["matvecs_f64"] if prec == "f64" else x["matvecs"] - x["matvecs_f64"] for x in st_counted)
+        if kind != "z_fused":
+            ran += steps_counted  # the history update's pass (never gated)
+        if 0 < ran <= cnt:
+            cnt = ran
     tb = 8 if prec == "f64" else 4
     if kind == "history_mac":
         tb = ring_t

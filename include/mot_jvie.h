@@ -164,6 +164,13 @@ int mot_excitation(mot_ctx* ctx, const mot_pulse* pulse, double t, double* out);
  * MOT_EBREAKDOWN, MOT_ENONFINITE, MOT_ESTATE, MOT_EHIP. */
 int mot_step(mot_ctx* ctx, const double* einc, double* J_n, double tol, int32_t max_iter, mot_stats* stats);
 
+/* on = 1: each TFQMR iteration of mot_step is replayed from a HIP graph
+ * (captured on first use, per vector precision, operator and whether it
+ * carries the true-residual check; the capture uses a stream of the
+ * context's own, the replay the context's stream).  Timing (mot_profile)
+ * uses the launch-by-launch path.  Errors: MOT_EINVAL. */
+int mot_set_graphs(mot_ctx* ctx, int32_t on);
+
 /* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
 int mot_reset(mot_ctx* ctx);
 

@@ -53,6 +53,10 @@ struct mot_ctx {
   double* hscal;       // pinned host mirror: [0] for synchronous reads, [1], [2] for the solver's queue
   hipEvent_t ev[3];
   hipEvent_t evq[2];   // the solver's queue: scalars of iteration m copied to bank 1 + (m & 1)
+  // TFQMR iterations as graphs: [FP64 vectors][adjoint][with residual check]
+  int use_graphs;
+  hipStream_t cap_stream;   // capture only; graphs are launched on `stream`
+  hipGraphExec_t iter_graph[2][2][2];
   // kernel timing (mot_profile)
   int prof_on, prof_used, prof_cap;
   int prof_mask;       // kinds timed while profiling is on (bit k = kind k)
@@ -327,6 +331,59 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
   TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
   HTP(K_KRY, f64, tfqmr_v0<V>(v[V_V], v[V_AU], v[V_RT], n, P, s, RUN));
   HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, s, RUN));
+  // one iteration's launches on the context stream (gated; see above)
+  auto enqueue_iter = [&](bool check) -> int {
+    hipStream_t st = c->stream;
+    HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], sc, n, P, st, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF0, st, RUN));
+    TRY(apply_z0(c, v[V_U2], v[V_AU2], RUN));
+    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], sc, n, P, st, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF1, st, RUN));
+    HTP(K_KRY, f64, tfqmr_rho<V>(x, v[V_D], v[V_W], v[V_RT], sc, n, P, st, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_RHONEW, POST_BETA, st, RUN));
+    // true residual with the solver's own operator, only when asked for
+    if (check) {
+      TRY(apply_z0(c, x, v[V_TMP], CHK));
+      HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, st, CHK));
+      HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, st, CHK));
+    }
+    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], sc, n, st, RUN));
+    TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
+    HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], sc, n, P, st, RUN));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, st, RUN));
+    return MOT_OK;
+  };
+  // graph mode: the same launches captured once per (precision, operator,
+  // check) on the capture stream and replayed on the context stream; b and x
+  // are the context's own vectors, so the captured arguments stay valid
+  const bool graphs = c->use_graphs && !c->prof_on;
+  auto launch_iter = [&](bool check) -> int {
+    if (!graphs) return enqueue_iter(check);
+    hipGraphExec_t& ex = c->iter_graph[f64 ? 1 : 0][c->adjoint ? 1 : 0][check ? 1 : 0];
+    if (!ex) {
+      if (!c->cap_stream) HT(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipStream_t saved = c->stream;
+      c->stream = c->cap_stream;
+      HT(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+      const int rc = enqueue_iter(check);
+      hipGraph_t gr = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
+      c->stream = saved;
+      if (rc != MOT_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      HT(ec);
+      const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (ei != hipSuccess) {
+        ex = nullptr;
+        HT(ei);
+      }
+    }
+    HT(hipGraphLaunch(ex, c->stream));
+    return MOT_OK;
+  };
   const double* h = nullptr;
   // host-side screen of the bound test, two iterations late: the true
   // residual is enqueued only once the last known quasi-residual bound is
@@ -336,25 +393,9 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
   // missed one a whole iteration)
   double tau_last = -1.0, tolb = -1.0;
   for (int it = 1; it <= max_iter + 1; ++it) {
-    HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], sc, n, P, s, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF0, s, RUN));
-    TRY(apply_z0(c, v[V_U2], v[V_AU2], RUN));
-    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], sc, n, P, s, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF1, s, RUN));
-    HTP(K_KRY, f64, tfqmr_rho<V>(x, v[V_D], v[V_W], v[V_RT], sc, n, P, s, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_RHONEW, POST_BETA, s, RUN));
-    // true residual with the solver's own operator, only when asked for
     bool check = true;
     if (tau_last > 0.0 && tolb > 0.0 && it < max_iter) check = tau_last * std::sqrt(2.0 * it + 1.0) <= 1e3 * tolb;
-    if (check) {
-      TRY(apply_z0(c, x, v[V_TMP], CHK));
-      HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s, CHK));
-      HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, s, CHK));
-    }
-    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], sc, n, s, RUN));
-    TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
-    HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], sc, n, P, s, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, s, RUN));
+    TRY(launch_iter(check));
     double* bank = c->hscal + (1 + (it & 1)) * S_NSLOT;
     HT(hipMemcpyAsync(bank, sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, s));
     HT(hipEventRecord(c->evq[it & 1], s));
@@ -694,6 +735,11 @@ int mot_destroy(mot_ctx* c) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (int i = 0; i < 2; ++i)
     if (c->evq[i]) (void)hipEventDestroy(c->evq[i]);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < 2; ++k)
+        if (c->iter_graph[a][b][k]) (void)hipGraphExecDestroy(c->iter_graph[a][b][k]);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->prof_ev) {
     for (int i = 0; i < 2 * c->prof_cap; ++i) (void)hipEventDestroy(c->prof_ev[i]);
@@ -947,6 +993,12 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
     st->ms_rhs = bms;
   }
   return rc;
+}
+
+int mot_set_graphs(mot_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
+  c->use_graphs = on;
+  return MOT_OK;
 }
 
 int mot_set_adjoint(mot_ctx* c, int32_t on) {

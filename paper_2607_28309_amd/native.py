@@ -23,7 +23,7 @@ EXPORTS = (
     "mot_excitation", "mot_step", "mot_reset", "mot_green_table", "mot_nlags", "mot_zk_nnz",
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
-    "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds",
+    "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs",
 )
 PROF_NCLASS = 22
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
@@ -80,6 +80,7 @@ def _load():
         "mot_last_error": (ctypes.c_char_p, [vp]),
         "mot_set_adjoint": (ctypes.c_int, [vp, i32]),
         "mot_profile_kinds": (ctypes.c_int, [vp, i32]),
+        "mot_set_graphs": (ctypes.c_int, [vp, i32]),
         "z0t_matvec": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "mot_history_gfield": (ctypes.c_int, [vp, vp]),
         "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
@@ -208,6 +209,9 @@ class Context:
         p = make_pulse(pulse)
         self._check(LIB.mot_excitation(self.h, ctypes.byref(p), float(t), _ptr(out, torch.float64, 3 * self.N)),
                     "mot_excitation")
+
+    def set_graphs(self, on=True):
+        self._check(LIB.mot_set_graphs(self.h, 1 if on else 0), "mot_set_graphs")
 
     def set_adjoint(self, on=True):
         self._check(LIB.mot_set_adjoint(self.h, 1 if on else 0), "mot_set_adjoint")
