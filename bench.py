@@ -134,6 +134,68 @@ def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
     return res
 
 
+def batch_leg(args, log_fn):
+    """Batch of 32 independent cubes (sides 24..80, alpha = 4, each with its own
+    incidence), every context on its own stream: batch steps/s with the
+    library's thread pool (mot_step_batch) and one context after another."""
+    import torch
+    import workloads as W
+    from paper_2607_28309_amd import native
+    sc = W.cube_batch()
+    alpha = W.BATCH_ALPHA
+    L = alpha / math.sqrt(3.0)
+    t0 = time.perf_counter()
+    ctxs = []
+    for s_ in sc:
+        c = native.Context(*s_.n, alpha=alpha, precision=args.precision, stream=torch.cuda.Stream())
+        c.set_material(torch.from_numpy(s_.eps.ravel()).cuda())
+        c.build_green_spectra()
+        c.reset()
+        c.set_step(c.info()["nlags"])
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    pulses = [W.pulse(W.BATCH_PPW, k_hat=s_.k_hat, e_hat=s_.e_hat) for s_ in sc]
+    E = [torch.empty(3 * c.N, dtype=torch.float64, device="cuda") for c in ctxs]
+    J = [torch.empty_like(e) for e in E]
+    start = 100
+
+    def excite(k):
+        for c, p_, e in zip(ctxs, pulses, E):
+            c.excitation(p_, (start + k) * L, e)
+
+    for k in range(2):
+        excite(k)
+        native.step_batch(ctxs, E, J, tol=args.tol)
+    torch.cuda.synchronize()
+    K = args.batch_steps
+    t = time.perf_counter()
+    its = 0
+    for k in range(K):
+        excite(2 + k)
+        st = native.step_batch(ctxs, E, J, tol=args.tol)[1]
+        its += sum(x["iters"] for x in st)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    t = time.perf_counter()
+    for k in range(K):
+        excite(2 + K + k)
+        for c, e, j in zip(ctxs, E, J):
+            c.step(e, j, tol=args.tol, stats=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    res = {"workload": "cubes32_sides24to80_a4", "scatterers": len(ctxs),
+           "unknowns": sum(3 * c.N for c in ctxs), "nlags": [c.info()["nlags"] for c in ctxs],
+           "precision": args.precision, "steps": K, "setup_s": setup,
+           "batch_steps_per_s": K / tb, "sequential_steps_per_s": K / ts, "speedup": ts / tb,
+           "iters_per_scatterer_step": its / (K * len(ctxs))}
+    log_fn(f"batch of {len(ctxs)} cubes: {1e3 * tb / K:.1f} ms per batch step with the thread pool, "
+           f"{1e3 * ts / K:.1f} ms one after another")
+    for c in ctxs:
+        c.close()
+    return res
+
+
 def sources_sha256(paths):
     """sha256 over the concatenated contents of the given repository files."""
     import hashlib
@@ -181,6 +243,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
     ap.add_argument("--graphs", action="store_true", help="replay TFQMR iterations from HIP graphs")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time a batch of 32 independent cubes (sides 24..80, alpha 4) stepped together")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no timing events in the timed region (the roofline then uses the breakdown steps)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -364,6 +429,8 @@ def main():
     del ctx
     if args.f64_steps > 0:
         out.update(f64_march(args, w, eps, p, L, Js, n_keep, log))
+    if args.batch:
+        out["batch"] = batch_leg(args, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, eps, out["matvecs_per_step"], nl, log)
     print(json.dumps(out), flush=True)

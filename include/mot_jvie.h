@@ -171,6 +171,16 @@ int mot_step(mot_ctx* ctx, const double* einc, double* J_n, double tol, int32_t 
  * uses the launch-by-launch path.  Errors: MOT_EINVAL. */
 int mot_set_graphs(mot_ctx* ctx, int32_t on);
 
+/* Batch of independent scatterers: one MOT step (as mot_step) of each of the
+ * `count` contexts, run by `nthreads` host threads so that contexts created
+ * on different streams overlap on the GPU.  einc[i], J_n[i]: the i-th
+ * context's vectors; stats (may be NULL) and status (required) are arrays of
+ * count.  Every context must be distinct (a context is not thread-safe).
+ * Returns MOT_OK or the first non-OK status; status[i] holds each one.
+ * Errors: MOT_EINVAL, and those of mot_step. */
+int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* einc, double* const* J_n, double tol,
+                   int32_t max_iter, mot_stats* stats, int32_t* status, int32_t nthreads);
+
 /* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
 int mot_reset(mot_ctx* ctx);
 

@@ -3,10 +3,12 @@
 // device-resident TFQMR solve.  See include/mot_jvie.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "fft_core.h"
@@ -470,13 +472,20 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
       const double* r = b;  // residual of x = 0
       double rnorm = bnorm;
       const int max_ref = 12;
+      // an FP32 TFQMR can stagnate (its recurrence residual keeps falling while
+      // the true one stalls): each inner solve gets at most kInnerCap
+      // iterations, after which its iterate is kept and the solve restarts
+      // from the FP64 residual
+      constexpr int kInnerCap = 40;
       while (true) {
         ++refinements;
         double tin = 0.5 * tol * bnorm / rnorm;
         if (tin < 2e-6) tin = 2e-6;
         SolveOut inner;
         HTP(K_KRY, false, vec_d2f(r, c->kf[V_B], n, P, s));
-        int irc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tin, max_iter, &inner);
+        const int left = max_iter - so.iters;
+        const int cap = left < kInnerCap ? (left > 1 ? left : 1) : kInnerCap;
+        int irc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tin, cap, &inner);
         so.iters += inner.iters;
         so.matvecs += inner.matvecs;
         if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
@@ -993,6 +1002,30 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
     st->ms_rhs = bms;
   }
   return rc;
+}
+
+int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* einc, double* const* J_n, double tol,
+                   int32_t max_iter, mot_stats* stats, int32_t* status, int32_t nthreads) {
+  if (!ctxs || !einc || !J_n || !status || count < 1 || nthreads < 1) return MOT_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return MOT_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return MOT_EINVAL;  // a context is not thread-safe
+  }
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1))
+      status[i] = mot_step(ctxs[i], einc[i], J_n[i], tol, max_iter, stats ? &stats[i] : nullptr);
+  };
+  const int nt = nthreads < count ? nthreads : count;
+  std::vector<std::thread> pool;
+  pool.reserve(nt > 1 ? nt - 1 : 0);
+  for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < count; ++i)
+    if (status[i] != MOT_OK) return status[i];
+  return MOT_OK;
 }
 
 int mot_set_graphs(mot_ctx* c, int32_t on) {

@@ -23,7 +23,7 @@ EXPORTS = (
     "mot_excitation", "mot_step", "mot_reset", "mot_green_table", "mot_nlags", "mot_zk_nnz",
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
-    "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs",
+    "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
 )
 PROF_NCLASS = 22
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
@@ -81,6 +81,8 @@ def _load():
         "mot_set_adjoint": (ctypes.c_int, [vp, i32]),
         "mot_profile_kinds": (ctypes.c_int, [vp, i32]),
         "mot_set_graphs": (ctypes.c_int, [vp, i32]),
+        "mot_step_batch": (ctypes.c_int, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32,
+                                          ctypes.POINTER(MotStats), ctypes.POINTER(i32), i32]),
         "z0t_matvec": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "mot_history_gfield": (ctypes.c_int, [vp, vp]),
         "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
@@ -95,6 +97,27 @@ def _load():
 
 
 LIB = _load()
+
+
+def step_batch(contexts, eincs, Js, tol=1e-6, max_iter=1000, threads=None, allow=()):
+    """One MOT step of every context (each on its own stream) by a pool of host
+    threads inside the library; returns (statuses, stats dicts)."""
+    import torch
+    n = len(contexts)
+    if not (len(eincs) == len(Js) == n) or n == 0:
+        raise ValueError("one excitation and one current vector per context")
+    ctxs = (ctypes.c_void_p * n)(*[c.h for c in contexts])
+    e = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64, 3 * c.N) for x, c in zip(eincs, contexts)])
+    j = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64, 3 * c.N) for x, c in zip(Js, contexts)])
+    st = (MotStats * n)()
+    status = (ctypes.c_int32 * n)()
+    rc = LIB.mot_step_batch(ctxs, n, e, j, float(tol), int(max_iter), st, status, int(threads or n))
+    if rc != MOT_OK and rc not in allow:
+        bad = [i for i in range(n) if status[i] != MOT_OK and status[i] not in allow]
+        if bad:
+            i = bad[0]
+            raise MotError(status[i], f"mot_step_batch, context {i}: {LIB.mot_last_error(contexts[i].h).decode()}")
+    return list(status), [s.as_dict() for s in st]
 
 
 class MotError(RuntimeError):

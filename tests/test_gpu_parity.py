@@ -352,3 +352,36 @@ def test_graph_replay_matches_stream_launches(gpu_lib, prec):
         st = [c.step(e, Jc, tol=1e-6)[1] for c, Jc in zip(cs, J)]
         assert st[0]["iters"] == st[1]["iters"]
         assert torch.equal(J[0], J[1])
+
+
+def test_step_batch_matches_single_steps(gpu_lib):
+    # contexts of uneven grids on their own streams, stepped together by the
+    # library's thread pool, give the currents of one-by-one steps, bit for bit
+    import torch
+    shapes = [(8, 8, 8), (12, 12, 12), (16, 16, 16), (8, 12, 16)]
+    rng = np.random.default_rng(7)
+    eps = [rng.uniform(1.5, 6.0, size=n[::-1]) for n in shapes]
+    pulses = [W.pulse(20, k_hat=(0.0, 0.0, 1.0), e_hat=(1.0, 0.0, 0.0)),
+              W.pulse(20, k_hat=(1.0, 0.0, 0.0), e_hat=(0.0, 1.0, 0.0)),
+              W.pulse(20, k_hat=(0.0, 1.0, 0.0), e_hat=(0.0, 0.0, 1.0)),
+              W.pulse(20, k_hat=(0.6, 0.0, 0.8), e_hat=(0.0, 1.0, 0.0))]
+    alpha = 4
+    batch = [_ctx(gpu_lib, n, alpha, "f32_refined", eps=e, stream=torch.cuda.Stream()) for n, e in zip(shapes, eps)]
+    single = [_ctx(gpu_lib, n, alpha, "f32_refined", eps=e) for n, e in zip(shapes, eps)]
+    for c in batch + single:
+        c.reset()
+    E = [torch.empty(3 * int(np.prod(n)), dtype=torch.float64, device="cuda") for n in shapes]
+    Jb = [torch.empty_like(e) for e in E]
+    Js = [torch.empty_like(e) for e in E]
+    for k in range(12):
+        t = (70 + k) * alpha / math.sqrt(3.0)
+        for c, p, e in zip(single, pulses, E):
+            c.excitation(p, t, e)
+        torch.cuda.synchronize()
+        status, stats = gpu_lib.step_batch(batch, E, Jb, tol=1e-6)
+        assert status == [0, 0, 0, 0]
+        for c, e, j in zip(single, E, Js):
+            c.step(e, j, tol=1e-6)
+        torch.cuda.synchronize()
+        for a, b in zip(Jb, Js):
+            assert torch.equal(a, b)

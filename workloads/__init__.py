@@ -110,3 +110,34 @@ CUBE96 = Workload("cube96_nested_sweep", (96, 96, 96), 16, 100, 40, lambda n: ep
 PILLARS = Workload("pillars8x8_320x320x48_a16", (320, 320, 48), 16, 120, 40,
                    lambda n: eps_pillars(n, 4))
 WORKLOADS = {w.name: w for w in (CUBE16, CUBE64, CUBE96, PILLARS)}
+
+
+@dataclass
+class Scatterer:
+    """One member of a batch: a cube with its own permittivity map and incidence."""
+    n: tuple
+    eps: np.ndarray = field(repr=False)
+    k_hat: tuple
+    e_hat: tuple
+
+
+def cube_batch(count=32, sides=(24, 32, 40, 48, 64, 80), lo=1.5, hi=6.0, seed=5):
+    """Batch of independent cubes: side drawn from ``sides``, eps_r i.i.d. U[lo, hi],
+    incidence direction uniform on the sphere, polarization uniform on the
+    circle orthogonal to it (all from one PCG64 stream)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        s = int(rng.choice(sides))
+        eps = rng.uniform(lo, hi, size=(s, s, s))
+        k = rng.standard_normal(3)
+        k /= np.linalg.norm(k)
+        a = rng.standard_normal(3)
+        e = a - np.dot(a, k) * k
+        e /= np.linalg.norm(e)
+        out.append(Scatterer((s, s, s), eps, tuple(float(v) for v in k), tuple(float(v) for v in e)))
+    return out
+
+
+# batch of 32 cubes (sides 24..80), alpha = 4, 150 steps, h = lambda_min / 40
+BATCH_ALPHA, BATCH_STEPS, BATCH_PPW = 4, 150, 40
