@@ -6,6 +6,10 @@ products with FP64 Krylov vectors and FP64 iterative refinement, TFQMR
 tolerance 1e-6.  A "step" is one MOT step (Eq. 3): excitation, history
 right-hand side, the Z0 solve and the history update.
 
+Set-up (untimed): the Green spectra, then the autotuner picks the FFT tile
+shape of each pass on this grid (mot_autotune; --no-autotune keeps the
+defaults).
+
 Timed region: K steps after W warm-up steps and 4 breakdown steps, inputs
 resident in HBM; the march starts at step ell with zero currents before it,
 so the history ring counts as full and every timed step multiplies all ell
@@ -104,6 +108,8 @@ def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
     c = native.Context(*n, alpha=w.alpha, precision="f64")
     c.set_material(torch.from_numpy(eps.ravel()).cuda())
     c.build_green_spectra()
+    if not args.no_autotune:
+        c.autotune()
     nl = c.info()["nlags"]
     c.reset()
     c.set_step(nl)
@@ -150,6 +156,8 @@ def batch_leg(args, log_fn):
         c = native.Context(*s_.n, alpha=alpha, precision=args.precision, stream=torch.cuda.Stream())
         c.set_material(torch.from_numpy(s_.eps.ravel()).cuda())
         c.build_green_spectra()
+        if not args.no_autotune:
+            c.autotune(reps=5)
         c.reset()
         c.set_step(c.info()["nlags"])
         ctxs.append(c)
@@ -205,14 +213,15 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, variant=0):
     """HBM bytes per launch from the committed counter runs, or None when the
-    kernel's sources changed since they were taken (or none were taken)."""
+    kernel's sources changed since they were taken, the counters were taken
+    for another tile variant, or none were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
-    if not rec:
+    if not rec or rec.get("tile_variant", 0) != variant:
         return None
     if sources_sha256(rec["sources"]) != rec["sources_sha256"]:
         return None
@@ -248,6 +257,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no timing events in the timed region (the roofline then uses the breakdown steps)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default FFT tile shapes instead of timing both variants per pass first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy kernel three times "
                          "(reference for the HBM traffic counters) and exit")
@@ -285,6 +296,13 @@ def main():
     info = ctx.info()
     nl = info["nlags"]
     log(f"spectra built in {setup_s:.1f} s (ell = {nl}, max |Im| = {imag:.2e})")
+    tune_ms, tune_s = None, 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune_ms = ctx.autotune()
+        tune_s = time.perf_counter() - t0
+        log(f"autotuned tile variants in {tune_s:.2f} s: {ctx.variants()}")
+    variants = ctx.variants()
 
     # start the march at step ell with J_m = 0 before it: every step multiplies all ell lags
     ctx.reset()
@@ -390,9 +408,12 @@ def main():
     alg = algorithmic_bytes(kind, n, tb, tb, nl, blk=4 if ring_t == 4 else 2)
     avg_s = ms / cnt / 1e3
     achieved = alg / avg_s / 1e9
+    knob = {"z_fused": "z_fused", "y_forward": "y", "y_inverse": "y"}.get(kind)
+    var = variants[prec][knob] if knob else 0
     roofline = {"bound": "hbm", "kernel": f"{kind}.{prec}", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{kind}.{prec}"),
-                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": ms / cnt}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(f"{kind}.{prec}", var),
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": ms / cnt, "tile_variant": var}
     # Z0 pipeline as a whole (five passes)
     pipe_bytes = sum(algorithmic_bytes(k, n, 4, 4, nl) for k in
                      ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue"))
@@ -422,6 +443,9 @@ def main():
         "ms_lhs_mean": sum(s["ms_lhs"] for s in stats) / len(stats),
         "ms_rhs_mean": sum(s["ms_rhs"] for s in stats) / len(stats),
         "setup_s": setup_s,
+        "autotune_s": tune_s,
+        "tile_variants": variants,
+        "autotune_ms": tune_ms,
         "roofline": roofline,
         "kernels": kernels,
     }

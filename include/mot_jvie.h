@@ -181,6 +181,38 @@ int mot_set_graphs(mot_ctx* ctx, int32_t on);
 int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* einc, double* const* J_n, double tol,
                    int32_t max_iter, mot_stats* stats, int32_t* status, int32_t nthreads);
 
+/* ---- Tile shapes of the FFT passes (Eq. 11 products) and their autotuner.
+ *
+ * Each pass of the Green products has two tile shapes, variant 0 (the
+ * default) and variant 1:
+ *   knob 0, x passes:        NP rows per workgroup, or 3 (NP/4) whole voxel
+ *                            rows of all three components;
+ *   knob 1, y passes:        NP kx columns per workgroup, or 2 NP when that
+ *                            fits a workgroup (else NP/2);
+ *   knob 2, history z passes: W kx columns per workgroup, or W/2;
+ *   knob 3, fused z pass:    W kx columns per workgroup, or W/2.
+ * Every variant computes the same sums in the same order: results are bit-identical
+ * across variants.  The knobs are held per compute precision:
+ * variants[4 p + k], p = 0 for the FP32 products, 1 for FP64.
+ *
+ * mot_set_variants: variants (host, 8 entries of 0 or 1).  Built Z0 spectra
+ *   are rewritten in the fused z pass's new tile layout; captured iteration
+ *   graphs are dropped.  Errors: MOT_EINVAL (NULL, a value other than 0 or 1).
+ * mot_get_variants: the current variants into `variants` (host, 8 entries).
+ * mot_autotune: times both variants of each knob on this context's grid and
+ *   keeps the faster (variant 1 only when it is faster by more than 2%):
+ *   knobs 0, 1, 3 by Z0 products in both precisions, knob 2 by the history z
+ *   passes in the history precision.  Each timing is the least over three
+ *   trials of `reps` calls (reps = 0: 20).  ms (host, optional, 16 entries):
+ *   ms[2 (4 p + k) + v] = milliseconds per call of variant v, -1 where not
+ *   timed.  Needs material and spectra, and a context at step 0 (a fresh
+ *   context or after mot_reset): it uses the history spectrum buffer and
+ *   leaves it zeroed.  Synchronises the context's stream.
+ *   Errors: MOT_EINVAL (reps < 0), MOT_ESTATE, MOT_EHIP. */
+int mot_set_variants(mot_ctx* ctx, const int32_t* variants);
+int mot_get_variants(const mot_ctx* ctx, int32_t* variants);
+int mot_autotune(mot_ctx* ctx, int32_t reps, double* ms);
+
 /* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
 int mot_reset(mot_ctx* ctx);
 

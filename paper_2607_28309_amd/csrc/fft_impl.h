@@ -25,28 +25,40 @@ constexpr int LDS_BUDGET = 81920;
 // LDS rows are padded to NPS = NP + 1 entries so that lanes walking along a
 // pencil (stride NPS) and the row stride of the Stockham writes spread over
 // the LDS banks instead of hitting the same ones.
-template <typename T, int M> struct XCfg {
+//
+// Tile-shape variants (chosen per context by the autotuner): V = 0 is the
+// default shape.  V = 1: the x pass takes 3 (NP0 / 4) rows (whole voxel rows
+// of all three components, fewer rows per workgroup); the y pass doubles its
+// columns when the doubled tile fits a workgroup (full 128-byte lines for
+// narrow tiles), else halves them; the z passes halve their columns (twice
+// the workgroups, half the LDS each).
+constexpr size_t LDS_MAX = 160 * 1024;
+template <typename T, int M, int V = 0> struct XCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
-  static constexpr int NP =
+  static constexpr int NP0 =
       cmax(1, floor_pow2(cmin(256 / TJ, (LDS_BUDGET - (2 * M + 1) * SZ) / ((M + 1) * SZ) - 1)));
+  static constexpr int NP = V == 0 ? NP0 : (NP0 >= 4 ? 3 * (NP0 / 4) : cmax(1, NP0 / 2));
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
   static constexpr size_t LDS = (size_t)((M + 1) * NPS + 2 * M + 1) * SZ;
 };
-template <typename T, int M> struct YCfg {
+template <typename T, int M, int V = 0> struct YCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
-  static constexpr int NP = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ) - 1)));
+  static constexpr int NP0 = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ) - 1)));
+  static constexpr bool DBL = 2 * NP0 * TJ <= 1024 && (size_t)(M * (2 * NP0 + 1) + M) * SZ <= LDS_MAX;
+  static constexpr int NP = V == 0 ? NP0 : (DBL ? 2 * NP0 : cmax(1, NP0 / 2));
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
   static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
 };
-template <typename T, int M, int NC> struct ZCfg {
+template <typename T, int M, int NC, int V = 0> struct ZCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
-  static constexpr int W =
+  static constexpr int W0 =
       cmax(1, floor_pow2(cmin(cmin(16, 1024 / (NC * TJ)), (LDS_BUDGET - 2 * M * SZ) / (NC * M * SZ))));
+  static constexpr int W = V == 0 ? W0 : cmax(1, W0 / 2);
   static constexpr int NP = NC * W;
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
@@ -54,11 +66,12 @@ template <typename T, int M, int NC> struct ZCfg {
 };
 
 // z pass with the spectral multiply: W kx columns x 3 components x 2 ky rows.
-template <typename T, int M> struct ZFCfg {
+template <typename T, int M, int V = 0> struct ZFCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
-  static constexpr int W =
+  static constexpr int W0 =
       cmax(1, floor_pow2(cmin(cmin(16, 1024 / (6 * TJ)), (LDS_BUDGET - 2 * M * SZ) / (6 * M * SZ))));
+  static constexpr int W = V == 0 ? W0 : cmax(1, W0 / 2);
   static constexpr int NP = 6 * W;
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;

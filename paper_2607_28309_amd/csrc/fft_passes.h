@@ -34,6 +34,8 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
 
 // Precision tags: T = compute type; IO = element type of real vectors.
 // Returns hipSuccess or an error; hipErrorInvalidValue for an unsupported length.
+// var: tile-shape variant, 0 (default) or 1 (see XCfg, YCfg, ZCfg, ZFCfg); the
+// full-length forward forms of the spectra precompute always use variant 0.
 
 // x pass, forward: `nrows` rows of `row_len` reals (row stride row_len) ->
 // rows of Nx+1 complex (stride kxs).  M = complex FFT length (= Nx), the
@@ -45,7 +47,7 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
 template <typename T, typename IO>
 hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
                      int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s,
-                     const double* pre = nullptr, Gate g = Gate{});
+                     const double* pre = nullptr, Gate g = Gate{}, int var = 0);
 
 // x pass, inverse with epilogue: rows of M+1 complex -> first n_out reals of
 // a length-2M real signal; y/J rows of row_len reals, eps indexed by
@@ -53,28 +55,29 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
 template <typename T, typename IO>
 hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
                      int nrows, int rows_per_comp, int ncomp, int row_len, int n_out, int kxs,
-                     const void* tw, const void* tw2, hipStream_t s, Gate g = Gate{});
+                     const void* tw, const void* tw2, hipStream_t s, Gate g = Gate{}, int var = 0);
 
 // y pass: `planes` planes; input rows_in rows (first n_in read), output
 // rows_out rows (first n_out written).
 template <typename T>
 hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kxs, int planes,
                   int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s,
-                  Gate g = Gate{});
+                  Gate g = Gate{}, int var = 0);
 
 // z pass over `nc` (1 or 3) components; ny = number of ky rows.
 // FUSED (nc = 3) multiplies by Lambda between the forward and inverse
 // transforms; Lambda is octant-compressed in the tile layout of
-// lam_tile_offset with W = z_fused_width(M, T is double).
+// lam_tile_offset with W = z_fused_width(M, T is double, var).
 template <typename T>
 hipError_t z_pass(const void* in, void* out, int M, int mode, int nc, int kx, int kxs, int ny,
                   int rows_in, int n_in, int rows_out, int n_out, const T* lam, const void* tw,
-                  hipStream_t s, Gate g = Gate{});
+                  hipStream_t s, Gate g = Gate{}, int var = 0);
 
 bool length_supported(int M);
 
-// kx columns per workgroup of the fused z pass (0 for an unsupported length).
-int z_fused_width(int M, bool f64);
+// kx columns per workgroup of the fused z pass in tile variant var (0 for an
+// unsupported length or variant).
+int z_fused_width(int M, bool f64, int var = 0);
 
 // Offset of the octant spectrum value of component comp (order xx, yy, zz,
 // xy, xz, yz) at (kx, kyc, kzc) in the fused z pass's tile layout

@@ -1,40 +1,15 @@
-// y pass of the circulant-embedded Green product (Eq. 11): complex pencils
-// along y for a tile of kx columns.  The forward pass of a product reads only
-// the Ny physical rows (the rest of the doubled grid is zero), the inverse
-// writes only the Ny rows that the truncation back to the physical grid keeps.
-#include "fft_impl.h"
+// y pass of the circulant-embedded Green product: entry points (tile
+// variant 0 is instantiated here, variant 1 in fft_y_alt.hip).
+#include "fft_y_kernels.h"
 
 namespace motfft {
 
-template <typename T, int M, bool INV, bool HIN, bool HOUT>
-__global__ __launch_bounds__((YCfg<T, M>::BLOCK)) void k_y_pass(const cpx<T>* __restrict__ in,
-                                                               cpx<T>* __restrict__ out, int kxn, int kxs,
-                                                               int rows_in, int rows_out,
-                                                               const cpx<T>* __restrict__ tw_g, int ntx, int nlog,
-                                                               Gate gate) {
-  using C = YCfg<T, M>;
-  constexpr int NP = C::NP, NPS = C::NPS;
-  if (gate_closed(gate)) return;
-  const int L = xcd_tile(blockIdx.x, nlog);
-  if (L >= nlog) return;
-  const int tile = L % ntx, plane = L / ntx;
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + M * NPS;
-  const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
-  const int kx = tile * NP + p;
-  const bool ok = kx < kxn;
-  // columns past the last kx load a valid column and store nothing
-  const cpx<T>* src = in + ((size_t)plane * rows_in + jt) * kxs + (ok ? kx : kxn - 1);
-  cpx<T>* dst = out + ((size_t)plane * rows_out + jt) * kxs + kx;
-  cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * kxs]; });
-  // the twiddles are first read after the first exchange's barrier
-  load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
-  run_fft<T, M, INV, HIN, HOUT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
-    if (ok) dst[(size_t)u * kxs] = val;
-  });
-}
+MOT_Y_VARIANT(0)
+
+extern template hipError_t y_pass_v<float, 1>(const void*, void*, int, bool, int, int, int, int, int, int, int,
+                                              const void*, hipStream_t, Gate);
+extern template hipError_t y_pass_v<double, 1>(const void*, void*, int, bool, int, int, int, int, int, int, int,
+                                               const void*, hipStream_t, Gate);
 
 bool length_supported(int M) {
   switch (M) {
@@ -47,45 +22,19 @@ bool length_supported(int M) {
   }
 }
 
-template <typename T, int M, bool INV, bool HIN, bool HOUT>
-static hipError_t y_launch(const void* in, void* out, int kx, int kxs, int planes, int rows_in, int rows_out,
-                           const void* tw, hipStream_t s, Gate g) {
-  using C = YCfg<T, M>;
-  const int ntx = (kx + C::NP - 1) / C::NP, nlog = ntx * planes;
-  hipLaunchKernelGGL((k_y_pass<T, M, INV, HIN, HOUT>), dim3(xcd_grid(nlog)), dim3(C::BLOCK), C::LDS, s,
-                     (const cpx<T>*)in, (cpx<T>*)out, kx, kxs, rows_in, rows_out, (const cpx<T>*)tw, ntx, nlog, g);
-  return hipGetLastError();
-}
-
-// Supported forms: forward with n_in = M/2 (product) or M (FP64 only,
-// spectra precompute), both with n_out = M; inverse with n_in = M, n_out = M/2.
 template <typename T>
 hipError_t y_pass(const void* in, void* out, int M, bool inverse, int kx, int kxs, int planes,
-                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s, Gate g) {
-  if (n_in > rows_in || n_out > rows_out) return hipErrorInvalidValue;
-  const int form = !inverse && 2 * n_in == M && n_out == M   ? 0
-                   : !inverse && n_in == M && n_out == M       ? 1
-                   : inverse && n_in == M && 2 * n_out == M    ? 2
-                                                               : -1;
-  if (form < 0 || (form == 1 && sizeof(T) != 8)) return hipErrorInvalidValue;
-  switch (M) {
-#define X(m)                                                                                     \
-  case m:                                                                                        \
-    if (form == 0) return y_launch<T, m, false, true, false>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s, g); \
-    if constexpr (sizeof(T) == 8)                                                                \
-      if (form == 1)                                                                             \
-        return y_launch<T, m, false, false, false>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s, g);           \
-    return y_launch<T, m, true, false, true>(in, out, kx, kxs, planes, rows_in, rows_out, tw, s, g);
-    MOT_FOR_EACH_LEN(X)
-#undef X
-    default:
-      return hipErrorInvalidValue;
-  }
+                  int rows_in, int n_in, int rows_out, int n_out, const void* tw, hipStream_t s, Gate g, int var) {
+  const bool full_fwd = !inverse && n_in == M;
+  if (var == 1 && !full_fwd)
+    return y_pass_v<T, 1>(in, out, M, inverse, kx, kxs, planes, rows_in, n_in, rows_out, n_out, tw, s, g);
+  if (var != 0 && var != 1) return hipErrorInvalidValue;
+  return y_pass_v<T, 0>(in, out, M, inverse, kx, kxs, planes, rows_in, n_in, rows_out, n_out, tw, s, g);
 }
 
 template hipError_t y_pass<float>(const void*, void*, int, bool, int, int, int, int, int, int, int,
-                                  const void*, hipStream_t, Gate);
+                                  const void*, hipStream_t, Gate, int);
 template hipError_t y_pass<double>(const void*, void*, int, bool, int, int, int, int, int, int, int,
-                                   const void*, hipStream_t, Gate);
+                                   const void*, hipStream_t, Gate, int);
 
 }  // namespace motfft

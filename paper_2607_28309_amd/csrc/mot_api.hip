@@ -3,6 +3,7 @@
 // device-resident TFQMR solve.  See include/mot_jvie.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -17,6 +18,10 @@
 
 using motfft::cpx;
 using namespace motimpl;
+
+// Tile-variant knobs per compute precision (tune[0] FP32, tune[1] FP64): the
+// x passes, the y passes, the history z passes and the fused z pass.
+enum { TUNE_X = 0, TUNE_Y, TUNE_Z, TUNE_ZF, TUNE_N };
 
 struct mot_ctx {
   mot_grid grid;
@@ -71,6 +76,7 @@ struct mot_ctx {
   int adjoint;         // 1: transposed operators Z_k^T (adjoint march)
   double* ffpart;      // scratch: far-field block partials
   size_t ffpart_n;
+  int tune[2][TUNE_N]; // tile variants of the FFT passes (0 or 1)
   size_t bytes;
   char err[512];
 };
@@ -236,6 +242,21 @@ __global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int n
       src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
 }
 
+// fused z pass tile layout of width ws -> the same spectra in width wd
+template <typename T>
+__global__ void k_retile(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int ws, int wd) {
+  const long long cnt = 6LL * (nx + 1) * (ny + 1) * (nz + 1);
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= cnt) return;
+  const int kx = (int)(id % (nx + 1));
+  long long r = id / (nx + 1);
+  const int ky = (int)(r % (ny + 1));
+  r /= (ny + 1);
+  const int kz = (int)(r % (nz + 1)), comp = (int)(r / (nz + 1));
+  dst[motfft::lam_tile_offset(kx, ky, kz, comp, nx + 1, nz + 1, wd)] =
+      src[motfft::lam_tile_offset(kx, ky, kz, comp, nx + 1, nz + 1, ws)];
+}
+
 }  // namespace
 
 namespace motimpl {
@@ -258,16 +279,17 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
   hipStream_t s = c->stream;
   const int rows = 3 * c->nz * c->ny;
   const bool d = ti == 1;
+  const int* tv = c->tune[ti];
   HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
-                                         c->twx[ti], c->tw2x[ti], s, pre, g)));
+                                         c->twx[ti], c->tw2x[ti], s, pre, g, tv[TUNE_X])));
   HTP(K_YF, d, motfft::y_pass<T>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py, c->py,
-                                 c->twy[ti], s, g));
+                                 c->twy[ti], s, g, tv[TUNE_Y]));
   HTP(K_ZFUSED, d, motfft::z_pass<T>(c->wsB, c->wsB, c->pz, motfft::Z_FUSED, 3, c->kx, c->kxs, c->py, c->nz, c->nz,
-                                     c->nz, c->nz, lam, c->twz[ti], s, g));
+                                     c->nz, c->nz, lam, c->twz[ti], s, g, tv[TUNE_ZF]));
   HTP(K_YI, d, motfft::y_pass<T>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny, c->ny,
-                                 c->twy[ti], s, g));
+                                 c->twy[ti], s, g, tv[TUNE_Y]));
   HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, J, c->eps, ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
-                                         c->kxs, c->twx[ti], c->tw2x[ti], s, g)));
+                                         c->kxs, c->twx[ti], c->tw2x[ti], s, g, tv[TUNE_X])));
   return MOT_OK;
 }
 
@@ -526,13 +548,15 @@ int history_update_t(mot_ctx* c, const double* J) {
   const int slot = (int)(c->nstep % c->nl);
   cpx<Tr>* dst = (cpx<Tr>*)c->ring + (size_t)slot * c->slot_elems;
   const bool d = ti == 1;
+  const int* tv = c->tune[ti];
   // the adjoint march transforms (eps - 1) lam: Z_k^T = T(k) diag(eps) - G_k X
   HTP(K_XF, d, (motfft::x_forward<Tr, double>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
-                                              c->twx[ti], c->tw2x[ti], s, c->adjoint ? c->eps : nullptr)));
+                                              c->twx[ti], c->tw2x[ti], s, c->adjoint ? c->eps : nullptr, {},
+                                              tv[TUNE_X])));
   HTP(K_YF, d, motfft::y_pass<Tr>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py,
-                                  c->py, c->twy[ti], s));
+                                  c->py, c->twy[ti], s, {}, tv[TUNE_Y]));
   HTP(K_ZF, d, motfft::z_pass<Tr>(c->wsB, dst, c->pz, motfft::Z_FWD, 3, c->kx, c->kxs, c->py, c->nz, c->nz, c->pz,
-                                  c->pz, nullptr, c->twz[ti], s));
+                                  c->pz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));
   const long long n = c->nstep;
   if (c->blk_n0 < 0 || n - c->blk_n0 >= c->blk_B) {
     // block start: contributions of every slot <= n to the next B right-hand sides
@@ -549,12 +573,13 @@ int history_update_t(mot_ctx* c, const double* J) {
                                      c->nz, c->kxs, s));
   }
   HTP(K_ZI, d, motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz,
-                                  c->nz, c->nz, nullptr, c->twz[ti], s));
+                                  c->nz, c->nz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
-                                  c->ny, c->twy[ti], s));
+                                  c->ny, c->twy[ti], s, {}, tv[TUNE_Y]));
   HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, c->adjoint ? EP_ADJ_HIST : EP_HIST, c->nx,
                                               rows, c->nz * c->ny, 3,
-                                              c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s)));
+                                              c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
+                                              tv[TUNE_X])));
   c->head = slot;
   c->nstep += 1;
   return MOT_OK;
@@ -569,18 +594,120 @@ int history_gfield_t(mot_ctx* c, double* out) {
   hipStream_t s = c->stream;
   const int rows = 3 * c->nz * c->ny;
   const bool d = ti == 1;
+  const int* tv = c->tune[ti];
   HTP(K_ZI, d, motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz,
-                                  c->nz, c->nz, nullptr, c->twz[ti], s));
+                                  c->nz, c->nz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
-                                  c->ny, c->twy[ti], s));
+                                  c->ny, c->twy[ti], s, {}, tv[TUNE_Y]));
   // EP_G ignores its current argument; hrhs is passed as a valid vector
   HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, out, c->hrhs, c->eps, EP_G, c->nx, rows, c->nz * c->ny, 3,
-                                              c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s)));
+                                              c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
+                                              tv[TUNE_X])));
   return MOT_OK;
 }
 
 int history_update_impl(mot_ctx* c, const double* J) {
   return c->ring_f64 ? history_update_t<double>(c, J) : history_update_t<float>(c, J);
+}
+
+void drop_graphs(mot_ctx* c) {
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < 2; ++k)
+        if (c->iter_graph[a][b][k]) {
+          (void)hipGraphExecDestroy(c->iter_graph[a][b][k]);
+          c->iter_graph[a][b][k] = nullptr;
+        }
+}
+
+// Rewrite stored Z0 spectra from the fused z pass's tile width ws to wd
+// (through the lam_tile scratch, so that the spectra keep their address).
+template <typename T>
+int retile_lam0(mot_ctx* c, T* lam, int ws, int wd) {
+  if (ws == wd) return MOT_OK;
+  if (ws <= 0 || wd <= 0) return set_err(c, MOT_EINVAL, "no fused z tile width for this length%s%d");
+  if (!c->lam_tile) TRY(dmalloc(c, &c->lam_tile, 6 * c->lam_comp * sizeof(double)));
+  const long long cnt = 6LL * (c->nx + 1) * (c->ny + 1) * (c->nz + 1);
+  hipLaunchKernelGGL(k_retile<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c->stream, lam,
+                     (T*)c->lam_tile, c->nx, c->ny, c->nz, ws, wd);
+  HT(hipGetLastError());
+  HT(hipMemcpyAsync(lam, c->lam_tile, sizeof(T) * 6 * c->lam_comp, hipMemcpyDeviceToDevice, c->stream));
+  return MOT_OK;
+}
+
+// Select tile variant v of one knob; built Z0 spectra follow the fused z
+// pass's width, and captured iteration graphs are dropped.
+int set_variant(mot_ctx* c, int ti, int knob, int v) {
+  if (c->tune[ti][knob] == v) return MOT_OK;
+  if (knob == TUNE_ZF && c->have_spectra) {
+    const int ws = motfft::z_fused_width(c->pz, ti == 1, c->tune[ti][knob]);
+    const int wd = motfft::z_fused_width(c->pz, ti == 1, v);
+    TRY(ti == 1 ? retile_lam0(c, c->lam0_64, ws, wd) : retile_lam0(c, c->lam0_32, ws, wd));
+  }
+  c->tune[ti][knob] = v;
+  drop_graphs(c);
+  return MOT_OK;
+}
+
+// The history z passes alone (forward into the history spectrum buffer and
+// back), for timing.
+template <typename Tr>
+int history_z_passes(mot_ctx* c) {
+  const int ti = sizeof(Tr) == 8 ? 1 : 0;
+  hipStream_t s = c->stream;
+  HT(motfft::z_pass<Tr>(c->wsB, c->spec, c->pz, motfft::Z_FWD, 3, c->kx, c->kxs, c->py, c->nz, c->nz, c->pz, c->pz,
+                        nullptr, c->twz[ti], s, {}, c->tune[ti][TUNE_Z]));
+  HT(motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz, c->nz, c->nz,
+                        nullptr, c->twz[ti], s, {}, c->tune[ti][TUNE_Z]));
+  return MOT_OK;
+}
+
+int autotune_impl(mot_ctx* c, int reps, double* ms) {
+  double* in = c->kv[V_TMP];
+  double* out = c->kv[V_XO];
+  TRY(zero_bytes(c, in, sizeof(double) * c->n3));
+  // ms per call of fn: the least over three trials of reps calls, after one warm-up call
+  auto time_runs = [&](auto&& fn, double* best) -> int {
+    TRY(fn());
+    *best = 1e300;
+    for (int t = 0; t < 3; ++t) {
+      HT(hipEventRecord(c->ev[0], c->stream));
+      for (int r = 0; r < reps; ++r) TRY(fn());
+      HT(hipEventRecord(c->ev[1], c->stream));
+      HT(hipEventSynchronize(c->ev[1]));
+      float e = 0.f;
+      HT(hipEventElapsedTime(&e, c->ev[0], c->ev[1]));
+      *best = std::min(*best, (double)e / reps);
+    }
+    return MOT_OK;
+  };
+  auto tune_knob = [&](int ti, int knob, auto&& fn) -> int {
+    double t[2];
+    for (int v = 0; v < 2; ++v) {
+      TRY(set_variant(c, ti, knob, v));
+      TRY(time_runs(fn, &t[v]));
+      if (ms) ms[(ti * TUNE_N + knob) * 2 + v] = t[v];
+    }
+    // variant 1 replaces the default only when it is faster by more than the
+    // run-to-run spread of these timings (about 1%)
+    return set_variant(c, ti, knob, t[1] < 0.98 * t[0] ? 1 : 0);
+  };
+  for (int ti = 1; ti >= 0; --ti) {
+    auto product = [&]() -> int {
+      return ti == 1 ? green_product<double, double>(c, in, out, c->lam0_64, EP_Z0)
+                     : green_product<float, float>(c, (const float*)in, (float*)out, c->lam0_32, EP_Z0);
+    };
+    for (int knob : {TUNE_X, TUNE_Y, TUNE_ZF}) TRY(tune_knob(ti, knob, product));
+    if (ti == c->ring_f64) {
+      auto hz = [&]() -> int { return ti == 1 ? history_z_passes<double>(c) : history_z_passes<float>(c); };
+      TRY(tune_knob(ti, TUNE_Z, hz));
+    }
+  }
+  // the history spectrum buffer held timing data: back to the state of step 0
+  const size_t rsz = c->ring_f64 ? sizeof(double) : sizeof(float);
+  TRY(zero_bytes(c, c->spec, rsz * 2 * c->slot_elems));
+  HT(hipStreamSynchronize(c->stream));
+  return MOT_OK;
 }
 
 }  // namespace
@@ -744,10 +871,7 @@ int mot_destroy(mot_ctx* c) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (int i = 0; i < 2; ++i)
     if (c->evq[i]) (void)hipEventDestroy(c->evq[i]);
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int k = 0; k < 2; ++k)
-        if (c->iter_graph[a][b][k]) (void)hipGraphExecDestroy(c->iter_graph[a][b][k]);
+  drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->prof_ev) {
@@ -839,8 +963,8 @@ int build_green_spectra(mot_ctx* c) {
       } else {
         l32 = (float*)c->lamh + (size_t)(k - 1) * 6 * c->lam_comp;
       }
-      const int w64 = k == 0 ? motfft::z_fused_width(c->pz, true) : 0;
-      const int w32 = k == 0 ? motfft::z_fused_width(c->pz, false) : 0;
+      const int w64 = k == 0 ? motfft::z_fused_width(c->pz, true, c->tune[1][TUNE_ZF]) : 0;
+      const int w32 = k == 0 ? motfft::z_fused_width(c->pz, false, c->tune[0][TUNE_ZF]) : 0;
       if ((e = launch_compress(T1, l64, l32, imax, comp, c->nx, c->ny, c->nz, c->kxs, scale, w64, w32, s)) !=
           hipSuccess)
         break;
@@ -893,12 +1017,14 @@ int gk_matvec(mot_ctx* c, int32_t k, const void* J, void* y, mot_precision dtype
   dim3 g((unsigned)((cnt + 255) / 256));
   if (c->ring_f64) {
     hipLaunchKernelGGL(k_relayout<double>, g, dim3(256), 0, c->stream, (const double*)c->lamh + off,
-                       (double*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs, motfft::z_fused_width(c->pz, true));
+                       (double*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs,
+                       motfft::z_fused_width(c->pz, true, c->tune[1][TUNE_ZF]));
     HT(hipGetLastError());
     return green_product<double, double>(c, (const double*)J, (double*)y, (const double*)c->lam_tile, EP_G);
   }
   hipLaunchKernelGGL(k_relayout<float>, g, dim3(256), 0, c->stream, (const float*)c->lamh + off,
-                     (float*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs, motfft::z_fused_width(c->pz, false));
+                     (float*)c->lam_tile, c->nx, c->ny, c->nz, c->kxs,
+                     motfft::z_fused_width(c->pz, false, c->tune[0][TUNE_ZF]));
   HT(hipGetLastError());
   if (dtype == MOT_F32)
     return green_product<float, float>(c, (const float*)J, (float*)y, (const float*)c->lam_tile, EP_G);
@@ -1038,6 +1164,35 @@ int mot_set_adjoint(mot_ctx* c, int32_t on) {
   if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
   c->adjoint = on;
   return MOT_OK;
+}
+
+int mot_set_variants(mot_ctx* c, const int32_t* v) {
+  if (!c || !v) return MOT_EINVAL;
+  for (int i = 0; i < 2 * TUNE_N; ++i)
+    if (v[i] != 0 && v[i] != 1) return MOT_EINVAL;
+  for (int ti = 0; ti < 2; ++ti)
+    for (int k = 0; k < TUNE_N; ++k) TRY(set_variant(c, ti, k, v[ti * TUNE_N + k]));
+  return MOT_OK;
+}
+
+int mot_get_variants(const mot_ctx* c, int32_t* v) {
+  if (!c || !v) return MOT_EINVAL;
+  for (int ti = 0; ti < 2; ++ti)
+    for (int k = 0; k < TUNE_N; ++k) v[ti * TUNE_N + k] = c->tune[ti][k];
+  return MOT_OK;
+}
+
+int mot_autotune(mot_ctx* c, int32_t reps, double* ms) {
+  if (!c || reps < 0) return MOT_EINVAL;
+  if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
+  if (c->nstep != 0) return set_err(c, MOT_ESTATE, "autotune runs at step 0 (before the march or after a reset)%s%d");
+  if (ms)
+    for (int i = 0; i < 4 * TUNE_N; ++i) ms[i] = -1.0;
+  const int prof = c->prof_on;
+  c->prof_on = 0;
+  const int rc = autotune_impl(c, reps > 0 ? reps : 20, ms);
+  c->prof_on = prof;
+  return rc;
 }
 
 int z0t_matvec(mot_ctx* c, const void* v, void* y, mot_precision dtype) {

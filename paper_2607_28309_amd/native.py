@@ -24,7 +24,9 @@ EXPORTS = (
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
+    "mot_set_variants", "mot_get_variants", "mot_autotune",
 )
+TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
 PROF_NCLASS = 22
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
               "history_mac", "z_inverse", "krylov", "excitation", "history_mac_recent")
@@ -88,6 +90,9 @@ def _load():
         "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
         "mot_farfield_adjoint": (ctypes.c_int, [vp, vp, i32, i32, ctypes.POINTER(dbl), dbl, i64, vp]),
         "mot_adjoint_gradient": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp, vp, vp, vp, vp, vp]),
+        "mot_set_variants": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
+        "mot_get_variants": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
+        "mot_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -238,6 +243,35 @@ class Context:
 
     def set_adjoint(self, on=True):
         self._check(LIB.mot_set_adjoint(self.h, 1 if on else 0), "mot_set_adjoint")
+
+    def variants(self):
+        """{"f32": {knob: 0|1}, "f64": {...}} of the FFT pass tile shapes."""
+        v = (ctypes.c_int32 * 8)()
+        self._check(LIB.mot_get_variants(self.h, v), "mot_get_variants")
+        return {p: {k: int(v[4 * i + j]) for j, k in enumerate(TUNE_KNOBS)} for i, p in enumerate(("f32", "f64"))}
+
+    def set_variants(self, variants):
+        """variants: 8 ints ([FP32 knobs, FP64 knobs], knob order TUNE_KNOBS)
+        or a dict as returned by ``variants``."""
+        if isinstance(variants, dict):
+            variants = [variants[p][k] for p in ("f32", "f64") for k in TUNE_KNOBS]
+        if len(variants) != 8:
+            raise ValueError("8 variants: 4 knobs for FP32 and 4 for FP64")
+        v = (ctypes.c_int32 * 8)(*[int(x) for x in variants])
+        self._check(LIB.mot_set_variants(self.h, v), "mot_set_variants")
+
+    def autotune(self, reps=0):
+        """Time both tile variants of every knob on this grid and keep the
+        faster; returns {"f32"|"f64": {knob: [ms variant 0, ms variant 1] or None}}."""
+        ms = (ctypes.c_double * 16)()
+        self._check(LIB.mot_autotune(self.h, int(reps), ms), "mot_autotune")
+        out = {}
+        for i, p in enumerate(("f32", "f64")):
+            out[p] = {}
+            for j, k in enumerate(TUNE_KNOBS):
+                a, b = ms[2 * (4 * i + j)], ms[2 * (4 * i + j) + 1]
+                out[p][k] = [a, b] if a >= 0 else None
+        return out
 
     def z0t_matvec(self, v, y, dtype="f64"):
         import torch
