@@ -10,7 +10,8 @@ Set-up (untimed): the Green spectra, then the autotuner picks the FFT tile
 shape of each pass on this grid (mot_autotune; --no-autotune keeps the
 defaults).
 
-Timed region: K steps after W warm-up steps and 4 breakdown steps, inputs
+Timed region: K steps after W warm-up steps and B breakdown steps (one
+history block, B = 8 for the FP32 ring), inputs
 resident in HBM; the march starts at step ell with zero currents before it,
 so the history ring counts as full and every timed step multiplies all ell
 lags.  The breakdown steps (one history block, untimed) time every kernel and
@@ -30,7 +31,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ROOFLINE_KINDS = ("history_mac", "z_fused", "y_forward", "y_inverse")
-BREAKDOWN_STEPS = 4
 
 
 def log(msg):
@@ -241,7 +241,8 @@ def _cpu_name():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=16,
+                    help="timed steps (a multiple of the history block, 8, times whole blocks)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f32_refined", choices=["f32_refined", "f64", "f32"])
     ap.add_argument("--matvec-reps", type=int, default=60, help="timed Z0 products per precision (median reported)")
@@ -311,7 +312,7 @@ def main():
     L = w.alpha / math.sqrt(3.0)
     einc = torch.empty(3 * N, dtype=torch.float64, device="cuda")
     # step sequence: warm-up, breakdown (untimed, every kernel timed), timed region
-    nbd = BREAKDOWN_STEPS
+    nbd = info["history_block"]  # one history block: exactly one block-start step
     first_timed = args.warmup + nbd
     # one output vector per step, so that the currents can be compared with an FP64 march afterwards
     n_keep = first_timed + min(args.steps, args.f64_steps)
@@ -325,7 +326,7 @@ def main():
     for s in range(args.warmup):
         st = one_step(ctx, s)
         log(f"warm-up step {s}: {st['iters']} iterations, relres {st['relres']:.2e}")
-    # breakdown over one history block (B = 4 steps for an FP32 ring): every
+    # breakdown over one history block (B = 8 steps for an FP32 ring): every
     # kernel timed; it names the dominant single kernel
     ctx.profile_kinds(None)
     ctx.profile(True)
@@ -404,8 +405,8 @@ def main():
     tb = 8 if prec == "f64" else 4
     if kind == "history_mac":
         tb = ring_t
-    # the history pass at a block start writes the partial sums of 4 (FP32 ring) or 2 (FP64) steps
-    alg = algorithmic_bytes(kind, n, tb, tb, nl, blk=4 if ring_t == 4 else 2)
+    # the history pass at a block start writes the partial sums of the B steps of a block
+    alg = algorithmic_bytes(kind, n, tb, tb, nl, blk=info["history_block"])
     avg_s = ms / cnt / 1e3
     achieved = alg / avg_s / 1e9
     knob = {"z_fused": "z_fused", "y_forward": "y", "y_inverse": "y"}.get(kind)

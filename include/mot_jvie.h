@@ -106,7 +106,9 @@ int mot_destroy(mot_ctx* ctx);
 
 /* Sizes: out[0] = ell, out[1..3] = 2nx, 2ny, 2nz, out[4] = padded row
  * stride of the spectral buffers, out[5] = device bytes held by the context,
- * out[6] = steps taken since the last reset.  Host array of n >= 7 entries. */
+ * out[6] = steps taken since the last reset, and with n >= 8 out[7] = B, the
+ * steps per history block (temporal blocking of the history sum).  Host array
+ * of n >= 7 entries. */
 int mot_info(const mot_ctx* ctx, int64_t* out, int32_t n);
 
 /* Operator precompute (Sec. II: Z_k for lags 0..ell; Sec. IV: spectra of the

@@ -7,8 +7,8 @@
 // in ky, xz odd in kz, yz odd in both).
 //
 // Temporal blocking: at the start of a block of B steps (after J^_{n0} is
-// pushed) one pass over the ring computes the contributions of all slots
-// t <= n0 to the next B right-hand sides,
+// pushed; B = 8 for an FP32 ring, 2 for FP64) one pass over the ring computes
+// the contributions of all slots t <= n0 to the next B right-hand sides,
 //   P_b = sum_{m>=0} Lambda_{m+b} J^_{n0-m},   b = 1..B,
 // reading every slot and every Lambda_j once (a sliding window of B Lambda
 // values is kept in registers).  Step n0+b-1 then adds only its b-1 newest
@@ -27,16 +27,19 @@ struct Geo {
   int nx, ny, nz, kxs, nl;
 };
 
-template <typename T>
+// The mirror points of one octant frequency that a thread takes: NM = 4
+// (both kz sides) or NM = 2 (the kz side `side`, both ky sides); mirror i is
+// kz side a(i), ky side b(i).
+template <int NM>
 struct Point {
-  size_t off[4];
-  bool keep[4];
+  size_t off[NM];
+  bool keep[NM];
+  int a[NM], b[NM];
 };
 
-template <typename T>
-__device__ __forceinline__ bool octant_point(const Geo& g, size_t& lo, Point<T>& pt) {
+template <int NM>
+__device__ __forceinline__ bool octant_point(const Geo& g, long long id, int side, size_t& lo, Point<NM>& pt) {
   const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= cnt) return false;
   const int kx = (int)(id % (g.nx + 1)), kyc = (int)((id / (g.nx + 1)) % (g.ny + 1)),
             kzc = (int)(id / ((long long)(g.nx + 1) * (g.ny + 1)));
@@ -45,24 +48,40 @@ __device__ __forceinline__ bool octant_point(const Geo& g, size_t& lo, Point<T>&
   lo = ((size_t)kzc * (g.ny + 1) + kyc) * g.kxs + kx;
   const bool dupy = (kyc == 0 || kyc == g.ny), dupz = (kzc == 0 || kzc == g.nz);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int a = i >> 1, b = i & 1;
+  for (int i = 0; i < NM; ++i) {
+    const int a = NM == 4 ? i >> 1 : side, b = i & 1;
     const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
     pt.off[i] = (size_t)(kz % pz) * plane + (size_t)(ky % py) * g.kxs + kx;
     pt.keep[i] = !((a && dupz) || (b && dupy));
+    pt.a[i] = a;
+    pt.b[i] = b;
   }
   return true;
 }
 
+// acc += Lambda J for one mirror point (signs sy, sz), one multiply-add per
+// term into the accumulator.
 template <typename T>
 __device__ __forceinline__ void mac3(cpx<T> (&acc)[3], const T* l, T sy, T sz, cpx<T> jx, cpx<T> jy, cpx<T> jz) {
   const T xy = sy * l[3], xz = sz * l[4], yz = sy * sz * l[5];
-  acc[0].x += l[0] * jx.x + xy * jy.x + xz * jz.x;
-  acc[0].y += l[0] * jx.y + xy * jy.y + xz * jz.y;
-  acc[1].x += xy * jx.x + l[1] * jy.x + yz * jz.x;
-  acc[1].y += xy * jx.y + l[1] * jy.y + yz * jz.y;
-  acc[2].x += xz * jx.x + yz * jy.x + l[2] * jz.x;
-  acc[2].y += xz * jx.y + yz * jy.y + l[2] * jz.y;
+  acc[0].x += l[0] * jx.x;
+  acc[0].x += xy * jy.x;
+  acc[0].x += xz * jz.x;
+  acc[0].y += l[0] * jx.y;
+  acc[0].y += xy * jy.y;
+  acc[0].y += xz * jz.y;
+  acc[1].x += xy * jx.x;
+  acc[1].x += l[1] * jy.x;
+  acc[1].x += yz * jz.x;
+  acc[1].y += xy * jx.y;
+  acc[1].y += l[1] * jy.y;
+  acc[1].y += yz * jz.y;
+  acc[2].x += xz * jx.x;
+  acc[2].x += yz * jy.x;
+  acc[2].x += l[2] * jz.x;
+  acc[2].y += xz * jx.y;
+  acc[2].y += yz * jy.y;
+  acc[2].y += l[2] * jz.y;
 }
 
 // S = init + sum_{j=1..nrec} Lambda_j J^_{n+1-j}  (init may be null)
@@ -71,8 +90,8 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
                                                     const cpx<T>* __restrict__ init, cpx<T>* __restrict__ out,
                                                     Geo g, long long n, int nrec) {
   size_t lo;
-  Point<T> pt;
-  if (!octant_point<T>(g, lo, pt)) return;
+  Point<4> pt;
+  if (!octant_point<4>(g, (long long)blockIdx.x * blockDim.x + threadIdx.x, 0, lo, pt)) return;
   const size_t comp = (size_t)(2 * g.nz) * (2 * g.ny) * g.kxs;
   const size_t slot = 3 * comp;
   const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;
@@ -98,14 +117,21 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
 }
 
 // P_b = sum_{m=0..nold-1} Lambda_{m+b} J^_{n0-m} for b = 1..B (Lambda_{>ell} = 0);
-// P_1 -> out0, P_b -> pblk + (b-2) * slot for b >= 2.
-template <typename T, int B>
-__global__ __launch_bounds__(256) void k_mac_block(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
+// P_1 -> out0, P_b -> pblk + (b-2) * slot for b >= 2.  NM = 4: a thread takes
+// all four mirror points of its octant frequency; NM = 2 (for long blocks,
+// whose B accumulators per point would not fit the registers): the two
+// threads of a frequency take one kz side each, in the two halves of the
+// workgroup, and read the same Lambda words.  Two waves per SIMD at least
+// (a register budget of 256).
+template <typename T, int B, int NM>
+__global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
                                                    cpx<T>* __restrict__ out0, cpx<T>* __restrict__ pblk, Geo g,
                                                    long long n0, int nold) {
+  constexpr int PER = NM == 4 ? 256 : 128;  // octant frequencies per workgroup
   size_t lo;
-  Point<T> pt;
-  if (!octant_point<T>(g, lo, pt)) return;
+  Point<NM> pt;
+  const long long id = (long long)blockIdx.x * PER + (int)threadIdx.x % PER;
+  if (!octant_point<NM>(g, id, (int)threadIdx.x / PER, lo, pt)) return;
   const size_t comp = (size_t)(2 * g.nz) * (2 * g.ny) * g.kxs;
   const size_t slot = 3 * comp;
   const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;
@@ -122,25 +148,34 @@ __global__ __launch_bounds__(256) void k_mac_block(const cpx<T>* __restrict__ ri
   T w[B][6];  // window: w[b] = Lambda_{m+1+b}
 #pragma unroll
   for (int b = 0; b < B; ++b) lam_at(b + 1, w[b]);
-  cpx<T> acc[B][4][3];
+  cpx<T> acc[B][NM][3];
 #pragma unroll
   for (int b = 0; b < B; ++b)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NM; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[b][i][q] = cpx<T>{(T)0, (T)0};
+  // With NM = 2 the kz sign sz is known only at run time: the z component of
+  // each loaded current is multiplied by sz and the z accumulators carry sz
+  // times their value (sz^2 = 1), so that the B multiply-adds per load see
+  // compile-time signs only.
+  const T sz2 = NM == 2 && pt.a[0] ? (T)-1 : (T)1;
   for (int m = 0; m < nold; ++m) {
     const cpx<T>* R = ring + (size_t)((n0 - m) % g.nl) * slot;
-    cpx<T> jv[4][3];
+    cpx<T> jv[NM][3];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NM; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
+    if constexpr (NM == 2)
+#pragma unroll
+      for (int i = 0; i < NM; ++i) jv[i][2] = cpx<T>{sz2 * jv[i][2].x, sz2 * jv[i][2].y};
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        mac3<T>(acc[b][i], w[b], (i & 1) ? (T)-1 : (T)1, (i >> 1) ? (T)-1 : (T)1, jv[i][0], jv[i][1], jv[i][2]);
+      for (int i = 0; i < NM; ++i)
+        mac3<T>(acc[b][i], w[b], (i & 1) ? (T)-1 : (T)1, (NM == 4 && (i >> 1)) ? (T)-1 : (T)1, jv[i][0], jv[i][1],
+                jv[i][2]);
 #pragma unroll
     for (int b = 0; b + 1 < B; ++b)
 #pragma unroll
@@ -151,10 +186,12 @@ __global__ __launch_bounds__(256) void k_mac_block(const cpx<T>* __restrict__ ri
   for (int b = 0; b < B; ++b) {
     cpx<T>* dst = b == 0 ? out0 : pblk + (size_t)(b - 1) * slot;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (pt.keep[i])
-#pragma unroll
-        for (int q = 0; q < 3; ++q) dst[q * comp + pt.off[i]] = acc[b][i][q];
+    for (int i = 0; i < NM; ++i)
+      if (pt.keep[i]) {
+        dst[pt.off[i]] = acc[b][i][0];
+        dst[comp + pt.off[i]] = acc[b][i][1];
+        dst[2 * comp + pt.off[i]] = cpx<T>{sz2 * acc[b][i][2].x, sz2 * acc[b][i][2].y};
+      }
   }
 }
 
@@ -179,17 +216,20 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
                             long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s) {
   const Geo g{nx, ny, nz, kxs, nl};
   const dim3 gr = mac_grid(g);
-#define LB(T, BB)                                                                                       \
-  hipLaunchKernelGGL((k_mac_block<T, BB>), gr, dim3(256), 0, s, (const cpx<T>*)ring, (const T*)lamh,     \
+  const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+  const dim3 gr2((unsigned)((cnt + 127) / 128));  // two threads per octant frequency
+#define LB(T, BB, NM, GR)                                                                                 \
+  hipLaunchKernelGGL((k_mac_block<T, BB, NM>), GR, dim3(256), 0, s, (const cpx<T>*)ring, (const T*)lamh,   \
                      (cpx<T>*)out0, (cpx<T>*)pblk, g, n0, nold)
   if (f64) {
-    if (B == 1) LB(double, 1);
-    else if (B == 2) LB(double, 2);
+    if (B == 1) LB(double, 1, 4, gr);
+    else if (B == 2) LB(double, 2, 4, gr);
     else return hipErrorInvalidValue;
   } else {
-    if (B == 1) LB(float, 1);
-    else if (B == 2) LB(float, 2);
-    else if (B == 4) LB(float, 4);
+    if (B == 1) LB(float, 1, 4, gr);
+    else if (B == 2) LB(float, 2, 4, gr);
+    else if (B == 4) LB(float, 4, 4, gr);
+    else if (B == 8) LB(float, 8, 2, gr2);
     else return hipErrorInvalidValue;
   }
 #undef LB

@@ -821,8 +821,8 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if ((rc = dmalloc(c, (void**)&c->lam0_32, sizeof(float) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->lamh, rsz * 6 * c->lam_comp * c->nl)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->spec, rsz * 2 * c->slot_elems)) != MOT_OK) return fail(rc);
-  c->blk_B = c->ring_f64 ? 2 : 4;
-  if (c->blk_B > c->nl) c->blk_B = c->nl >= 4 && !c->ring_f64 ? 4 : (c->nl >= 2 ? 2 : 1);
+  c->blk_B = c->ring_f64 ? 2 : 8;
+  while (c->blk_B > c->nl) c->blk_B /= 2;
   c->blk_n0 = -1;
   if (c->blk_B > 1 && (rc = dmalloc(c, &c->pblk, rsz * 2 * c->slot_elems * (c->blk_B - 1))) != MOT_OK)
     return fail(rc);
@@ -892,6 +892,7 @@ int mot_info(const mot_ctx* c, int64_t* out, int32_t n) {
   out[4] = c->kxs;
   out[5] = (int64_t)c->bytes;
   out[6] = c->nstep;
+  if (n >= 8) out[7] = c->blk_B;
   return MOT_OK;
 }
 

@@ -199,9 +199,9 @@ class Context:
             pass
 
     def info(self):
-        out = (ctypes.c_int64 * 7)()
-        self._check(LIB.mot_info(self.h, out, 7), "mot_info")
-        keys = ("nlags", "px", "py", "pz", "kxs", "bytes", "steps")
+        out = (ctypes.c_int64 * 8)()
+        self._check(LIB.mot_info(self.h, out, 8), "mot_info")
+        keys = ("nlags", "px", "py", "pz", "kxs", "bytes", "steps", "history_block")
         return dict(zip(keys, list(out)))
 
     def build_green_spectra(self):
