@@ -7,7 +7,7 @@
 // in ky, xz odd in kz, yz odd in both).
 //
 // Temporal blocking: at the start of a block of B steps (after J^_{n0} is
-// pushed; B = 8 for an FP32 ring, 2 for FP64) one pass over the ring computes
+// pushed; B = 8 for an FP32 ring, 4 for FP64) one pass over the ring computes
 // the contributions of all slots t <= n0 to the next B right-hand sides,
 //   P_b = sum_{m>=0} Lambda_{m+b} J^_{n0-m},   b = 1..B,
 // reading every slot and every Lambda_j once (a sliding window of B Lambda
@@ -224,6 +224,7 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
   if (f64) {
     if (B == 1) LB(double, 1, 4, gr);
     else if (B == 2) LB(double, 2, 4, gr);
+    else if (B == 4) LB(double, 4, 2, gr2);
     else return hipErrorInvalidValue;
   } else {
     if (B == 1) LB(float, 1, 4, gr);

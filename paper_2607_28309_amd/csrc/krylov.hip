@@ -33,6 +33,29 @@ __device__ __forceinline__ void block_partial(double v, double* partials) {
   }
 }
 
+// Two block sums -> partials[blockIdx.x] and partials[RED_BLOCKS + blockIdx.x].
+__device__ __forceinline__ void block_partial2(double v1, double v2, double* partials) {
+  __shared__ double red[2][RED_THREADS / 64];
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wid] = v1;
+    red[1][wid] = v2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RED_THREADS / 64; ++i) {
+      t1 += red[0][i];
+      t2 += red[1][i];
+    }
+    partials[blockIdx.x] = t1;
+    partials[RED_BLOCKS + blockIdx.x] = t2;
+  }
+}
+
 #define GRID_STRIDE(i, n) \
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
@@ -143,9 +166,8 @@ __device__ void post_op(double* scal, int post) {
   }
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
-                                                        int slot, int post, Gate g) {
-  if (motfft::gate_closed(g)) return;
+// Sum of RED_BLOCKS partials in a fixed order (every thread returns it).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partials) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partials[i];
   __shared__ double red[RED_THREADS];
@@ -155,9 +177,32 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
+                                                        int slot, int post, Gate g) {
+  if (motfft::gate_closed(g)) return;
+  const double sum = sum_partials(partials);
   if (threadIdx.x == 0) {
-    scal[slot] = red[0];
+    scal[slot] = sum;
     post_op(scal, post);
+  }
+}
+
+// Two sums (partials of block_partial2), then their scalar recurrences in order.
+__global__ __launch_bounds__(RED_THREADS) void k_reduce2(const double* __restrict__ partials, double* scal,
+                                                         int slot1, int post1, int slot2, int post2, Gate g) {
+  if (motfft::gate_closed(g)) return;
+  const double s1 = sum_partials(partials);
+  const double s2 = sum_partials(partials + RED_BLOCKS);
+  if (threadIdx.x == 0) {
+    scal[slot1] = s1;
+    scal[slot2] = s2;
+    post_op(scal, post1);
+    post_op(scal, post2);
   }
 }
 
@@ -259,15 +304,17 @@ __global__ __launch_bounds__(RED_THREADS) void k_half0(V* __restrict__ u2, const
   block_partial(acc, partials);
 }
 
-// second half step: x += eta d (first half's update); w -= alpha au2; d = u2 + dcoef d; |w|^2
+// second half step: x += eta d (first half's update); w -= alpha au2;
+// d = u2 + dcoef d; |w|^2 and w . rt (the next rho) in one pass
 template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_half1(V* __restrict__ x, V* __restrict__ w,
                                                        const V* __restrict__ au2, V* __restrict__ d,
-                                                       const V* __restrict__ u2, const double* __restrict__ scal,
-                                                       long long n, double* partials, Gate g) {
+                                                       const V* __restrict__ u2, const V* __restrict__ rt,
+                                                       const double* __restrict__ scal, long long n,
+                                                       double* partials, Gate g) {
   if (motfft::gate_closed(g)) return;
   const V alpha = (V)scal[S_ALPHA], dc = (V)scal[S_DCOEF], eta = (V)scal[S_ETA];
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   GRID_STRIDE(i, n) {
     const V di = d[i];
     x[i] += eta * di;
@@ -275,32 +322,22 @@ __global__ __launch_bounds__(RED_THREADS) void k_half1(V* __restrict__ x, V* __r
     w[i] = wi;
     d[i] = u2[i] + dc * di;
     acc += (double)wi * (double)wi;
+    acc2 += (double)wi * (double)rt[i];
   }
-  block_partial(acc, partials);
+  block_partial2(acc, acc2, partials);
 }
 
-// x += eta d (second half's update); w . rt
+// end of an iteration: x += eta d (second half's update, eta of the second
+// half step); u = w + beta u2
 template <typename V>
-__global__ __launch_bounds__(RED_THREADS) void k_rho(V* __restrict__ x, const V* __restrict__ d,
-                                                     const V* __restrict__ w, const V* __restrict__ rt,
-                                                     const double* __restrict__ scal, long long n,
-                                                     double* partials, Gate g) {
+__global__ void k_u(V* __restrict__ u, const V* __restrict__ w, const V* __restrict__ u2, V* __restrict__ x,
+                    const V* __restrict__ d, const double* __restrict__ scal, long long n, Gate g) {
   if (motfft::gate_closed(g)) return;
-  const V eta = (V)scal[S_ETA];
-  double acc = 0.0;
+  const V beta = (V)scal[S_BETA], eta = (V)scal[S_ETA];
   GRID_STRIDE(i, n) {
+    u[i] = w[i] + beta * u2[i];
     x[i] += eta * d[i];
-    acc += (double)w[i] * (double)rt[i];
   }
-  block_partial(acc, partials);
-}
-
-template <typename V>
-__global__ void k_u(V* __restrict__ u, const V* __restrict__ w, const V* __restrict__ u2,
-                    const double* __restrict__ scal, long long n, Gate g) {
-  if (motfft::gate_closed(g)) return;
-  const V beta = (V)scal[S_BETA];
-  GRID_STRIDE(i, n) u[i] = w[i] + beta * u2[i];
 }
 
 // v = au + beta (au2 + beta v); v . rt
@@ -350,6 +387,11 @@ hipError_t reduce_post(const double* partials, double* scal, int slot, int post,
   hipLaunchKernelGGL(k_reduce, dim3(1), RB(), 0, s, partials, scal, slot, post, g);
   return hipGetLastError();
 }
+hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,
+                        hipStream_t s, Gate g) {
+  hipLaunchKernelGGL(k_reduce2, dim3(1), RB(), 0, s, partials, scal, slot1, post1, slot2, post2, g);
+  return hipGetLastError();
+}
 hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s) {
   hipLaunchKernelGGL(k_solver_setup, dim3(1), dim3(64), 0, s, scal, tol, (double)max_iter);
   return hipGetLastError();
@@ -381,18 +423,14 @@ hipError_t tfqmr_half0(V* u2, const V* u, const V* v, V* w, const V* au, V* d, c
   LAUNCH(k_half0<V>, u2, u, v, w, au, d, scal, n, partials, g);
 }
 template <typename V>
-hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const double* scal, long long n,
+hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const V* rt, const double* scal, long long n,
                        double* partials, hipStream_t s, Gate g) {
-  LAUNCH(k_half1<V>, x, w, au2, d, u2, scal, n, partials, g);
+  LAUNCH(k_half1<V>, x, w, au2, d, u2, rt, scal, n, partials, g);
 }
 template <typename V>
-hipError_t tfqmr_rho(V* x, const V* d, const V* w, const V* rt, const double* scal, long long n, double* partials,
-                     hipStream_t s, Gate g) {
-  LAUNCH(k_rho<V>, x, d, w, rt, scal, n, partials, g);
-}
-template <typename V>
-hipError_t tfqmr_u(V* u, const V* w, const V* u2, const double* scal, long long n, hipStream_t s, Gate g) {
-  LAUNCH(k_u<V>, u, w, u2, scal, n, g);
+hipError_t tfqmr_u(V* u, const V* w, const V* u2, V* x, const V* d, const double* scal, long long n, hipStream_t s,
+                   Gate g) {
+  LAUNCH(k_u<V>, u, w, u2, x, d, scal, n, g);
 }
 template <typename V>
 hipError_t tfqmr_v(V* v, const V* au, const V* au2, const V* rt, const double* scal, long long n,
@@ -411,11 +449,10 @@ hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partial
   template hipError_t tfqmr_init<V>(const V*, V*, V*, V*, V*, V*, long long, hipStream_t);                    \
   template hipError_t tfqmr_half0<V>(V*, const V*, const V*, V*, const V*, V*, const double*, long long,       \
                                      double*, hipStream_t, Gate);                                             \
-  template hipError_t tfqmr_half1<V>(V*, V*, const V*, V*, const V*, const double*, long long, double*,        \
-                                     hipStream_t, Gate);                                                      \
-  template hipError_t tfqmr_rho<V>(V*, const V*, const V*, const V*, const double*, long long, double*,        \
-                                   hipStream_t, Gate);                                                        \
-  template hipError_t tfqmr_u<V>(V*, const V*, const V*, const double*, long long, hipStream_t, Gate);         \
+  template hipError_t tfqmr_half1<V>(V*, V*, const V*, V*, const V*, const V*, const double*, long long,      \
+                                     double*, hipStream_t, Gate);                                             \
+  template hipError_t tfqmr_u<V>(V*, const V*, const V*, V*, const V*, const double*, long long, hipStream_t,  \
+                                 Gate);                                                                       \
   template hipError_t tfqmr_v<V>(V*, const V*, const V*, const V*, const double*, long long, double*,          \
                                  hipStream_t, Gate);                                                          \
   template hipError_t tfqmr_v0<V>(V*, const V*, const V*, long long, double*, hipStream_t, Gate);

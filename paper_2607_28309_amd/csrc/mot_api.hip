@@ -361,17 +361,17 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
     HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], sc, n, P, st, RUN));
     HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF0, st, RUN));
     TRY(apply_z0(c, v[V_U2], v[V_AU2], RUN));
-    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], sc, n, P, st, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF1, st, RUN));
-    HTP(K_KRY, f64, tfqmr_rho<V>(x, v[V_D], v[V_W], v[V_RT], sc, n, P, st, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_RHONEW, POST_BETA, st, RUN));
+    // the second half step also forms w . rt, the next rho
+    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], v[V_RT], sc, n, P, st, RUN));
+    HTP(K_KRY, f64, reduce_post2(P, sc, S_W2, POST_HALF1, S_RHONEW, POST_BETA, st, RUN));
+    // u = w + beta u2 and the second half step's x update
+    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], x, v[V_D], sc, n, st, RUN));
     // true residual with the solver's own operator, only when asked for
     if (check) {
       TRY(apply_z0(c, x, v[V_TMP], CHK));
       HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, st, CHK));
       HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, st, CHK));
     }
-    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], sc, n, st, RUN));
     TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
     HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], sc, n, P, st, RUN));
     HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, st, RUN));
@@ -821,7 +821,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if ((rc = dmalloc(c, (void**)&c->lam0_32, sizeof(float) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->lamh, rsz * 6 * c->lam_comp * c->nl)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->spec, rsz * 2 * c->slot_elems)) != MOT_OK) return fail(rc);
-  c->blk_B = c->ring_f64 ? 2 : 8;
+  c->blk_B = c->ring_f64 ? 4 : 8;
   while (c->blk_B > c->nl) c->blk_B /= 2;
   c->blk_n0 = -1;
   if (c->blk_B > 1 && (rc = dmalloc(c, &c->pblk, rsz * 2 * c->slot_elems * (c->blk_B - 1))) != MOT_OK)
@@ -833,7 +833,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if (prec != MOT_F64)
     for (int i = 0; i < 11; ++i)
       if ((rc = dmalloc(c, (void**)&c->kf[i], sizeof(float) * c->n3)) != MOT_OK) return fail(rc);
-  if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * RED_BLOCKS)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * 2 * RED_BLOCKS)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->scal, sizeof(double) * S_NSLOT)) != MOT_OK) return fail(rc);
   if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 3 * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
     c->hscal = nullptr;
