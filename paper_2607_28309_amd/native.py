@@ -106,7 +106,9 @@ LIB = _load()
 
 def step_batch(contexts, eincs, Js, tol=1e-6, max_iter=1000, threads=None, allow=()):
     """One MOT step of every context (each on its own stream) by a pool of host
-    threads inside the library; returns (statuses, stats dicts)."""
+    threads inside the library (default min(contexts, 8): more threads than
+    that contend for the device's few hardware queues); returns (statuses,
+    stats dicts)."""
     import torch
     n = len(contexts)
     if not (len(eincs) == len(Js) == n) or n == 0:
@@ -116,7 +118,7 @@ def step_batch(contexts, eincs, Js, tol=1e-6, max_iter=1000, threads=None, allow
     j = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64, 3 * c.N) for x, c in zip(Js, contexts)])
     st = (MotStats * n)()
     status = (ctypes.c_int32 * n)()
-    rc = LIB.mot_step_batch(ctxs, n, e, j, float(tol), int(max_iter), st, status, int(threads or n))
+    rc = LIB.mot_step_batch(ctxs, n, e, j, float(tol), int(max_iter), st, status, int(threads or min(n, 8)))
     if rc != MOT_OK and rc not in allow:
         bad = [i for i in range(n) if status[i] != MOT_OK and status[i] not in allow]
         if bad:
