@@ -32,6 +32,40 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
   return g.mode == 2 && g.f[1] == 0.0;
 }
 
+// Solver work fused into the x passes of a Z0 product (TFQMR, Freund): the
+// vector updates that go with the product's input or output, done by the
+// thread that loads or stores each element, and their inner products as one
+// FP64 partial per workgroup (fixed grid and order: deterministic).  Vectors
+// are of the product's element type IO (= T); scalars are read from the
+// solver's FP64 slots.
+//   KRY_HALF0 (x forward; in = u):  x += etap d; u2 = u - alpha v;
+//       w -= alpha au; d = u + dcoef d (d before the update in both);
+//       the product's input is u2; partial |w|^2.
+//   KRY_U (x forward; in = w):  u = w + beta u2, the product's input.
+//   KRY_XFIX (x forward; in = x):  x += etap d, the product's input.
+//   KRY_HALF1 (x inverse; J = u2, y = au2):  x += eta d; w -= alpha au2;
+//       d = u2 + dcoef d; partials |w|^2 and w . rt.
+//   KRY_V (x inverse; y = au):  v = au + beta (au2 + beta v); partial v . rt.
+enum KryMode { KRY_NONE = 0, KRY_HALF0, KRY_U, KRY_XFIX, KRY_HALF1, KRY_V };
+struct Krylov {
+  int mode = KRY_NONE;
+  const double* alpha = nullptr;  // solver scalars (device)
+  const double* beta = nullptr;
+  const double* eta = nullptr;
+  const double* etap = nullptr;   // pending x update coefficient
+  const double* dcoef = nullptr;
+  void* x = nullptr;
+  void* d = nullptr;
+  void* w = nullptr;
+  void* v = nullptr;
+  void* au = nullptr;   // KRY_HALF0: au; KRY_V: au2
+  void* rt = nullptr;
+  void* out = nullptr;  // KRY_HALF0: u2; KRY_U: u
+  void* u2 = nullptr;   // KRY_U: u2
+  double* partials = nullptr;  // partials[b] (and partials[stride + b] for a second sum)
+  int stride = 0;
+};
+
 // Precision tags: T = compute type; IO = element type of real vectors.
 // Returns hipSuccess or an error; hipErrorInvalidValue for an unsupported length.
 // var: tile-shape variant, 0 (default) or 1 (see XCfg, YCfg, ZCfg, ZFCfg); the
@@ -44,10 +78,11 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
 // workgroup takes the same voxel rows of all three.  pre (optional, n_in =
 // M/2 only): per-voxel values indexed like the inverse pass's eps; the input
 // is multiplied by (pre - 1) on load.
+// kry: solver work fused into the pass (n_in = M/2 only, IO = T).
 template <typename T, typename IO>
 hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
                      int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s,
-                     const double* pre = nullptr, Gate g = Gate{}, int var = 0);
+                     const double* pre = nullptr, Gate g = Gate{}, int var = 0, const Krylov* kry = nullptr);
 
 // x pass, inverse with epilogue: rows of M+1 complex -> first n_out reals of
 // a length-2M real signal; y/J rows of row_len reals, eps indexed by
@@ -55,7 +90,12 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
 template <typename T, typename IO>
 hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
                      int nrows, int rows_per_comp, int ncomp, int row_len, int n_out, int kxs,
-                     const void* tw, const void* tw2, hipStream_t s, Gate g = Gate{}, int var = 0);
+                     const void* tw, const void* tw2, hipStream_t s, Gate g = Gate{}, int var = 0,
+                     const Krylov* kry = nullptr);
+
+// Workgroups of an x pass (forward and inverse alike): the number of partials
+// a fused solver sum leaves; 0 for an unsupported length or variant.
+int x_pass_blocks(int M, bool f64, int var, int nrows, int rows_per_comp, int ncomp);
 
 // y pass: `planes` planes; input rows_in rows (first n_in read), output
 // rows_out rows (first n_out written).

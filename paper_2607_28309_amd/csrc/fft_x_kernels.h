@@ -12,6 +12,8 @@
 // Lanes walk along a row (jt fastest), so row loads and stores are coalesced.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_impl.h"
 
 namespace motfft {
@@ -32,16 +34,42 @@ __device__ __forceinline__ int xrow(int p, int ncomp, int rows_per_comp, int nro
   return r < nrows ? r : nrows;
 }
 
+// Deterministic workgroup sums of NV values per thread: out[blockIdx.x]
+// (and out[stride + blockIdx.x]), by a tree in LDS `scratch` (2 BLOCK
+// doubles, free when called; every thread of the workgroup must call).
+template <int BLOCK, int NV>
+__device__ __forceinline__ void wg_sums(const double (&val)[NV], double* scratch, double* out, int stride) {
+  constexpr int P2 = BLOCK <= 1 ? 1 : 2 * floor_pow2(BLOCK - 1);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) scratch[k * BLOCK + t] = val[k];
+  __syncthreads();
+#pragma unroll
+  for (int h = P2 / 2; h > 0; h >>= 1) {
+    if (t < h && t + h < BLOCK)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) scratch[k * BLOCK + t] += scratch[k * BLOCK + t + h];
+    __syncthreads();
+  }
+  if (t == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[(size_t)k * stride + blockIdx.x] = scratch[k * BLOCK];
+}
+
 // pre (optional, per voxel row like the epilogue's permittivity): the input
 // is multiplied by (pre - 1) as it is loaded, i.e. the contrast applied on the
 // input for the transposed operators.
-template <typename T, typename IO, int M, bool HIN, int V>
+//
+// KM: solver work fused into the loads (see Krylov); the thread that loads a
+// pair of elements updates the solver vectors there.
+template <typename T, typename IO, int M, bool HIN, int V, int KM>
 __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* __restrict__ in,
                                                                   cpx<T>* __restrict__ out, int nrows,
                                                                   int rows_per_comp, int ncomp, int row_len,
                                                                   int kxs, const cpx<T>* __restrict__ tw_g,
                                                                   const cpx<T>* __restrict__ tw2_g,
-                                                                  const double* __restrict__ pre, Gate gate) {
+                                                                  const double* __restrict__ pre, Gate gate,
+                                                                  Krylov kry) {
   using C = XCfg<T, M, V>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
   if (gate_closed(gate)) return;
@@ -53,46 +81,134 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
   const int jt = threadIdx.x % TJ, p = threadIdx.x / TJ;
   const int grow = xrow<NP>(p, ncomp, rows_per_comp, nrows);
   const bool valid = grow < nrows;
-  const IO* src = in + (size_t)(valid ? grow : 0) * row_len + 2 * jt;
+  const size_t ro = (size_t)(valid ? grow : 0) * row_len + 2 * jt;
+  const IO* src = in + ro;
   const double* prow = pre ? pre + (size_t)((valid ? grow : 0) % rows_per_comp) * row_len + 2 * jt : nullptr;
+  IO ka = 0, kb = 0, kep = 0, kdc = 0;
+  if constexpr (KM == KRY_HALF0) {
+    ka = (IO)*kry.alpha;
+    kep = (IO)*kry.etap;
+    kdc = (IO)*kry.dcoef;
+  }
+  if constexpr (KM == KRY_U) kb = (IO)*kry.beta;
+  if constexpr (KM == KRY_XFIX) kep = (IO)*kry.etap;
+  double acc = 0.0;
   cpx<T> v[E];
-  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) {
-    const V2 pr = *reinterpret_cast<const V2*>(src + 2 * u);
+  auto contrast = [&](V2 pr, int u) {
     if (prow) {
       const double2 x2 = *reinterpret_cast<const double2*>(prow + 2 * u);
       return cpx<T>{(T)((double)pr.x * (x2.x - 1.0)), (T)((double)pr.y * (x2.y - 1.0))};
     }
     return cpx<T>{(T)pr.x, (T)pr.y};
-  });
+  };
+  if constexpr (KM == KRY_NONE) {
+    load_first<T, M, HIN>(v, p, jt,
+                          [&](int, int, int u) { return contrast(*reinterpret_cast<const V2*>(src + 2 * u), u); });
+  } else {
+    // the elements load_first would load (lower half: element jt + u,
+    // u = t TJ + r M/R0, register t R0 + r), in chunks of CH: all operand
+    // loads of a chunk are issued before its stores
+    static_assert(HIN, "solver work rides on the product form");
+    constexpr int R0 = PlanInfo<M>::R0, MR = M / R0, HR = R0 / 2, NL = (M / (R0 * TJ)) * HR;
+    constexpr int CH = NL < 4 ? NL : 4;
+    const IO* kin = KM == KRY_XFIX ? (const IO*)kry.x : in;
+#pragma unroll
+    for (int l0 = 0; l0 < NL; l0 += CH) {
+      V2 a0[CH], a1[CH], a2[CH], a3[CH], a4[CH], a5[CH];
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        const int l = l0 + cc;
+        if (l >= NL) break;
+        const int u = (l / HR) * TJ + (l % HR) * MR;
+        const size_t o = ro + 2 * u;
+        a0[cc] = *reinterpret_cast<const V2*>(kin + o);
+        if constexpr (KM == KRY_HALF0) {
+          a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.v + o);
+          a2[cc] = *reinterpret_cast<const V2*>((const IO*)kry.w + o);
+          a3[cc] = *reinterpret_cast<const V2*>((const IO*)kry.au + o);
+          a4[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
+          a5[cc] = *reinterpret_cast<const V2*>((const IO*)kry.x + o);
+        } else if constexpr (KM == KRY_U) {
+          a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.u2 + o);
+        } else {
+          a4[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        const int l = l0 + cc;
+        if (l >= NL) break;
+        const int u = (l / HR) * TJ + (l % HR) * MR;
+        const size_t o = ro + 2 * u;
+        V2 pr;
+        if constexpr (KM == KRY_HALF0) {
+          // a0 = u, a1 = v, a2 = w, a3 = au, a4 = d, a5 = x
+          V2 ww, dd, xx;
+          xx.x = a5[cc].x + kep * a4[cc].x;
+          xx.y = a5[cc].y + kep * a4[cc].y;
+          pr.x = a0[cc].x - ka * a1[cc].x;
+          pr.y = a0[cc].y - ka * a1[cc].y;
+          ww.x = a2[cc].x - ka * a3[cc].x;
+          ww.y = a2[cc].y - ka * a3[cc].y;
+          dd.x = a0[cc].x + kdc * a4[cc].x;
+          dd.y = a0[cc].y + kdc * a4[cc].y;
+          if (valid) {
+            *reinterpret_cast<V2*>((IO*)kry.x + o) = xx;
+            *reinterpret_cast<V2*>((IO*)kry.out + o) = pr;
+            *reinterpret_cast<V2*>((IO*)kry.w + o) = ww;
+            *reinterpret_cast<V2*>((IO*)kry.d + o) = dd;
+            acc += (double)ww.x * (double)ww.x + (double)ww.y * (double)ww.y;
+          }
+        } else if constexpr (KM == KRY_U) {  // a0 = w, a1 = u2
+          pr.x = a0[cc].x + kb * a1[cc].x;
+          pr.y = a0[cc].y + kb * a1[cc].y;
+          if (valid) *reinterpret_cast<V2*>((IO*)kry.out + o) = pr;
+        } else {  // KRY_XFIX: a0 = x, a4 = d
+          pr.x = a0[cc].x + kep * a4[cc].x;
+          pr.y = a0[cc].y + kep * a4[cc].y;
+          if (valid) *reinterpret_cast<V2*>((IO*)kry.x + o) = pr;
+        }
+        v[(l / HR) * R0 + (l % HR)] = contrast(pr, u);
+      }
+    }
+  }
   load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
   load_table<cpx<T>, M + 1, C::BLOCK>(tw2, tw2_g);
   run_fft<T, M, false, HIN, false>(v, lds, tw, p, jt, NPS,
                                    [&](int pp, int, int u, cpx<T> val) { lds[(jt + u) * NPS + pp] = val; });
   __syncthreads();
-  if (!valid) return;
-  // bins k = jt + TJ i of row p (and k = M by lane jt = 0)
-  cpx<T>* dst = out + (size_t)grow * kxs + jt;
-  const cpx<T>* zr = lds + p;
-  auto unpack = [&](cpx<T> zk, cpx<T> zm, cpx<T> w) {
-    // E = (zk + conj zm)/2, O = -i/2 (zk - conj zm), X = E + w O
-    const cpx<T> ev{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
-    const cpx<T> od{(T)0.5 * (zk.y + zm.y), (T)-0.5 * (zk.x - zm.x)};
-    return cadd(ev, cmul(w, od));
-  };
+  if (valid) {
+    // bins k = jt + TJ i of row p (and k = M by lane jt = 0)
+    cpx<T>* dst = out + (size_t)grow * kxs + jt;
+    const cpx<T>* zr = lds + p;
+    auto unpack = [&](cpx<T> zk, cpx<T> zm, cpx<T> w) {
+      // E = (zk + conj zm)/2, O = -i/2 (zk - conj zm), X = E + w O
+      const cpx<T> ev{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+      const cpx<T> od{(T)0.5 * (zk.y + zm.y), (T)-0.5 * (zk.x - zm.x)};
+      return cadd(ev, cmul(w, od));
+    };
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int k = jt + TJ * i;
-    const int m = i == 0 ? (jt == 0 ? 0 : M - jt) : M - k;
-    dst[TJ * i] = unpack(zr[k * NPS], zr[m * NPS], tw2[k]);
+    for (int i = 0; i < E; ++i) {
+      const int k = jt + TJ * i;
+      const int m = i == 0 ? (jt == 0 ? 0 : M - jt) : M - k;
+      dst[TJ * i] = unpack(zr[k * NPS], zr[m * NPS], tw2[k]);
+    }
+    if (jt == 0) dst[M] = unpack(zr[0], zr[0], tw2[M]);
   }
-  if (jt == 0) dst[M] = unpack(zr[0], zr[0], tw2[M]);
+  if constexpr (KM == KRY_HALF0) {
+    __syncthreads();  // the unpack's LDS reads are done: LDS holds the sums
+    const double val[1] = {acc};
+    wg_sums<C::BLOCK, 1>(val, reinterpret_cast<double*>(smem_raw), kry.partials, kry.stride);
+  }
 }
 
-template <typename T, typename IO, int M, int V>
+// KM: solver work fused into the stores (see Krylov); the thread that
+// writes a pair of y elements updates the solver vectors there.
+template <typename T, typename IO, int M, int V, int KM>
 __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     const cpx<T>* __restrict__ in, IO* __restrict__ y, const IO* __restrict__ J,
     const double* __restrict__ eps, Epilogue ep, int nrows, int rows_per_comp, int ncomp, int row_len,
-    int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g, Gate gate) {
+    int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g, Gate gate, Krylov kry) {
   using C = XCfg<T, M, V>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
   if (gate_closed(gate)) return;
@@ -141,6 +257,15 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   });
   __syncthreads();
   IO* yrow = y + roff;
+  IO ka = 0, kb = 0, ke = 0, kdc = 0;
+  if constexpr (KM == KRY_HALF1) {
+    ka = (IO)*kry.alpha;
+    ke = (IO)*kry.eta;
+    kdc = (IO)*kry.dcoef;
+  }
+  if constexpr (KM == KRY_V) kb = (IO)*kry.beta;
+  double acc1 = 0.0, acc2 = 0.0;
+  V2 yo[KM == KRY_NONE ? 1 : EH];  // the y pairs this lane wrote (solver forms)
   run_fft<T, M, true, false, true>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> z) {
     if (!valid) return;
     const int i = u / TJ;
@@ -150,7 +275,70 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     r.x = (IO)(((T)(ep.ca * e2.x + ep.c0)) * (T)j2.x + ((T)(ep.cb * e2.x + ep.cb0)) * z.x);
     r.y = (IO)(((T)(ep.ca * e2.y + ep.c0)) * (T)j2.y + ((T)(ep.cb * e2.y + ep.cb0)) * z.y);
     *reinterpret_cast<V2*>(yrow + 2 * u) = r;
+    if constexpr (KM != KRY_NONE) yo[i] = r;
   });
+  if constexpr (KM != KRY_NONE) {
+    // pairs n = jt + TJ i of the row, in chunks of CH: all operand loads of a
+    // chunk are issued before its stores
+    constexpr int CH = EH < 4 ? EH : 4;
+    if (valid) {
+#pragma unroll
+      for (int i0 = 0; i0 < EH; i0 += CH) {
+        V2 a0[CH], a1[CH], a2[CH], a3[CH];
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          const int i = i0 + cc;
+          if (i >= EH) break;
+          const size_t o = roff + 2 * TJ * i;
+          if constexpr (KM == KRY_HALF1) {
+            a0[cc] = *reinterpret_cast<const V2*>((const IO*)kry.x + o);
+            a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.w + o);
+            a2[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
+            a3[cc] = *reinterpret_cast<const V2*>((const IO*)kry.rt + o);
+          } else {
+            a0[cc] = *reinterpret_cast<const V2*>((const IO*)kry.au + o);
+            a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.v + o);
+            a3[cc] = *reinterpret_cast<const V2*>((const IO*)kry.rt + o);
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          const int i = i0 + cc;
+          if (i >= EH) break;
+          const size_t o = roff + 2 * TJ * i;
+          const V2 r = yo[i];
+          if constexpr (KM == KRY_HALF1) {  // r = au2, jv = u2; a0 = x, a1 = w, a2 = d, a3 = rt
+            V2 xx, ww, dd;
+            xx.x = a0[cc].x + ke * a2[cc].x;
+            xx.y = a0[cc].y + ke * a2[cc].y;
+            ww.x = a1[cc].x - ka * r.x;
+            ww.y = a1[cc].y - ka * r.y;
+            dd.x = jv[i].x + kdc * a2[cc].x;
+            dd.y = jv[i].y + kdc * a2[cc].y;
+            *reinterpret_cast<V2*>((IO*)kry.x + o) = xx;
+            *reinterpret_cast<V2*>((IO*)kry.w + o) = ww;
+            *reinterpret_cast<V2*>((IO*)kry.d + o) = dd;
+            acc1 += (double)ww.x * (double)ww.x + (double)ww.y * (double)ww.y;
+            acc2 += (double)ww.x * (double)a3[cc].x + (double)ww.y * (double)a3[cc].y;
+          } else {  // KRY_V: r = au; a0 = au2, a1 = v, a3 = rt
+            V2 vv;
+            vv.x = r.x + kb * (a0[cc].x + kb * a1[cc].x);
+            vv.y = r.y + kb * (a0[cc].y + kb * a1[cc].y);
+            *reinterpret_cast<V2*>((IO*)kry.v + o) = vv;
+            acc1 += (double)vv.x * (double)a3[cc].x + (double)vv.y * (double)a3[cc].y;
+          }
+        }
+      }
+    }
+  }
+  // the last stage's exchange ended with a barrier: LDS is free for the sums
+  if constexpr (KM == KRY_HALF1) {
+    const double val[2] = {acc1, acc2};
+    wg_sums<C::BLOCK, 2>(val, reinterpret_cast<double*>(smem_raw), kry.partials, kry.stride);
+  } else if constexpr (KM == KRY_V) {
+    const double val[1] = {acc1};
+    wg_sums<C::BLOCK, 1>(val, reinterpret_cast<double*>(smem_raw), kry.partials, kry.stride);
+  }
 }
 
 template <int NP>
@@ -159,14 +347,15 @@ static int x_blocks(int nrows, int rows_per_comp, int ncomp) {
 }
 
 // Supported forms: n_in = M/2 (product: rows of M reals) or n_in = M (FP64
-// only, spectra precompute: rows of 2M reals; tile variant 0 only).
-template <typename T, typename IO, int V>
+// only, spectra precompute: rows of 2M reals; tile variant 0 only).  KM != 0
+// (solver work, IO = T): the product form only.
+template <typename T, typename IO, int V, int KM>
 hipError_t x_forward_v(const IO* in, void* out, int M, int nrows, int rows_per_comp, int ncomp, int row_len,
                        int n_in, int kxs, const void* tw, const void* tw2, hipStream_t s, const double* pre,
-                       Gate gg) {
+                       Gate gg, const Krylov& kry) {
   const bool half = 2 * n_in == M;
-  if ((!half && n_in != M) || (!half && (sizeof(T) != 8 || V != 0)) || 2 * n_in > row_len || kxs < M + 1 ||
-      (pre && !half))
+  if ((!half && n_in != M) || (!half && (sizeof(T) != 8 || V != 0 || KM != KRY_NONE)) || 2 * n_in > row_len ||
+      kxs < M + 1 || (pre && !half))
     return hipErrorInvalidValue;
   switch (M) {
 #define X(m)                                                                                              \
@@ -174,11 +363,13 @@ hipError_t x_forward_v(const IO* in, void* out, int M, int nrows, int rows_per_c
     using C = XCfg<T, m, V>;                                                                              \
     const dim3 g(x_blocks<C::NP>(nrows, rows_per_comp, ncomp));                                           \
     if (half)                                                                                             \
-      hipLaunchKernelGGL((k_x_forward<T, IO, m, true, V>), g, dim3(C::BLOCK), C::LDS, s, in, (cpx<T>*)out, \
-                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, pre, gg); \
-    else if constexpr (sizeof(T) == 8 && sizeof(IO) == 8 && V == 0)                                      \
-      hipLaunchKernelGGL((k_x_forward<T, IO, m, false, V>), g, dim3(C::BLOCK), C::LDS, s, in, (cpx<T>*)out, \
-                         nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, nullptr, gg); \
+      hipLaunchKernelGGL((k_x_forward<T, IO, m, true, V, KM>), g, dim3(C::BLOCK), C::LDS, s, in,           \
+                         (cpx<T>*)out, nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw,        \
+                         (const cpx<T>*)tw2, pre, gg, kry);                                               \
+    else if constexpr (sizeof(T) == 8 && sizeof(IO) == 8 && V == 0 && KM == KRY_NONE)                    \
+      hipLaunchKernelGGL((k_x_forward<T, IO, m, false, V, KM>), g, dim3(C::BLOCK), C::LDS, s, in,          \
+                         (cpx<T>*)out, nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw,        \
+                         (const cpx<T>*)tw2, nullptr, gg, kry);                                           \
     return hipGetLastError();                                                                             \
   }
     MOT_FOR_EACH_LEN(X)
@@ -189,18 +380,19 @@ hipError_t x_forward_v(const IO* in, void* out, int M, int nrows, int rows_per_c
 }
 
 // Supported form: n_out = M reals (the physical half of the length-2M row).
-template <typename T, typename IO, int V>
+template <typename T, typename IO, int V, int KM>
 hipError_t x_inverse_v(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M, int nrows,
                        int rows_per_comp, int ncomp, int row_len, int n_out, int kxs, const void* tw,
-                       const void* tw2, hipStream_t s, Gate gg) {
+                       const void* tw2, hipStream_t s, Gate gg, const Krylov& kry) {
   if (n_out != M || row_len < M || kxs < M + 1) return hipErrorInvalidValue;
   switch (M) {
 #define X(m)                                                                                            \
   case m: {                                                                                             \
     using C = XCfg<T, m, V>;                                                                            \
     const dim3 g(x_blocks<C::NP>(nrows, rows_per_comp, ncomp));                                         \
-    hipLaunchKernelGGL((k_x_inverse<T, IO, m, V>), g, dim3(C::BLOCK), C::LDS, s, (const cpx<T>*)in, y, J, eps, \
-                       ep, nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw, (const cpx<T>*)tw2, gg); \
+    hipLaunchKernelGGL((k_x_inverse<T, IO, m, V, KM>), g, dim3(C::BLOCK), C::LDS, s, (const cpx<T>*)in, y, J, \
+                       eps, ep, nrows, rows_per_comp, ncomp, row_len, kxs, (const cpx<T>*)tw,             \
+                       (const cpx<T>*)tw2, gg, kry);                                                    \
     return hipGetLastError();                                                                           \
   }
     MOT_FOR_EACH_LEN(X)
@@ -210,16 +402,42 @@ hipError_t x_inverse_v(const void* in, IO* y, const IO* J, const double* eps, Ep
   }
 }
 
-// Explicit instantiations of one tile variant (each variant has its own
-// translation unit so that they compile in parallel).
+template <int V>
+int x_pass_blocks_v(int M, bool f64, int nrows, int rows_per_comp, int ncomp) {
+  switch (M) {
+#define X(m)                                                                                            \
+  case m:                                                                                               \
+    return f64 ? x_blocks<XCfg<double, m, V>::NP>(nrows, rows_per_comp, ncomp)                          \
+               : x_blocks<XCfg<float, m, V>::NP>(nrows, rows_per_comp, ncomp);
+    MOT_FOR_EACH_LEN(X)
+#undef X
+    default:
+      return 0;
+  }
+}
+
+// Explicit instantiations of one tile variant (each variant, and the solver
+// forms, have their own translation units so that they compile in parallel).
+#define MOT_X_FWD(T, IO, V, KM)                                                                                \
+  template hipError_t x_forward_v<T, IO, V, KM>(const IO*, void*, int, int, int, int, int, int, int,            \
+                                                const void*, const void*, hipStream_t, const double*, Gate,     \
+                                                const Krylov&);
+#define MOT_X_INV(T, IO, V, KM)                                                                                \
+  template hipError_t x_inverse_v<T, IO, V, KM>(const void*, IO*, const IO*, const double*, Epilogue, int, int, \
+                                                int, int, int, int, int, const void*, const void*,              \
+                                                hipStream_t, Gate, const Krylov&);
 #define MOT_X_VARIANT(V)                                                                                       \
-  MOT_X_VARIANT_T(float, float, V)                                                                             \
-  MOT_X_VARIANT_T(float, double, V)                                                                            \
-  MOT_X_VARIANT_T(double, double, V)
-#define MOT_X_VARIANT_T(T, IO, V)                                                                              \
-  template hipError_t x_forward_v<T, IO, V>(const IO*, void*, int, int, int, int, int, int, int, const void*,  \
-                                            const void*, hipStream_t, const double*, Gate);                    \
-  template hipError_t x_inverse_v<T, IO, V>(const void*, IO*, const IO*, const double*, Epilogue, int, int,    \
-                                            int, int, int, int, int, const void*, const void*, hipStream_t, Gate);
+  MOT_X_FWD(float, float, V, KRY_NONE)                                                                         \
+  MOT_X_FWD(float, double, V, KRY_NONE)                                                                        \
+  MOT_X_FWD(double, double, V, KRY_NONE)                                                                       \
+  MOT_X_INV(float, float, V, KRY_NONE)                                                                         \
+  MOT_X_INV(float, double, V, KRY_NONE)                                                                        \
+  MOT_X_INV(double, double, V, KRY_NONE)
+#define MOT_X_SOLVER_T(T, V)                                                                                   \
+  MOT_X_FWD(T, T, V, KRY_HALF0)                                                                                \
+  MOT_X_FWD(T, T, V, KRY_U)                                                                                    \
+  MOT_X_FWD(T, T, V, KRY_XFIX)                                                                                 \
+  MOT_X_INV(T, T, V, KRY_HALF1)                                                                                \
+  MOT_X_INV(T, T, V, KRY_V)
 
 }  // namespace motfft

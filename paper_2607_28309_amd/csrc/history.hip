@@ -120,18 +120,22 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
 // P_1 -> out0, P_b -> pblk + (b-2) * slot for b >= 2.  NM = 4: a thread takes
 // all four mirror points of its octant frequency; NM = 2 (for long blocks,
 // whose B accumulators per point would not fit the registers): the two
-// threads of a frequency take one kz side each, in the two halves of the
-// workgroup, and read the same Lambda words.  Two waves per SIMD at least
+// threads of a frequency take one kz side each and read the same Lambda
+// words.  Two waves per SIMD at least
 // (a register budget of 256).
 template <typename T, int B, int NM>
 __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
                                                    cpx<T>* __restrict__ out0, cpx<T>* __restrict__ pblk, Geo g,
                                                    long long n0, int nold) {
-  constexpr int PER = NM == 4 ? 256 : 128;  // octant frequencies per workgroup
+  // octant frequencies per workgroup; with NM = 2 the two kz sides of a
+  // frequency are neighbouring lanes of one wave, which read its Lambda words
+  // with the same instruction
+  constexpr int PER = NM == 4 ? 256 : 128;
   size_t lo;
   Point<NM> pt;
-  const long long id = (long long)blockIdx.x * PER + (int)threadIdx.x % PER;
-  if (!octant_point<NM>(g, id, (int)threadIdx.x / PER, lo, pt)) return;
+  const int t = (int)threadIdx.x;
+  const long long id = (long long)blockIdx.x * PER + (NM == 4 ? t : t >> 1);
+  if (!octant_point<NM>(g, id, NM == 4 ? 0 : (t & 1), lo, pt)) return;
   const size_t comp = (size_t)(2 * g.nz) * (2 * g.ny) * g.kxs;
   const size_t slot = 3 * comp;
   const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;

@@ -33,29 +33,6 @@ __device__ __forceinline__ void block_partial(double v, double* partials) {
   }
 }
 
-// Two block sums -> partials[blockIdx.x] and partials[RED_BLOCKS + blockIdx.x].
-__device__ __forceinline__ void block_partial2(double v1, double v2, double* partials) {
-  __shared__ double red[2][RED_THREADS / 64];
-  v1 = wave_sum(v1);
-  v2 = wave_sum(v2);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][wid] = v1;
-    red[1][wid] = v2;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t1 = 0.0, t2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < RED_THREADS / 64; ++i) {
-      t1 += red[0][i];
-      t2 += red[1][i];
-    }
-    partials[blockIdx.x] = t1;
-    partials[RED_BLOCKS + blockIdx.x] = t2;
-  }
-}
-
 #define GRID_STRIDE(i, n) \
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
@@ -79,6 +56,7 @@ __device__ void post_op(double* scal, int post) {
       scal[S_ETA] = 0.0;
       scal[S_FLAG] = 0.0;
       scal[S_DCOEF] = 0.0;
+      scal[S_ETAP] = 0.0;
       if (!isfinite(b2)) {  // nothing to iterate on
         scal[S_STATUS] = (double)MOT_ENONFINITE;
         scal[S_DONE] = 1.0;
@@ -128,6 +106,9 @@ __device__ void post_op(double* scal, int post) {
         scal[S_BETA] = rn / rho;
         scal[S_RHO] = rn;
       }
+      // the second half step's x update (x += eta d) is applied by the next
+      // iteration's first product, or by the residual check
+      scal[S_ETAP] = scal[S_ETA];
       const double it = scal[S_ITER] + 1.0;
       scal[S_ITER] = it;
       // quasi-residual bound tau sqrt(2m + 1); its passing, a breakdown or the
@@ -141,10 +122,11 @@ __device__ void post_op(double* scal, int post) {
       }
       break;
     }
-    case POST_RESID: {  // true residual |b - A x|^2 in S_R2
+    case POST_RESID: {  // true residual |b - A x|^2 in S_R2 (the check applied the pending x update)
       const double rel = sqrt(scal[S_R2]) / scal[S_BNORM];
       scal[S_RELRES] = rel;
       scal[S_NMV] += 1.0;
+      scal[S_ETAP] = 0.0;
       if (!isfinite(rel)) {
         scal[S_STATUS] = (double)MOT_ENONFINITE;
         scal[S_DONE] = 1.0;
@@ -166,10 +148,10 @@ __device__ void post_op(double* scal, int post) {
   }
 }
 
-// Sum of RED_BLOCKS partials in a fixed order (every thread returns it).
-__device__ __forceinline__ double sum_partials(const double* __restrict__ partials) {
+// Sum of nparts partials in a fixed order (every thread returns it).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int nparts) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < RED_BLOCKS; i += RED_THREADS) acc += partials[i];
+  for (int i = threadIdx.x; i < nparts; i += RED_THREADS) acc += partials[i];
   __shared__ double red[RED_THREADS];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -183,21 +165,23 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
-                                                        int slot, int post, Gate g) {
+                                                        int slot, int post, Gate g, int nparts) {
   if (motfft::gate_closed(g)) return;
-  const double sum = sum_partials(partials);
+  const double sum = sum_partials(partials, nparts);
   if (threadIdx.x == 0) {
     scal[slot] = sum;
     post_op(scal, post);
   }
 }
 
-// Two sums (partials of block_partial2), then their scalar recurrences in order.
+// Two sums (partials[0, nparts) and [stride, stride + nparts)), then their
+// scalar recurrences in order.
 __global__ __launch_bounds__(RED_THREADS) void k_reduce2(const double* __restrict__ partials, double* scal,
-                                                         int slot1, int post1, int slot2, int post2, Gate g) {
+                                                         int slot1, int post1, int slot2, int post2, Gate g,
+                                                         int nparts, int stride) {
   if (motfft::gate_closed(g)) return;
-  const double s1 = sum_partials(partials);
-  const double s2 = sum_partials(partials + RED_BLOCKS);
+  const double s1 = sum_partials(partials, nparts);
+  const double s2 = sum_partials(partials + stride, nparts);
   if (threadIdx.x == 0) {
     scal[slot1] = s1;
     scal[slot2] = s2;
@@ -283,80 +267,6 @@ __global__ void k_tfqmr_init(const V* __restrict__ r0, V* __restrict__ w, V* __r
   }
 }
 
-// first half step: u2 = u - alpha v; w -= alpha au; d = u + dcoef d; |w|^2
-template <typename V>
-__global__ __launch_bounds__(RED_THREADS) void k_half0(V* __restrict__ u2, const V* __restrict__ u,
-                                                       const V* __restrict__ v, V* __restrict__ w,
-                                                       const V* __restrict__ au, V* __restrict__ d,
-                                                       const double* __restrict__ scal, long long n,
-                                                       double* partials, Gate g) {
-  if (motfft::gate_closed(g)) return;
-  const V alpha = (V)scal[S_ALPHA], dc = (V)scal[S_DCOEF];
-  double acc = 0.0;
-  GRID_STRIDE(i, n) {
-    const V ui = u[i];
-    u2[i] = ui - alpha * v[i];
-    const V wi = w[i] - alpha * au[i];
-    w[i] = wi;
-    d[i] = ui + dc * d[i];
-    acc += (double)wi * (double)wi;
-  }
-  block_partial(acc, partials);
-}
-
-// second half step: x += eta d (first half's update); w -= alpha au2;
-// d = u2 + dcoef d; |w|^2 and w . rt (the next rho) in one pass
-template <typename V>
-__global__ __launch_bounds__(RED_THREADS) void k_half1(V* __restrict__ x, V* __restrict__ w,
-                                                       const V* __restrict__ au2, V* __restrict__ d,
-                                                       const V* __restrict__ u2, const V* __restrict__ rt,
-                                                       const double* __restrict__ scal, long long n,
-                                                       double* partials, Gate g) {
-  if (motfft::gate_closed(g)) return;
-  const V alpha = (V)scal[S_ALPHA], dc = (V)scal[S_DCOEF], eta = (V)scal[S_ETA];
-  double acc = 0.0, acc2 = 0.0;
-  GRID_STRIDE(i, n) {
-    const V di = d[i];
-    x[i] += eta * di;
-    const V wi = w[i] - alpha * au2[i];
-    w[i] = wi;
-    d[i] = u2[i] + dc * di;
-    acc += (double)wi * (double)wi;
-    acc2 += (double)wi * (double)rt[i];
-  }
-  block_partial2(acc, acc2, partials);
-}
-
-// end of an iteration: x += eta d (second half's update, eta of the second
-// half step); u = w + beta u2
-template <typename V>
-__global__ void k_u(V* __restrict__ u, const V* __restrict__ w, const V* __restrict__ u2, V* __restrict__ x,
-                    const V* __restrict__ d, const double* __restrict__ scal, long long n, Gate g) {
-  if (motfft::gate_closed(g)) return;
-  const V beta = (V)scal[S_BETA], eta = (V)scal[S_ETA];
-  GRID_STRIDE(i, n) {
-    u[i] = w[i] + beta * u2[i];
-    x[i] += eta * d[i];
-  }
-}
-
-// v = au + beta (au2 + beta v); v . rt
-template <typename V>
-__global__ __launch_bounds__(RED_THREADS) void k_v(V* __restrict__ v, const V* __restrict__ au,
-                                                   const V* __restrict__ au2, const V* __restrict__ rt,
-                                                   const double* __restrict__ scal, long long n,
-                                                   double* partials, Gate g) {
-  if (motfft::gate_closed(g)) return;
-  const V beta = (V)scal[S_BETA];
-  double acc = 0.0;
-  GRID_STRIDE(i, n) {
-    const V vi = au[i] + beta * (au2[i] + beta * v[i]);
-    v[i] = vi;
-    acc += (double)vi * (double)rt[i];
-  }
-  block_partial(acc, partials);
-}
-
 // v = au (start); v . rt
 template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_v0(V* __restrict__ v, const V* __restrict__ au,
@@ -383,13 +293,17 @@ template <typename V>
 hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s) {
   LAUNCH(k_dot<V>, a, b, n, partials);
 }
-hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), RB(), 0, s, partials, scal, slot, post, g);
+hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g,
+                       int nparts) {
+  if (nparts < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce, dim3(1), RB(), 0, s, partials, scal, slot, post, g, nparts);
   return hipGetLastError();
 }
 hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,
-                        hipStream_t s, Gate g) {
-  hipLaunchKernelGGL(k_reduce2, dim3(1), RB(), 0, s, partials, scal, slot1, post1, slot2, post2, g);
+                        hipStream_t s, Gate g, int nparts, int stride) {
+  if (nparts < 1 || stride < nparts) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce2, dim3(1), RB(), 0, s, partials, scal, slot1, post1, slot2, post2, g, nparts,
+                     stride);
   return hipGetLastError();
 }
 hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s) {
@@ -418,26 +332,6 @@ hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, h
   LAUNCH(k_tfqmr_init<V>, r0, w, u, rt, d, x, n);
 }
 template <typename V>
-hipError_t tfqmr_half0(V* u2, const V* u, const V* v, V* w, const V* au, V* d, const double* scal, long long n,
-                       double* partials, hipStream_t s, Gate g) {
-  LAUNCH(k_half0<V>, u2, u, v, w, au, d, scal, n, partials, g);
-}
-template <typename V>
-hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const V* rt, const double* scal, long long n,
-                       double* partials, hipStream_t s, Gate g) {
-  LAUNCH(k_half1<V>, x, w, au2, d, u2, rt, scal, n, partials, g);
-}
-template <typename V>
-hipError_t tfqmr_u(V* u, const V* w, const V* u2, V* x, const V* d, const double* scal, long long n, hipStream_t s,
-                   Gate g) {
-  LAUNCH(k_u<V>, u, w, u2, x, d, scal, n, g);
-}
-template <typename V>
-hipError_t tfqmr_v(V* v, const V* au, const V* au2, const V* rt, const double* scal, long long n,
-                   double* partials, hipStream_t s, Gate g) {
-  LAUNCH(k_v<V>, v, au, au2, rt, scal, n, partials, g);
-}
-template <typename V>
 hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials, hipStream_t s, Gate g) {
   LAUNCH(k_v0<V>, v, au, rt, n, partials, g);
 }
@@ -447,14 +341,6 @@ hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partial
   template hipError_t vec_sub<V>(const V*, const V*, V*, long long, double*, hipStream_t, Gate);              \
   template hipError_t vec_zero<V>(V*, long long, hipStream_t);                                                \
   template hipError_t tfqmr_init<V>(const V*, V*, V*, V*, V*, V*, long long, hipStream_t);                    \
-  template hipError_t tfqmr_half0<V>(V*, const V*, const V*, V*, const V*, V*, const double*, long long,       \
-                                     double*, hipStream_t, Gate);                                             \
-  template hipError_t tfqmr_half1<V>(V*, V*, const V*, V*, const V*, const V*, const double*, long long,      \
-                                     double*, hipStream_t, Gate);                                             \
-  template hipError_t tfqmr_u<V>(V*, const V*, const V*, V*, const V*, const double*, long long, hipStream_t,  \
-                                 Gate);                                                                       \
-  template hipError_t tfqmr_v<V>(V*, const V*, const V*, const V*, const double*, long long, double*,          \
-                                 hipStream_t, Gate);                                                          \
   template hipError_t tfqmr_v0<V>(V*, const V*, const V*, long long, double*, hipStream_t, Gate);
 INST(float)
 INST(double)

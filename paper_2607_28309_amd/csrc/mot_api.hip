@@ -56,6 +56,7 @@ struct mot_ctx {
   double* kv[13];      // FP64 Krylov vectors
   float* kf[11];       // FP32 Krylov vectors (FP32 and refined modes)
   double* partials;
+  size_t partials_n;   // entries of partials
   double* scal;
   double* hscal;       // pinned host mirror: [0] for synchronous reads, [1], [2] for the solver's queue
   hipEvent_t ev[3];
@@ -271,25 +272,36 @@ hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* 
 namespace {
 
 // ---------------------------------------------------------------- Green product
+struct NoMid {
+  int operator()() const { return MOT_OK; }
+};
+
 // y = epilogue(J, G J) with spectra `lam` (precision T) through the five passes.
-template <typename T, typename IO>
+// kf / ki: solver work fused into the x forward / x inverse pass; mid() is
+// enqueued between the x forward and the y forward pass.  With kf, J is the
+// x forward pass's solver input (see motfft::Krylov) and `Jd` the vector the
+// epilogue's diagonal term reads (the product's actual input).
+template <typename T, typename IO, typename Mid = NoMid>
 int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue ep, const double* pre = nullptr,
-                  motfft::Gate g = motfft::Gate{}) {
+                  motfft::Gate g = motfft::Gate{}, const motfft::Krylov* kf = nullptr,
+                  const motfft::Krylov* ki = nullptr, const IO* Jd = nullptr, Mid mid = Mid{}) {
   const int ti = sizeof(T) == 8 ? 1 : 0;
   hipStream_t s = c->stream;
   const int rows = 3 * c->nz * c->ny;
   const bool d = ti == 1;
   const int* tv = c->tune[ti];
+  if (!Jd) Jd = J;
   HTP(K_XF, d, (motfft::x_forward<T, IO>(J, c->wsA, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx / 2, c->kxs,
-                                         c->twx[ti], c->tw2x[ti], s, pre, g, tv[TUNE_X])));
+                                         c->twx[ti], c->tw2x[ti], s, pre, g, tv[TUNE_X], kf)));
+  TRY(mid());
   HTP(K_YF, d, motfft::y_pass<T>(c->wsA, c->wsB, c->py, false, c->kx, c->kxs, 3 * c->nz, c->ny, c->ny, c->py, c->py,
                                  c->twy[ti], s, g, tv[TUNE_Y]));
   HTP(K_ZFUSED, d, motfft::z_pass<T>(c->wsB, c->wsB, c->pz, motfft::Z_FUSED, 3, c->kx, c->kxs, c->py, c->nz, c->nz,
                                      c->nz, c->nz, lam, c->twz[ti], s, g, tv[TUNE_ZF]));
   HTP(K_YI, d, motfft::y_pass<T>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny, c->ny,
                                  c->twy[ti], s, g, tv[TUNE_Y]));
-  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, J, c->eps, ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
-                                         c->kxs, c->twx[ti], c->tw2x[ti], s, g, tv[TUNE_X])));
+  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, Jd, c->eps, ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
+                                         c->kxs, c->twx[ti], c->tw2x[ti], s, g, tv[TUNE_X], ki)));
   return MOT_OK;
 }
 
@@ -314,13 +326,21 @@ struct SolveOut {
 // Z0 product in the precision of the vectors: FP64 vectors -> FP64 FFTs,
 // FP32 vectors -> FP32 FFTs.
 // In an adjoint context the solver's operator is Z0^T.
-int apply_z0(mot_ctx* c, const double* in, double* out, motfft::Gate g = motfft::Gate{}) {
-  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0T, c->eps, g);
-  return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0, nullptr, g);
+// With solver hooks: `in` is the x forward pass's solver input, `jd` the
+// product's actual input (see green_product).
+template <typename Mid = NoMid>
+int apply_z0(mot_ctx* c, const double* in, double* out, motfft::Gate g = motfft::Gate{},
+             const motfft::Krylov* kf = nullptr, const motfft::Krylov* ki = nullptr, const double* jd = nullptr,
+             Mid mid = Mid{}) {
+  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0T, c->eps, g, kf, ki, jd, mid);
+  return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0, nullptr, g, kf, ki, jd, mid);
 }
-int apply_z0(mot_ctx* c, const float* in, float* out, motfft::Gate g = motfft::Gate{}) {
-  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0T, c->eps, g);
-  return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0, nullptr, g);
+template <typename Mid = NoMid>
+int apply_z0(mot_ctx* c, const float* in, float* out, motfft::Gate g = motfft::Gate{},
+             const motfft::Krylov* kf = nullptr, const motfft::Krylov* ki = nullptr, const float* jd = nullptr,
+             Mid mid = Mid{}) {
+  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0T, c->eps, g, kf, ki, jd, mid);
+  return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0, nullptr, g, kf, ki, jd, mid);
 }
 
 template <typename V> struct KV;
@@ -355,26 +375,67 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
   TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
   HTP(K_KRY, f64, tfqmr_v0<V>(v[V_V], v[V_AU], v[V_RT], n, P, s, RUN));
   HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, s, RUN));
+  // The iteration's vector work rides on its products (motfft::Krylov): the
+  // first half step on the forward x pass of the product of u2, the second
+  // on that product's inverse x pass; u = w + beta u2 on the forward x pass
+  // and the v update on the inverse x pass of the product of u; the second
+  // half step's x update waits in S_ETAP for the next iteration's first
+  // product or for the residual check.  The fused sums leave one partial per
+  // x-pass workgroup.
+  const int rows = 3 * c->nz * c->ny;
+  const int xb = motfft::x_pass_blocks(c->nx, f64, c->tune[f64 ? 1 : 0][TUNE_X], rows, c->nz * c->ny, 3);
+  if (xb < 1 || 2 * (size_t)xb > c->partials_n) return set_err(c, MOT_EINVAL, "x pass grid outside the partials%s%d");
+  motfft::Krylov kb;
+  kb.alpha = sc + S_ALPHA;
+  kb.beta = sc + S_BETA;
+  kb.eta = sc + S_ETA;
+  kb.etap = sc + S_ETAP;
+  kb.dcoef = sc + S_DCOEF;
+  kb.partials = P;
+  kb.stride = xb;
+  motfft::Krylov kh0 = kb, kh1 = kb, ku = kb, kvv = kb, kfix = kb;
+  kh0.mode = motfft::KRY_HALF0;  // in = u
+  kh0.v = v[V_V];
+  kh0.w = v[V_W];
+  kh0.au = v[V_AU];
+  kh0.d = v[V_D];
+  kh0.x = x;
+  kh0.out = v[V_U2];
+  kh1.mode = motfft::KRY_HALF1;  // J = u2, y = au2
+  kh1.x = x;
+  kh1.w = v[V_W];
+  kh1.d = v[V_D];
+  kh1.rt = v[V_RT];
+  ku.mode = motfft::KRY_U;  // in = w
+  ku.u2 = v[V_U2];
+  ku.out = v[V_U];
+  kvv.mode = motfft::KRY_V;  // y = au
+  kvv.au = v[V_AU2];
+  kvv.v = v[V_V];
+  kvv.rt = v[V_RT];
+  kfix.mode = motfft::KRY_XFIX;  // in = x
+  kfix.x = x;
+  kfix.d = v[V_D];
   // one iteration's launches on the context stream (gated; see above)
   auto enqueue_iter = [&](bool check) -> int {
     hipStream_t st = c->stream;
-    HTP(K_KRY, f64, tfqmr_half0<V>(v[V_U2], v[V_U], v[V_V], v[V_W], v[V_AU], v[V_D], sc, n, P, st, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF0, st, RUN));
-    TRY(apply_z0(c, v[V_U2], v[V_AU2], RUN));
-    // the second half step also forms w . rt, the next rho
-    HTP(K_KRY, f64, tfqmr_half1<V>(x, v[V_W], v[V_AU2], v[V_D], v[V_U2], v[V_RT], sc, n, P, st, RUN));
-    HTP(K_KRY, f64, reduce_post2(P, sc, S_W2, POST_HALF1, S_RHONEW, POST_BETA, st, RUN));
-    // u = w + beta u2 and the second half step's x update
-    HTP(K_KRY, f64, tfqmr_u<V>(v[V_U], v[V_W], v[V_U2], x, v[V_D], sc, n, st, RUN));
-    // true residual with the solver's own operator, only when asked for
+    auto half0_sum = [&]() -> int {
+      HTP(K_KRY, f64, reduce_post(P, sc, S_W2, POST_HALF0, st, RUN, xb));
+      return MOT_OK;
+    };
+    // u2 = u - alpha v and the first half step; au2 = A u2 and the second
+    TRY(apply_z0(c, v[V_U], v[V_AU2], RUN, &kh0, &kh1, v[V_U2], half0_sum));
+    HTP(K_KRY, f64, reduce_post2(P, sc, S_W2, POST_HALF1, S_RHONEW, POST_BETA, st, RUN, xb, xb));
+    // true residual with the solver's own operator, only when asked for (its
+    // forward x pass applies the pending x update)
     if (check) {
-      TRY(apply_z0(c, x, v[V_TMP], CHK));
+      TRY(apply_z0(c, x, v[V_TMP], CHK, &kfix, nullptr, x));
       HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, st, CHK));
       HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, st, CHK));
     }
-    TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
-    HTP(K_KRY, f64, tfqmr_v<V>(v[V_V], v[V_AU], v[V_AU2], v[V_RT], sc, n, P, st, RUN));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, st, RUN));
+    // u = w + beta u2; au = A u and v = au + beta (au2 + beta v)
+    TRY(apply_z0(c, v[V_W], v[V_AU], RUN, &ku, &kvv, v[V_U]));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, st, RUN, xb));
     return MOT_OK;
   };
   // graph mode: the same launches captured once per (precision, operator,
@@ -833,7 +894,10 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if (prec != MOT_F64)
     for (int i = 0; i < 11; ++i)
       if ((rc = dmalloc(c, (void**)&c->kf[i], sizeof(float) * c->n3)) != MOT_OK) return fail(rc);
-  if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * 2 * RED_BLOCKS)) != MOT_OK) return fail(rc);
+  // the vector kernels' partials, or two sums of one partial per x-pass
+  // workgroup (at most one workgroup per row)
+  c->partials_n = 2 * (size_t)std::max<long long>(RED_BLOCKS, 3LL * c->nz * c->ny);
+  if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * c->partials_n)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->scal, sizeof(double) * S_NSLOT)) != MOT_OK) return fail(rc);
   if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 3 * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
     c->hscal = nullptr;

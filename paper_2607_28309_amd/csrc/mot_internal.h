@@ -28,6 +28,7 @@ enum Slot {
   S_R2,
   S_TAU0,
   S_X2,
+  S_ETAP,  // coefficient of an x update still to be applied (x += etap d)
   // device-side convergence state of a solve (S_CHECK must follow S_DONE:
   // the launch gates read the pair)
   S_DONE,
@@ -60,11 +61,14 @@ hipError_t launch_compress(const void* spec, double* lam64, float* lam32, double
 using motfft::Gate;
 // Scalar recurrence applied by the reduction that produced scal[slot].
 enum Post { POST_NONE = 0, POST_INIT, POST_ALPHA, POST_HALF0, POST_HALF1, POST_BETA, POST_RESID };
-hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g = Gate{});
-// Two sums at once (partials[0, RED_BLOCKS) and [RED_BLOCKS, 2 RED_BLOCKS)),
-// then post1 and post2 in that order.
+// Sum of nparts partials (RED_BLOCKS for the vector kernels here, the
+// workgroup count for sums fused into the x passes) into scal[slot].
+hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g = Gate{},
+                       int nparts = RED_BLOCKS);
+// Two sums at once (partials[0, nparts) and [stride, stride + nparts)), then
+// post1 and post2 in that order.
 hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,
-                        hipStream_t s, Gate g = Gate{});
+                        hipStream_t s, Gate g, int nparts, int stride);
 // Start of a solve: tol, max_iter and the convergence state (iteration 0, not done).
 hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s);
 template <typename V> hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s);
@@ -78,18 +82,6 @@ hipError_t vec_d2f(const double* in, float* out, long long n, double* partials, 
 hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s);
 hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s);
 template <typename V> hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, hipStream_t s);
-template <typename V> hipError_t tfqmr_half0(V* u2, const V* u, const V* v, V* w, const V* au, V* d,
-                                             const double* scal, long long n, double* partials, hipStream_t s,
-                                             Gate g);
-// second half step; partials of |w|^2 and w . rt (2 RED_BLOCKS entries)
-template <typename V> hipError_t tfqmr_half1(V* x, V* w, const V* au2, V* d, const V* u2, const V* rt,
-                                             const double* scal, long long n, double* partials, hipStream_t s,
-                                             Gate g);
-// u = w + beta u2; x += eta d
-template <typename V> hipError_t tfqmr_u(V* u, const V* w, const V* u2, V* x, const V* d, const double* scal,
-                                         long long n, hipStream_t s, Gate g);
-template <typename V> hipError_t tfqmr_v(V* v, const V* au, const V* au2, const V* rt, const double* scal,
-                                         long long n, double* partials, hipStream_t s, Gate g);
 template <typename V> hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials,
                                           hipStream_t s, Gate g);
 
