@@ -43,18 +43,12 @@ template <bool INV, typename C> __device__ __forceinline__ C mul_i(C a) {
   return INV ? C{-a.y, a.x} : C{a.y, -a.x};
 }
 
-// cos/sin of 2 pi j / R for the composite radices 6, 8, 10 (j < R/2)
-__host__ __device__ constexpr double rot_cos(int R, int j) {
-  return R == 6 ? (j == 0 ? 1.0 : j == 1 ? 0.5 : -0.5)
-       : R == 8 ? (j == 0 ? 1.0 : j == 1 ? 0.70710678118654752440 : j == 2 ? 0.0 : -0.70710678118654752440)
-       : (j == 0 ? 1.0 : j == 1 ? 0.80901699437494742410 : j == 2 ? 0.30901699437494742410
-                : j == 3 ? -0.30901699437494742410 : -0.80901699437494742410);
+// cos/sin of 2 pi j / 8 (j < 4): the rotations of the radix-2 split of a
+// length-8 DFT (lengths 6 and 10 use the prime-factor mapping, no rotations)
+__host__ __device__ constexpr double rot_cos(int, int j) {
+  return j == 0 ? 1.0 : j == 1 ? 0.70710678118654752440 : j == 2 ? 0.0 : -0.70710678118654752440;
 }
-__host__ __device__ constexpr double rot_sin(int R, int j) {
-  return R == 6 ? (j == 0 ? 0.0 : 0.86602540378443864676)
-       : R == 8 ? (j == 0 ? 0.0 : j == 2 ? 1.0 : 0.70710678118654752440)
-       : (j == 0 ? 0.0 : (j == 1 || j == 4) ? 0.58778525229247312917 : 0.95105651629515357212);
-}
+__host__ __device__ constexpr double rot_sin(int, int j) { return j == 0 ? 0.0 : j == 2 ? 1.0 : 0.70710678118654752440; }
 
 // d * exp(-+2 pi i j / R) for a compile-time j (after unrolling): no
 // arithmetic for j = 0, a swap for the quarter turn.
@@ -70,8 +64,8 @@ __device__ __forceinline__ cpx<T> rotate(cpx<T> d, int j) {
 // In-register DFT of length R: v[k] <- sum_j v[j] exp(-+2 pi i jk/R).
 // run_half: the same with v[R/2..R-1] = 0 (those registers are not read).
 template <int R, bool INV, typename T> struct Dft {
-  // even composite radix R = 2Q: radix-2 split, rotate the odd half, two DFT_Q
-  static_assert(R % 2 == 0, "composite radices are even");
+  // radix 8 = 2 x 4: radix-2 split, rotate the odd half, two DFT_4
+  static_assert(R == 8, "composite radices: 8 here, 6 and 10 by PfaDft");
   static constexpr int Q = R / 2;
   static __device__ __forceinline__ void finish(cpx<T>* v, cpx<T>* a, cpx<T>* b) {
     Dft<Q, INV, T>::run(a);
@@ -159,6 +153,52 @@ template <bool INV, typename T> struct Dft<5, INV, T> {
     v[3] = csub(a2, b2);
   }
 };
+
+// Length R = 2Q with Q odd (6, 10) by the prime-factor (Good-Thomas)
+// mapping: input n = (Q n1 + 2 n2) mod R, output k = (Q k1 + (Q+1) k2) mod R
+// make W_R^{nk} = W_2^{n1 k1} W_Q^{n2 k2}, so Q length-2 DFTs feed two
+// length-Q DFTs with no rotations between them (the index maps are resolved
+// at compile time).
+template <int Q, bool INV, typename T> struct PfaDft {
+  static constexpr int R = 2 * Q;
+  static __device__ __forceinline__ void finish(cpx<T>* v, cpx<T>* a, cpx<T>* b) {
+    Dft<Q, INV, T>::run(a);
+    Dft<Q, INV, T>::run(b);
+#pragma unroll
+    for (int k2 = 0; k2 < Q; ++k2) {
+      v[((Q + 1) * k2) % R] = a[k2];
+      v[(Q + (Q + 1) * k2) % R] = b[k2];
+    }
+  }
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a[Q], b[Q];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      const cpx<T> x0 = v[(2 * n2) % R], x1 = v[(Q + 2 * n2) % R];
+      a[n2] = cadd(x0, x1);
+      b[n2] = csub(x0, x1);
+    }
+    finish(v, a, b);
+  }
+  // v[Q..R-1] = 0: of each input pair exactly one index is below Q
+  static __device__ __forceinline__ void run_half(cpx<T>* v) {
+    cpx<T> a[Q], b[Q];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      const int i0 = (2 * n2) % R, i1 = (Q + 2 * n2) % R;
+      if (i0 < Q) {
+        a[n2] = v[i0];
+        b[n2] = v[i0];
+      } else {
+        a[n2] = v[i1];
+        b[n2] = cpx<T>{-v[i1].x, -v[i1].y};
+      }
+    }
+    finish(v, a, b);
+  }
+};
+template <bool INV, typename T> struct Dft<6, INV, T> : PfaDft<3, INV, T> {};
+template <bool INV, typename T> struct Dft<10, INV, T> : PfaDft<5, INV, T> {};
 
 template <int... Rs> struct RadixList {};
 
