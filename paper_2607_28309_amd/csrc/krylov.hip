@@ -117,6 +117,19 @@ __device__ void post_op(double* scal, int post) {
       if (!isfinite(bound)) {
         scal[S_STATUS] = (double)MOT_ENONFINITE;
         scal[S_DONE] = 1.0;
+      } else if (scal[S_BOUND_ONLY] != 0.0) {
+        // the bound decides: converged, broken down or out of iterations
+        if (bound <= scal[S_TOL] * scal[S_BNORM]) {
+          scal[S_RELRES] = bound / scal[S_BNORM];
+          scal[S_DONE] = 1.0;
+        } else if (scal[S_FLAG] != 0.0) {
+          scal[S_STATUS] = (double)MOT_EBREAKDOWN;
+          scal[S_DONE] = 1.0;
+        } else if (it >= scal[S_MAXIT]) {
+          scal[S_RELRES] = bound / scal[S_BNORM];
+          scal[S_STATUS] = (double)MOT_ENOCONV;
+          scal[S_DONE] = 1.0;
+        }
       } else if (bound <= scal[S_TOL] * scal[S_BNORM] || scal[S_FLAG] != 0.0 || it >= scal[S_MAXIT]) {
         scal[S_CHECK] = 1.0;
       }
@@ -190,8 +203,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce2(const double* __restric
   }
 }
 
-__global__ void k_solver_setup(double* scal, double tol, double max_iter) {
+__global__ void k_solver_setup(double* scal, double tol, double max_iter, double bound_only) {
   if (threadIdx.x != 0) return;
+  scal[S_BOUND_ONLY] = bound_only;
   scal[S_TOL] = tol;
   scal[S_MAXIT] = max_iter;
   scal[S_ITER] = 0.0;
@@ -253,6 +267,14 @@ __global__ void k_zero(V* __restrict__ a, long long n) {
   GRID_STRIDE(i, n) a[i] = (V)0;
 }
 
+// x += coef d (coef read on the device)
+template <typename V>
+__global__ void k_axpy_scal(V* __restrict__ x, const V* __restrict__ d, const double* __restrict__ coef,
+                            long long n) {
+  const V a = (V)*coef;
+  GRID_STRIDE(i, n) x[i] += a * d[i];
+}
+
 // w = u = rt = r0, d = 0, x = 0
 template <typename V>
 __global__ void k_tfqmr_init(const V* __restrict__ r0, V* __restrict__ w, V* __restrict__ u, V* __restrict__ rt,
@@ -306,9 +328,13 @@ hipError_t reduce_post2(const double* partials, double* scal, int slot1, int pos
                      stride);
   return hipGetLastError();
 }
-hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s) {
-  hipLaunchKernelGGL(k_solver_setup, dim3(1), dim3(64), 0, s, scal, tol, (double)max_iter);
+hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only) {
+  hipLaunchKernelGGL(k_solver_setup, dim3(1), dim3(64), 0, s, scal, tol, (double)max_iter, bound_only ? 1.0 : 0.0);
   return hipGetLastError();
+}
+template <typename V>
+hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipStream_t s) {
+  LAUNCH(k_axpy_scal<V>, x, d, coef, n);
 }
 template <typename V>
 hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials, hipStream_t s, Gate g) {
@@ -341,6 +367,7 @@ hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partial
   template hipError_t vec_sub<V>(const V*, const V*, V*, long long, double*, hipStream_t, Gate);              \
   template hipError_t vec_zero<V>(V*, long long, hipStream_t);                                                \
   template hipError_t tfqmr_init<V>(const V*, V*, V*, V*, V*, V*, long long, hipStream_t);                    \
+  template hipError_t vec_axpy_scal<V>(V*, const V*, const double*, long long, hipStream_t);                  \
   template hipError_t tfqmr_v0<V>(V*, const V*, const V*, long long, double*, hipStream_t, Gate);
 INST(float)
 INST(double)

@@ -359,8 +359,10 @@ template <> struct KV<float> {
 // stays one iteration ahead: it enqueues iteration m, then waits only for the
 // scalars of iteration m-1 (copied to pinned memory behind an event); an
 // iteration enqueued after convergence does nothing.
+// bound_only: the quasi-residual bound alone ends the solve (no true
+// residual products); the pending x update is applied at the end.
 template <typename V>
-int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) {
+int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, bool bound_only = false) {
   hipStream_t s = c->stream;
   const long long n = c->n3;
   V** v = KV<V>::get(c);
@@ -368,7 +370,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
   double* sc = c->scal;
   const bool f64 = sizeof(V) == 8;
   const motfft::Gate RUN{sc + S_DONE, 1}, CHK{sc + S_DONE, 2};
-  HTP(K_KRY, f64, solver_setup(sc, tol, max_iter, s));
+  HTP(K_KRY, f64, solver_setup(sc, tol, max_iter, s, bound_only));
   HTP(K_KRY, f64, dot_partial<V>(b, b, n, P, s));
   HTP(K_KRY, f64, reduce_post(P, sc, S_B2, POST_INIT, s));
   HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));  // x = 0 also for b = 0
@@ -478,8 +480,9 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
   // missed one a whole iteration)
   double tau_last = -1.0, tolb = -1.0;
   for (int it = 1; it <= max_iter + 1; ++it) {
-    bool check = true;
-    if (tau_last > 0.0 && tolb > 0.0 && it < max_iter) check = tau_last * std::sqrt(2.0 * it + 1.0) <= 1e3 * tolb;
+    bool check = !bound_only;
+    if (check && tau_last > 0.0 && tolb > 0.0 && it < max_iter)
+      check = tau_last * std::sqrt(2.0 * it + 1.0) <= 1e3 * tolb;
     TRY(launch_iter(check));
     double* bank = c->hscal + (1 + (it & 1)) * S_NSLOT;
     HT(hipMemcpyAsync(bank, sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, s));
@@ -507,6 +510,8 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so) 
     }
   }
   if (!h || h[S_DONE] == 0.0) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
+  // a solve ended by the bound leaves the second half step's x update pending
+  if (bound_only) HTP(K_KRY, f64, vec_axpy_scal<V>(x, v[V_D], sc + S_ETAP, n, s));
   so->iters = (int)h[S_ITER];
   so->matvecs += (int)h[S_NMV];
   if (f64) so->matvecs64 += (int)h[S_NMV];
@@ -568,7 +573,9 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
         HTP(K_KRY, false, vec_d2f(r, c->kf[V_B], n, P, s));
         const int left = max_iter - so.iters;
         const int cap = left < kInnerCap ? (left > 1 ? left : 1) : kInnerCap;
-        int irc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tin, cap, &inner);
+        // the inner solve stops on its quasi-residual bound: the FP64
+        // residual below is its check
+        int irc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tin, cap, &inner, true);
         so.iters += inner.iters;
         so.matvecs += inner.matvecs;
         if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;

@@ -29,6 +29,7 @@ enum Slot {
   S_TAU0,
   S_X2,
   S_ETAP,  // coefficient of an x update still to be applied (x += etap d)
+  S_BOUND_ONLY,  // 1: the quasi-residual bound ends the solve (no true residual)
   // device-side convergence state of a solve (S_CHECK must follow S_DONE:
   // the launch gates read the pair)
   S_DONE,
@@ -69,8 +70,12 @@ hipError_t reduce_post(const double* partials, double* scal, int slot, int post,
 // post1 and post2 in that order.
 hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,
                         hipStream_t s, Gate g, int nparts, int stride);
-// Start of a solve: tol, max_iter and the convergence state (iteration 0, not done).
-hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s);
+// Start of a solve: tol, max_iter and the convergence state (iteration 0, not
+// done); bound_only: stop when the quasi-residual bound passes (for inner
+// solves whose result an outer residual checks).
+hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only = false);
+// x += scal[slot] d
+template <typename V> hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipStream_t s);
 template <typename V> hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s);
 template <typename V> hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials,
                                          hipStream_t s, Gate g = Gate{});  // out = a - b, partials of |out|^2
