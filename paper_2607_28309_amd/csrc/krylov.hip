@@ -93,7 +93,17 @@ __device__ void post_op(double* scal, int post) {
       scal[S_DCOEF] = alpha != 0.0 ? theta * theta * eta / alpha : 0.0;
       if (post == POST_HALF0) {
         scal[S_TAU0] = tau;
-        scal[S_NMV] += 1.0;  // the product A u2 that follows
+        // a solve ended by the bound may stop after this half step (half
+        // step 2 it + 1: bound tau sqrt(2 it + 2)); its x update x += eta d
+        // is then the pending one and the product A u2 is not completed
+        const double bound = tau * sqrt(2.0 * scal[S_ITER] + 2.0);
+        if (scal[S_BOUND_ONLY] != 0.0 && isfinite(bound) && bound <= scal[S_TOL] * scal[S_BNORM]) {
+          scal[S_ETAP] = eta;
+          scal[S_RELRES] = bound / scal[S_BNORM];
+          scal[S_DONE] = 1.0;
+        } else {
+          scal[S_NMV] += 1.0;  // the product A u2 that follows
+        }
       }
       break;
     }
