@@ -46,7 +46,12 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
 //   KRY_HALF1 (x inverse; J = u2, y = au2):  x += eta d; w -= alpha au2;
 //       d = u2 + dcoef d; partials |w|^2 and w . rt.
 //   KRY_V (x inverse; y = au):  v = au + beta (au2 + beta v); partial v . rt.
-enum KryMode { KRY_NONE = 0, KRY_HALF0, KRY_U, KRY_XFIX, KRY_HALF1, KRY_V };
+//   KRY_SCALE (either pass): no vector work, only the scale below.
+// rs (optional with every mode but KRY_NONE; per voxel, indexed like the
+// epilogue's permittivity): right diagonal scaling of the solver's operator,
+// Z0 diag(rs): the product's input (forward pass) and the diagonal term's
+// current (inverse pass) are multiplied by rs.
+enum KryMode { KRY_NONE = 0, KRY_HALF0, KRY_U, KRY_XFIX, KRY_HALF1, KRY_V, KRY_SCALE };
 struct Krylov {
   int mode = KRY_NONE;
   const double* alpha = nullptr;  // solver scalars (device)
@@ -64,6 +69,7 @@ struct Krylov {
   void* u2 = nullptr;   // KRY_U: u2
   double* partials = nullptr;  // partials[b] (and partials[stride + b] for a second sum)
   int stride = 0;
+  const void* rs = nullptr;    // right scaling (see above), IO values
 };
 
 // Precision tags: T = compute type; IO = element type of real vectors.

@@ -26,8 +26,10 @@ MOT_X_EXT_INV(double, double, 1, KRY_NONE)
   MOT_X_EXT_FWD(T, T, V, KRY_HALF0)  \
   MOT_X_EXT_FWD(T, T, V, KRY_U)      \
   MOT_X_EXT_FWD(T, T, V, KRY_XFIX)   \
+  MOT_X_EXT_FWD(T, T, V, KRY_SCALE)  \
   MOT_X_EXT_INV(T, T, V, KRY_HALF1)  \
-  MOT_X_EXT_INV(T, T, V, KRY_V)
+  MOT_X_EXT_INV(T, T, V, KRY_V)      \
+  MOT_X_EXT_INV(T, T, V, KRY_SCALE)
 MOT_X_EXT_SOLVER(float, 0)
 MOT_X_EXT_SOLVER(double, 0)
 MOT_X_EXT_SOLVER(float, 1)
@@ -52,6 +54,7 @@ hipError_t x_forward_k(const IO* in, void* out, int M, int nrows, int rows_per_c
     F(KRY_HALF0)
     F(KRY_U)
     F(KRY_XFIX)
+    F(KRY_SCALE)
 #undef F
   }
   return hipErrorInvalidValue;
@@ -72,6 +75,7 @@ hipError_t x_inverse_k(const void* in, IO* y, const IO* J, const double* eps, Ep
                                      tw2, s, gg, *kry);
     F(KRY_HALF1)
     F(KRY_V)
+    F(KRY_SCALE)
 #undef F
   }
   return hipErrorInvalidValue;

@@ -84,6 +84,10 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
   const size_t ro = (size_t)(valid ? grow : 0) * row_len + 2 * jt;
   const IO* src = in + ro;
   const double* prow = pre ? pre + (size_t)((valid ? grow : 0) % rows_per_comp) * row_len + 2 * jt : nullptr;
+  // right scaling of the solver's operator, per voxel
+  const IO* srow = KM != KRY_NONE && kry.rs
+                       ? (const IO*)kry.rs + (size_t)((valid ? grow : 0) % rows_per_comp) * row_len + 2 * jt
+                       : nullptr;
   IO ka = 0, kb = 0, kep = 0, kdc = 0;
   if constexpr (KM == KRY_HALF0) {
     ka = (IO)*kry.alpha;
@@ -114,7 +118,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
     const IO* kin = KM == KRY_XFIX ? (const IO*)kry.x : in;
 #pragma unroll
     for (int l0 = 0; l0 < NL; l0 += CH) {
-      V2 a0[CH], a1[CH], a2[CH], a3[CH], a4[CH], a5[CH];
+      V2 a0[CH], a1[CH], a2[CH], a3[CH], a4[CH], a5[CH], sc[CH];
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc) {
         const int l = l0 + cc;
@@ -122,6 +126,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
         const int u = (l / HR) * TJ + (l % HR) * MR;
         const size_t o = ro + 2 * u;
         a0[cc] = *reinterpret_cast<const V2*>(kin + o);
+        if (srow) sc[cc] = *reinterpret_cast<const V2*>(srow + 2 * u);
         if constexpr (KM == KRY_HALF0) {
           a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.v + o);
           a2[cc] = *reinterpret_cast<const V2*>((const IO*)kry.w + o);
@@ -130,7 +135,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
           a5[cc] = *reinterpret_cast<const V2*>((const IO*)kry.x + o);
         } else if constexpr (KM == KRY_U) {
           a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.u2 + o);
-        } else {
+        } else if constexpr (KM == KRY_XFIX) {
           a4[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
         }
       }
@@ -163,10 +168,16 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
           pr.x = a0[cc].x + kb * a1[cc].x;
           pr.y = a0[cc].y + kb * a1[cc].y;
           if (valid) *reinterpret_cast<V2*>((IO*)kry.out + o) = pr;
-        } else {  // KRY_XFIX: a0 = x, a4 = d
+        } else if constexpr (KM == KRY_XFIX) {  // a0 = x, a4 = d
           pr.x = a0[cc].x + kep * a4[cc].x;
           pr.y = a0[cc].y + kep * a4[cc].y;
           if (valid) *reinterpret_cast<V2*>((IO*)kry.x + o) = pr;
+        } else {  // KRY_SCALE
+          pr = a0[cc];
+        }
+        if (srow) {
+          pr.x *= sc[cc].x;
+          pr.y *= sc[cc].y;
         }
         v[(l / HR) * R0 + (l % HR)] = contrast(pr, u);
       }
@@ -234,10 +245,17 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   const size_t eoff = (size_t)(growc % rows_per_comp) * row_len + 2 * jt;
   V2 jv[EH];
   double2 ev[EH];
+  // right scaling of the solver's operator: the diagonal term's current is rs J
+  constexpr bool SCALED = KM != KRY_NONE;
+  const IO* rsrow = SCALED && kry.rs ? (const IO*)kry.rs + eoff : nullptr;
+  V2 sv[SCALED ? EH : 1];
 #pragma unroll
   for (int i = 0; i < EH; ++i) {
     jv[i] = *reinterpret_cast<const V2*>(J + roff + 2 * TJ * i);
     ev[i] = *reinterpret_cast<const double2*>(eps + eoff + 2 * TJ * i);
+    if constexpr (SCALED) {
+      if (rsrow) sv[i] = *reinterpret_cast<const V2*>(rsrow + 2 * TJ * i);
+    }
   }
   load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
   load_table<cpx<T>, M + 1, C::BLOCK>(tw2, tw2_g);
@@ -265,19 +283,25 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   }
   if constexpr (KM == KRY_V) kb = (IO)*kry.beta;
   double acc1 = 0.0, acc2 = 0.0;
-  V2 yo[KM == KRY_NONE ? 1 : EH];  // the y pairs this lane wrote (solver forms)
+  V2 yo[KM == KRY_HALF1 || KM == KRY_V ? EH : 1];  // the y pairs this lane wrote (solver forms)
   run_fft<T, M, true, false, true>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> z) {
     if (!valid) return;
     const int i = u / TJ;
     const double2 e2 = ev[i];
-    const V2 j2 = jv[i];
+    V2 j2 = jv[i];
+    if constexpr (SCALED) {
+      if (rsrow) {
+        j2.x *= sv[i].x;
+        j2.y *= sv[i].y;
+      }
+    }
     V2 r;
     r.x = (IO)(((T)(ep.ca * e2.x + ep.c0)) * (T)j2.x + ((T)(ep.cb * e2.x + ep.cb0)) * z.x);
     r.y = (IO)(((T)(ep.ca * e2.y + ep.c0)) * (T)j2.y + ((T)(ep.cb * e2.y + ep.cb0)) * z.y);
     *reinterpret_cast<V2*>(yrow + 2 * u) = r;
-    if constexpr (KM != KRY_NONE) yo[i] = r;
+    if constexpr (KM != KRY_NONE && KM != KRY_SCALE) yo[i] = r;
   });
-  if constexpr (KM != KRY_NONE) {
+  if constexpr (KM == KRY_HALF1 || KM == KRY_V) {
     // pairs n = jt + TJ i of the row, in chunks of CH: all operand loads of a
     // chunk are issued before its stores
     constexpr int CH = EH < 4 ? EH : 4;
@@ -437,7 +461,9 @@ int x_pass_blocks_v(int M, bool f64, int nrows, int rows_per_comp, int ncomp) {
   MOT_X_FWD(T, T, V, KRY_HALF0)                                                                                \
   MOT_X_FWD(T, T, V, KRY_U)                                                                                    \
   MOT_X_FWD(T, T, V, KRY_XFIX)                                                                                 \
+  MOT_X_FWD(T, T, V, KRY_SCALE)                                                                                \
   MOT_X_INV(T, T, V, KRY_HALF1)                                                                                \
-  MOT_X_INV(T, T, V, KRY_V)
+  MOT_X_INV(T, T, V, KRY_V)                                                                                    \
+  MOT_X_INV(T, T, V, KRY_SCALE)
 
 }  // namespace motfft

@@ -277,6 +277,12 @@ __global__ void k_zero(V* __restrict__ a, long long n) {
   GRID_STRIDE(i, n) a[i] = (V)0;
 }
 
+// x *= rs (per voxel: x holds three components of nvox values each)
+template <typename V>
+__global__ void k_scale_voxel(V* __restrict__ x, const V* __restrict__ rs, long long n, long long nvox) {
+  GRID_STRIDE(i, n) x[i] *= rs[i % nvox];
+}
+
 // x += coef d (coef read on the device)
 template <typename V>
 __global__ void k_axpy_scal(V* __restrict__ x, const V* __restrict__ d, const double* __restrict__ coef,
@@ -347,6 +353,10 @@ hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipS
   LAUNCH(k_axpy_scal<V>, x, d, coef, n);
 }
 template <typename V>
+hipError_t vec_scale_voxel(V* x, const V* rs, long long n, long long nvox, hipStream_t s) {
+  LAUNCH(k_scale_voxel<V>, x, rs, n, nvox);
+}
+template <typename V>
 hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials, hipStream_t s, Gate g) {
   LAUNCH(k_sub<V>, a, b, out, n, partials, g);
 }
@@ -378,6 +388,7 @@ hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partial
   template hipError_t vec_zero<V>(V*, long long, hipStream_t);                                                \
   template hipError_t tfqmr_init<V>(const V*, V*, V*, V*, V*, V*, long long, hipStream_t);                    \
   template hipError_t vec_axpy_scal<V>(V*, const V*, const double*, long long, hipStream_t);                  \
+  template hipError_t vec_scale_voxel<V>(V*, const V*, long long, long long, hipStream_t);                   \
   template hipError_t tfqmr_v0<V>(V*, const V*, const V*, long long, double*, hipStream_t, Gate);
 INST(float)
 INST(double)

@@ -38,6 +38,11 @@ struct mot_ctx {
   void* twz[2];
   double* eps;
   bool have_eps, have_spectra;
+  // right diagonal scaling of the solver's Z0: rs = 1 / diag(Z0) per voxel,
+  // diag(Z0) = eps/2 - (eps - 1) G0(0)_pp (G0(0) is isotropic)
+  double g0self;       // G0(0)_xx
+  float* rs32;
+  double* rs64;
   double* lam0_64;
   float* lam0_32;
   void* lamh;          // lags 1..nl, ring precision
@@ -243,6 +248,16 @@ __global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int n
       src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
 }
 
+// rs = 1 / (eps/2 - (eps - 1) g0), the inverse diagonal of Z0 per voxel
+__global__ void k_right_scale(const double* __restrict__ eps, double g0, float* __restrict__ rs32,
+                              double* __restrict__ rs64, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = 1.0 / (eps[i] * (0.5 - g0) + g0);
+  rs64[i] = r;
+  rs32[i] = (float)r;
+}
+
 // fused z pass tile layout of width ws -> the same spectra in width wd
 template <typename T>
 __global__ void k_retile(const T* __restrict__ src, T* __restrict__ dst, int nx, int ny, int nz, int ws, int wd) {
@@ -374,7 +389,13 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   HTP(K_KRY, f64, dot_partial<V>(b, b, n, P, s));
   HTP(K_KRY, f64, reduce_post(P, sc, S_B2, POST_INIT, s));
   HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));  // x = 0 also for b = 0
-  TRY(apply_z0(c, v[V_U], v[V_AU], RUN));
+  // the solver's operator is Z0 diag(rs) (right scaling by the inverse
+  // diagonal of Z0); its solution y gives x = rs y at the end
+  const V* rs = f64 ? (const V*)c->rs64 : (const V*)c->rs32;
+  motfft::Krylov ks;
+  ks.mode = motfft::KRY_SCALE;
+  ks.rs = rs;
+  TRY(apply_z0(c, v[V_U], v[V_AU], RUN, &ks, &ks));
   HTP(K_KRY, f64, tfqmr_v0<V>(v[V_V], v[V_AU], v[V_RT], n, P, s, RUN));
   HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, s, RUN));
   // The iteration's vector work rides on its products (motfft::Krylov): the
@@ -395,6 +416,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   kb.dcoef = sc + S_DCOEF;
   kb.partials = P;
   kb.stride = xb;
+  kb.rs = rs;
   motfft::Krylov kh0 = kb, kh1 = kb, ku = kb, kvv = kb, kfix = kb;
   kh0.mode = motfft::KRY_HALF0;  // in = u
   kh0.v = v[V_V];
@@ -431,7 +453,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
     // true residual with the solver's own operator, only when asked for (its
     // forward x pass applies the pending x update)
     if (check) {
-      TRY(apply_z0(c, x, v[V_TMP], CHK, &kfix, nullptr, x));
+      TRY(apply_z0(c, x, v[V_TMP], CHK, &kfix, &ks, x));
       HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, st, CHK));
       HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, st, CHK));
     }
@@ -497,7 +519,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
       }
       // a check the device asked for but the host did not enqueue: enqueue it now
       if (prev[S_CHECK] != 0.0 && !check) {
-        TRY(apply_z0(c, x, v[V_TMP], CHK));
+        TRY(apply_z0(c, x, v[V_TMP], CHK, &kfix, &ks, x));
         HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s, CHK));
         HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, s, CHK));
       }
@@ -512,6 +534,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   if (!h || h[S_DONE] == 0.0) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
   // a solve ended by the bound leaves the second half step's x update pending
   if (bound_only) HTP(K_KRY, f64, vec_axpy_scal<V>(x, v[V_D], sc + S_ETAP, n, s));
+  HTP(K_KRY, f64, vec_scale_voxel<V>(x, rs, n, c->N, s));
   so->iters = (int)h[S_ITER];
   so->matvecs += (int)h[S_NMV];
   if (f64) so->matvecs64 += (int)h[S_NMV];
@@ -686,6 +709,15 @@ void drop_graphs(mot_ctx* c) {
           (void)hipGraphExecDestroy(c->iter_graph[a][b][k]);
           c->iter_graph[a][b][k] = nullptr;
         }
+}
+
+// The solver's right scaling from the current material and G0(0).
+int update_right_scale(mot_ctx* c) {
+  if (!c->have_eps || !c->have_spectra) return MOT_OK;
+  hipLaunchKernelGGL(k_right_scale, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, c->stream, c->eps,
+                     c->g0self, c->rs32, c->rs64, c->N);
+  HT(hipGetLastError());
+  return MOT_OK;
 }
 
 // Rewrite stored Z0 spectra from the fused z pass's tile width ws to wd
@@ -883,6 +915,8 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   const size_t wsA = (size_t)3 * c->nz * c->ny * c->kxs * 16;
   const size_t wsB = (size_t)3 * c->nz * c->py * c->kxs * 16;
   if ((rc = dmalloc(c, (void**)&c->eps, sizeof(double) * c->N)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->rs32, sizeof(float) * c->N)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->rs64, sizeof(double) * c->N)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->wsA, wsA)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->wsB, wsB)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->lam0_64, sizeof(double) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
@@ -925,7 +959,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
 int mot_destroy(mot_ctx* c) {
   if (!c) return MOT_OK;
   (void)hipStreamSynchronize(c->stream);
-  void* bufs[] = {c->eps, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
+  void* bufs[] = {c->eps, c->rs32, c->rs64, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
                   c->partials, c->scal, c->lam_tile, c->pblk, c->ffpart};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -973,7 +1007,7 @@ int mot_set_material(mot_ctx* c, const double* eps_r) {
   if (!c || !eps_r) return MOT_EINVAL;
   HT(hipMemcpyAsync(c->eps, eps_r, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
   c->have_eps = true;
-  return MOT_OK;
+  return update_right_scale(c);
 }
 
 int mot_green_table(mot_ctx* c, int32_t k, double* out) {
@@ -1013,6 +1047,10 @@ int build_green_spectra(mot_ctx* c) {
   std::vector<double> hmax(nblk);
   for (int k = 0; k <= c->nl && rc == MOT_OK; ++k) {
     hipError_t e = launch_green(goct, c->nx, c->ny, c->nz, k, c->alpha, c->L, c->nq, s);
+    // G0(0)_xx (octant entry 0 of component xx) for the solver's scaling
+    if (k == 0 && e == hipSuccess)
+      if ((e = hipMemcpyAsync(&c->g0self, goct, sizeof(double), hipMemcpyDeviceToHost, s)) == hipSuccess)
+        e = hipStreamSynchronize(s);
     for (int comp = 0; comp < 6 && e == hipSuccess; ++comp) {
       if ((e = launch_embed(goct, E, comp, c->nx, c->ny, c->nz, s)) != hipSuccess) break;
       if ((e = motfft::x_forward<double, double>(E, T1, c->nx, c->pz * c->py, c->pz * c->py, 1, c->px, c->nx,
@@ -1051,7 +1089,7 @@ int build_green_spectra(mot_ctx* c) {
   if (rc != MOT_OK) return rc;
   c->spectra_imag = imag;
   c->have_spectra = true;
-  return MOT_OK;
+  return update_right_scale(c);
 }
 
 int z0_matvec(mot_ctx* c, const void* J, void* y, mot_precision dtype) {

@@ -76,6 +76,8 @@ hipError_t reduce_post2(const double* partials, double* scal, int slot1, int pos
 hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only = false);
 // x += scal[slot] d
 template <typename V> hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipStream_t s);
+// x *= rs per voxel (x: components of nvox values each)
+template <typename V> hipError_t vec_scale_voxel(V* x, const V* rs, long long n, long long nvox, hipStream_t s);
 template <typename V> hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s);
 template <typename V> hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials,
                                          hipStream_t s, Gate g = Gate{});  // out = a - b, partials of |out|^2
