@@ -216,6 +216,17 @@ int mot_set_variants(mot_ctx* ctx, const int32_t* variants);
 int mot_get_variants(const mot_ctx* ctx, int32_t* variants);
 int mot_autotune(mot_ctx* ctx, int32_t reps, double* ms);
 
+/* Initial guess of the MOT_F32_REFINED solve (not in the paper; the solution
+ * still meets the same true-residual test): with k > 0 the context keeps the
+ * solutions J_i of its last k steps and Z0 J_i (the product its last FP64
+ * residual computes anyway) and starts each solve from x0 = sum_i c_i J_i,
+ * c the least-squares fit of the right-hand side by the Z0 J_i, so that
+ * r0 = b - sum_i c_i Z0 J_i costs no product.  Uses 2k FP64 vectors of 3N,
+ * allocated on first use.  Default k = 0 (off).  The stored pairs are dropped by mot_reset, mot_set_step,
+ * mot_set_material, build_green_spectra, a change of mot_set_adjoint and this
+ * call.  Errors: MOT_EINVAL (k outside 0..8, or k > 0 for another precision). */
+int mot_set_predictor(mot_ctx* ctx, int32_t k);
+
 /* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
 int mot_reset(mot_ctx* ctx);
 

@@ -277,6 +277,56 @@ __global__ void k_zero(V* __restrict__ a, long long n) {
   GRID_STRIDE(i, n) a[i] = (V)0;
 }
 
+// Dots of the multidot set: u_j . w_i and u_0 . u_0, partials per dot.
+__global__ __launch_bounds__(RED_THREADS) void k_multidot(DotSet ds, long long n, double* partials) {
+  constexpr int ND = 2 * PRED_MAX + 1;
+  double acc[ND];
+#pragma unroll
+  for (int q = 0; q < ND; ++q) acc[q] = 0.0;
+  GRID_STRIDE(i, n) {
+    const double u0 = ds.u[0][i];
+    const double u1 = ds.nu > 1 ? ds.u[1][i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < PRED_MAX; ++k)
+      if (k < ds.nw) {
+        const double w = ds.w[k][i];
+        acc[k] += u0 * w;
+        acc[PRED_MAX + k] += u1 * w;
+      }
+    acc[2 * PRED_MAX] += u0 * u0;
+  }
+  // partials of dot (j, k) at (j nw + k) RED_BLOCKS; the self dot after them
+#pragma unroll
+  for (int q = 0; q < ND; ++q) {
+    const int j = q / PRED_MAX, k = q % PRED_MAX;
+    const bool used = q == 2 * PRED_MAX || (j < ds.nu && k < ds.nw);
+    const int slot = q == 2 * PRED_MAX ? ds.nu * ds.nw : j * ds.nw + k;
+    if (used) block_partial(acc[q], partials + (size_t)slot * RED_BLOCKS);
+    __syncthreads();  // block_partial's LDS is reused by the next dot
+  }
+}
+
+// out[d] = sum of partials[d RED_BLOCKS ...] (one block per dot)
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_many(const double* __restrict__ partials, double* out) {
+  const double sum = sum_partials(partials + (size_t)blockIdx.x * RED_BLOCKS, RED_BLOCKS);
+  if (threadIdx.x == 0) out[blockIdx.x] = sum;
+}
+
+__global__ void k_pred_combine(Combo cb, const double* __restrict__ b, double* __restrict__ x0,
+                               double* __restrict__ r0, long long n) {
+  GRID_STRIDE(i, n) {
+    double x = 0.0, z = 0.0;
+#pragma unroll
+    for (int k = 0; k < PRED_MAX; ++k)
+      if (k < cb.k) {
+        x += cb.c[k] * cb.J[k][i];
+        z += cb.c[k] * cb.Z[k][i];
+      }
+    x0[i] = x;
+    r0[i] = b[i] - z;
+  }
+}
+
 // x *= rs (per voxel: x holds three components of nvox values each)
 template <typename V>
 __global__ void k_scale_voxel(V* __restrict__ x, const V* __restrict__ rs, long long n, long long nvox) {
@@ -355,6 +405,18 @@ hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipS
 template <typename V>
 hipError_t vec_scale_voxel(V* x, const V* rs, long long n, long long nvox, hipStream_t s) {
   LAUNCH(k_scale_voxel<V>, x, rs, n, nvox);
+}
+hipError_t multidot(const DotSet& ds, long long n, double* partials, double* out, hipStream_t s) {
+  if (ds.nu < 1 || ds.nu > 2 || ds.nw < 0 || ds.nw > PRED_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_multidot, RG(), RB(), 0, s, ds, n, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_many, dim3(ds.nu * ds.nw + 1), RB(), 0, s, partials, out);
+  return hipGetLastError();
+}
+hipError_t pred_combine(const Combo& cb, const double* b, double* x0, double* r0, long long n, hipStream_t s) {
+  if (cb.k < 1 || cb.k > PRED_MAX) return hipErrorInvalidValue;
+  LAUNCH(k_pred_combine, cb, b, x0, r0, n);
 }
 template <typename V>
 hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials, hipStream_t s, Gate g) {

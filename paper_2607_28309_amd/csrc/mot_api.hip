@@ -83,6 +83,15 @@ struct mot_ctx {
   double* ffpart;      // scratch: far-field block partials
   size_t ffpart_n;
   int tune[2][TUNE_N]; // tile variants of the FFT passes (0 or 1)
+  // initial guess of the refined solve from earlier steps: least squares
+  // over the pairs (J_i, Z0 J_i) of the last pred_k steps
+  int pred_k;
+  int pred_count, pred_head;  // stored pairs; slot of the next one
+  bool pred_newrow;           // the newest pair's Gram row is still to be formed
+  double* pred_j[PRED_MAX];   // J_i
+  double* pred_z[PRED_MAX];   // Z0 J_i
+  double pred_G[PRED_MAX][PRED_MAX];  // Gram matrix of the stored Z0 J_i
+  double* pred_dots;                  // device: dots of one multidot
   size_t bytes;
   char err[512];
 };
@@ -551,6 +560,119 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   }
 }
 
+// ---------------------------------------------------------------- initial guess
+// x0 = sum_i c_i J_i over the stored solutions of earlier steps, with c the
+// least-squares fit of b by the stored Z0 J_i, so that r0 = b - Z0 x0 =
+// b - sum_i c_i Z0 J_i needs no product (the refined solve computes Z0 J of
+// every solution in FP64 for its last residual).  The Gram matrix of the
+// Z0 J_i is kept on the host; one pass forms the newest pair's row, the
+// dots with b and |b|^2.
+static_assert(2 * PRED_MAX + 1 <= S_NSLOT, "the predictor's dots fit a scalar bank");
+
+void pred_clear(mot_ctx* c) {
+  c->pred_count = 0;
+  c->pred_head = 0;
+  c->pred_newrow = false;
+}
+
+// Solve the k x k system G c = d by Cholesky with a small diagonal shift;
+// false when G is not positive definite even so.
+bool pred_solve(int k, const double (*G)[PRED_MAX], const double* d, double* out) {
+  double L[PRED_MAX][PRED_MAX] = {};
+  double gmax = 0.0;
+  for (int i = 0; i < k; ++i) gmax = std::max(gmax, G[i][i]);
+  if (!(gmax > 0.0) || !std::isfinite(gmax)) return false;
+  const double shift = 1e-12 * gmax;
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double a = G[i][j] + (i == j ? shift : 0.0);
+      for (int q = 0; q < j; ++q) a -= L[i][q] * L[j][q];
+      if (i == j) {
+        if (!(a > 0.0)) return false;
+        L[i][i] = std::sqrt(a);
+      } else {
+        L[i][j] = a / L[j][j];
+      }
+    }
+  double y[PRED_MAX];
+  for (int i = 0; i < k; ++i) {
+    double a = d[i];
+    for (int q = 0; q < i; ++q) a -= L[i][q] * y[q];
+    y[i] = a / L[i][i];
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    double a = y[i];
+    for (int q = i + 1; q < k; ++q) a -= L[q][i] * out[q];
+    out[i] = a / L[i][i];
+  }
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(out[i])) return false;
+  return true;
+}
+
+// x0 into x, r0 into r0; bnorm = |b|, rnorm = |r0| (from the Gram data).
+int pred_guess(mot_ctx* c, const double* b, double* x, double* r0, double& bnorm, double& rnorm) {
+  hipStream_t s = c->stream;
+  const int k = c->pred_count, K = c->pred_k;
+  const int newest = (c->pred_head + K - 1) % K;
+  DotSet ds{};
+  ds.u[0] = b;
+  ds.u[1] = c->pred_newrow ? c->pred_z[newest] : nullptr;
+  ds.nu = c->pred_newrow ? 2 : 1;
+  for (int i = 0; i < k; ++i) ds.w[i] = c->pred_z[i];
+  ds.nw = k;
+  if (!c->pred_dots) TRY(dmalloc(c, (void**)&c->pred_dots, sizeof(double) * (2 * PRED_MAX + 1)));
+  HTP(K_KRY, true, multidot(ds, c->n3, c->partials, c->pred_dots, s));
+  double* h = c->hscal;
+  HT(hipMemcpyAsync(h, c->pred_dots, sizeof(double) * (ds.nu * k + 1), hipMemcpyDeviceToHost, s));
+  HT(hipStreamSynchronize(s));
+  double d[PRED_MAX], coef[PRED_MAX] = {};
+  for (int i = 0; i < k; ++i) d[i] = h[i];
+  if (c->pred_newrow) {
+    for (int i = 0; i < k; ++i) c->pred_G[newest][i] = c->pred_G[i][newest] = h[k + i];
+    c->pred_newrow = false;
+  }
+  const double bb = h[ds.nu * k];
+  bnorm = std::sqrt(bb);
+  double rr = bb;
+  if (bb > 0.0 && pred_solve(k, c->pred_G, d, coef)) {
+    double cd = 0.0, cgc = 0.0;
+    for (int i = 0; i < k; ++i) {
+      cd += coef[i] * d[i];
+      for (int j = 0; j < k; ++j) cgc += coef[i] * c->pred_G[i][j] * coef[j];
+    }
+    rr = bb - 2.0 * cd + cgc;
+    // the fit cannot do worse than x0 = 0; fall back to it if rounding says so
+    if (!(rr >= 0.0 && rr <= bb)) {
+      for (int i = 0; i < k; ++i) coef[i] = 0.0;
+      rr = bb;
+    }
+  }
+  Combo cb{};
+  for (int i = 0; i < k; ++i) {
+    cb.J[i] = c->pred_j[i];
+    cb.Z[i] = c->pred_z[i];
+    cb.c[i] = coef[i];
+  }
+  cb.k = k;
+  HTP(K_KRY, true, pred_combine(cb, b, x, r0, c->n3, s));
+  rnorm = std::sqrt(rr);
+  return MOT_OK;
+}
+
+// Store the solution x and zx = Z0 x as the newest pair.
+int pred_push(mot_ctx* c, const double* x, const double* zx) {
+  const int h = c->pred_head;
+  if (!c->pred_j[h]) TRY(dmalloc(c, (void**)&c->pred_j[h], sizeof(double) * c->n3));
+  if (!c->pred_z[h]) TRY(dmalloc(c, (void**)&c->pred_z[h], sizeof(double) * c->n3));
+  HT(hipMemcpyAsync(c->pred_j[h], x, sizeof(double) * c->n3, hipMemcpyDeviceToDevice, c->stream));
+  HT(hipMemcpyAsync(c->pred_z[h], zx, sizeof(double) * c->n3, hipMemcpyDeviceToDevice, c->stream));
+  c->pred_head = (h + 1) % c->pred_k;
+  c->pred_count = std::min(c->pred_count + 1, c->pred_k);
+  c->pred_newrow = true;
+  return MOT_OK;
+}
+
 // Solve Z0 x = b (FP64 b, x) in the context precision.
 //   MOT_F64:         FP64 TFQMR, FP64 FFTs.
 //   MOT_F32:         FP32 TFQMR (FP64 inner products), FP32 FFTs.
@@ -571,17 +693,24 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
     HTP(K_KRY, false, vec_f2d(c->kf[V_X], x, n, s));
   } else {
     double** v = c->kv;
-    HTP(K_KRY, true, dot_partial<double>(b, b, n, P, s));
-    HTP(K_KRY, true, reduce_post(P, c->scal, S_B2, POST_NONE, s));
-    TRY(reduce_sync(c));
-    const double bnorm = sqrt(c->hscal[S_B2]);
+    double bnorm = 0.0, rnorm = 0.0;
+    const double* r = b;  // residual of the initial x
+    const bool guess = c->pred_k > 0 && c->pred_count > 0;
+    if (guess) {
+      TRY(pred_guess(c, b, x, v[V_RO], bnorm, rnorm));
+      r = v[V_RO];
+    } else {
+      HTP(K_KRY, true, dot_partial<double>(b, b, n, P, s));
+      HTP(K_KRY, true, reduce_post(P, c->scal, S_B2, POST_NONE, s));
+      TRY(reduce_sync(c));
+      bnorm = rnorm = sqrt(c->hscal[S_B2]);
+      HTP(K_KRY, true, vec_zero<double>(x, n, s));
+    }
     if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
-    HTP(K_KRY, true, vec_zero<double>(x, n, s));
     if (bnorm == 0.0) {
       so.relres = 0.0;
+      if (guess) HTP(K_KRY, true, vec_zero<double>(x, n, s));
     } else {
-      const double* r = b;  // residual of x = 0
-      double rnorm = bnorm;
       const int max_ref = 12;
       // an FP32 TFQMR can stagnate (its recurrence residual keeps falling while
       // the true one stalls): each inner solve gets at most kInnerCap
@@ -590,7 +719,7 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
       constexpr int kInnerCap = 40;
       while (true) {
         ++refinements;
-        double tin = 0.5 * tol * bnorm / rnorm;
+        double tin = rnorm > 0.0 ? 0.5 * tol * bnorm / rnorm : 1.0;
         if (tin < 2e-6) tin = 2e-6;
         SolveOut inner;
         HTP(K_KRY, false, vec_d2f(r, c->kf[V_B], n, P, s));
@@ -619,6 +748,8 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
           break;
         }
       }
+      // the last residual's product is Z0 x: the pair for later guesses
+      if (c->pred_k > 0) TRY(pred_push(c, x, v[V_TMP]));
     }
   }
   if (st) {
@@ -899,6 +1030,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   c->n3 = 3 * c->N;
   c->prec = prec;
   c->ring_f64 = prec == MOT_F64 ? 1 : 0;
+  c->pred_k = 0;  // the initial guess is opt-in (mot_set_predictor)
   c->stream = (hipStream_t)hip_stream;
   const size_t rsz = c->ring_f64 ? sizeof(double) : sizeof(float);
   c->lam_comp = (size_t)(c->nz + 1) * (c->ny + 1) * c->kxs;
@@ -937,7 +1069,8 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
       if ((rc = dmalloc(c, (void**)&c->kf[i], sizeof(float) * c->n3)) != MOT_OK) return fail(rc);
   // the vector kernels' partials, or two sums of one partial per x-pass
   // workgroup (at most one workgroup per row)
-  c->partials_n = 2 * (size_t)std::max<long long>(RED_BLOCKS, 3LL * c->nz * c->ny);
+  c->partials_n = std::max<size_t>(2 * (size_t)std::max<long long>(RED_BLOCKS, 3LL * c->nz * c->ny),
+                                   (size_t)(2 * PRED_MAX + 1) * RED_BLOCKS);
   if ((rc = dmalloc(c, (void**)&c->partials, sizeof(double) * c->partials_n)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->scal, sizeof(double) * S_NSLOT)) != MOT_OK) return fail(rc);
   if (hipHostMalloc((void**)&c->hscal, sizeof(double) * 3 * S_NSLOT, hipHostMallocDefault) != hipSuccess) {
@@ -976,6 +1109,11 @@ int mot_destroy(mot_ctx* c) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   for (int i = 0; i < 2; ++i)
     if (c->evq[i]) (void)hipEventDestroy(c->evq[i]);
+  for (int i = 0; i < PRED_MAX; ++i) {
+    if (c->pred_j[i]) (void)hipFree(c->pred_j[i]);
+    if (c->pred_z[i]) (void)hipFree(c->pred_z[i]);
+  }
+  if (c->pred_dots) (void)hipFree(c->pred_dots);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->hscal) (void)hipHostFree(c->hscal);
@@ -1005,6 +1143,7 @@ double mot_spectra_imag(const mot_ctx* c) { return c ? c->spectra_imag : -1.0; }
 
 int mot_set_material(mot_ctx* c, const double* eps_r) {
   if (!c || !eps_r) return MOT_EINVAL;
+  pred_clear(c);
   HT(hipMemcpyAsync(c->eps, eps_r, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream));
   c->have_eps = true;
   return update_right_scale(c);
@@ -1018,6 +1157,7 @@ int mot_green_table(mot_ctx* c, int32_t k, double* out) {
 
 int build_green_spectra(mot_ctx* c) {
   if (!c) return MOT_EINVAL;
+  pred_clear(c);
   hipStream_t s = c->stream;
   const size_t esz = (size_t)c->px * c->py * c->pz;
   const size_t ssz = (size_t)c->pz * c->py * c->kxs;  // complex elements of one component's spectrum
@@ -1195,6 +1335,7 @@ int mot_profile_read(mot_ctx* c, double* ms, int64_t* counts, int32_t n) {
 
 int mot_reset(mot_ctx* c) {
   if (!c) return MOT_EINVAL;
+  pred_clear(c);
   const size_t rsz = c->ring_f64 ? sizeof(double) : sizeof(float);
   TRY(zero_bytes(c, c->ring, rsz * 2 * c->slot_elems * c->nl));
   TRY(zero_bytes(c, c->hrhs, sizeof(double) * c->n3));
@@ -1207,6 +1348,7 @@ int mot_reset(mot_ctx* c) {
 
 int mot_set_step(mot_ctx* c, int64_t n) {
   if (!c || n < 0) return MOT_EINVAL;
+  pred_clear(c);
   c->nstep = n;
   c->head = (int)((n + c->nl - 1) % c->nl);
   c->blk_n0 = -1;
@@ -1264,6 +1406,13 @@ int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* ein
   return MOT_OK;
 }
 
+int mot_set_predictor(mot_ctx* c, int32_t k) {
+  if (!c || k < 0 || k > PRED_MAX || (k > 0 && c->prec != MOT_F32_REFINED)) return MOT_EINVAL;
+  c->pred_k = k;
+  pred_clear(c);
+  return MOT_OK;
+}
+
 int mot_set_graphs(mot_ctx* c, int32_t on) {
   if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
   c->use_graphs = on;
@@ -1272,6 +1421,7 @@ int mot_set_graphs(mot_ctx* c, int32_t on) {
 
 int mot_set_adjoint(mot_ctx* c, int32_t on) {
   if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
+  if (c->adjoint != on) pred_clear(c);
   c->adjoint = on;
   return MOT_OK;
 }

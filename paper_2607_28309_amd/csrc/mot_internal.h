@@ -76,6 +76,25 @@ hipError_t reduce_post2(const double* partials, double* scal, int slot1, int pos
 hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only = false);
 // x += scal[slot] d
 template <typename V> hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipStream_t s);
+// Initial guess from earlier solutions (at most PRED_MAX pairs J_i, Z0 J_i).
+constexpr int PRED_MAX = 8;
+struct DotSet {
+  const double* u[2];        // u[0] = b; u[1] = the newest Z0 J (may be null)
+  const double* w[PRED_MAX]; // the stored Z0 J_i
+  int nu, nw;
+};
+// Dots u_j . w_i (index j nw + i), then u_0 . u_0 (index nu nw): one pass
+// over the vectors, RED_BLOCKS partials per dot, then one block per dot
+// sums them in a fixed order into out (device).
+hipError_t multidot(const DotSet& ds, long long n, double* partials, double* out, hipStream_t s);
+struct Combo {
+  const double* J[PRED_MAX];
+  const double* Z[PRED_MAX];
+  double c[PRED_MAX];
+  int k;
+};
+// x0 = sum_i c_i J_i, r0 = b - sum_i c_i Z_i
+hipError_t pred_combine(const Combo& cb, const double* b, double* x0, double* r0, long long n, hipStream_t s);
 // x *= rs per voxel (x: components of nvox values each)
 template <typename V> hipError_t vec_scale_voxel(V* x, const V* rs, long long n, long long nvox, hipStream_t s);
 template <typename V> hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hipStream_t s);
