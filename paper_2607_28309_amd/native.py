@@ -9,6 +9,12 @@ no CPU fallback.
 import ctypes
 import os
 
+# torch ships its own HIP runtime: load it before the library so that the
+# library binds to that runtime (loading the library first would pull in a
+# second copy from the system ROCm, whose device memory and streams are not
+# torch's)
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmotjvie.so")
 

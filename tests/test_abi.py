@@ -34,6 +34,18 @@ def test_library_exports_every_declared_symbol():
     assert set(native.EXPORTS) == set(_declared())
 
 
+def test_binding_uses_torchs_hip_runtime():
+    # importing the binding first must not map a second HIP runtime beside
+    # torch's (torch's device memory and streams belong to its own copy)
+    import subprocess
+    import sys
+    code = ("import paper_2607_28309_amd.native, torch\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True)
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1 and os.path.dirname(libs[0]).endswith(os.path.join("torch", "lib")), libs
+
+
 @pytest.mark.parametrize("n,alpha", [((16, 16, 16), 1), ((64, 64, 64), 8), ((96, 96, 96), 1),
                                      ((320, 320, 48), 16), ((9, 7, 5), 3), ((1, 1, 1), 4)])
 def test_nlags_bit_exact(n, alpha):
