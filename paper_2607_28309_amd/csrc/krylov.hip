@@ -254,17 +254,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_add64(const double* __restrict_
 __global__ void k_acc_f2d(double* __restrict__ x, const float* __restrict__ d, long long n) {
   GRID_STRIDE(i, n) x[i] += (double)d[i];
 }
-// out = (float) in, and |out|^2 partials
-__global__ __launch_bounds__(RED_THREADS) void k_d2f(const double* __restrict__ in, float* __restrict__ out,
-                                                     long long n, double* partials) {
-  double acc = 0.0;
-  GRID_STRIDE(i, n) {
-    const float v = (float)in[i];
-    out[i] = v;
-    acc += (double)v * (double)v;
-  }
-  block_partial(acc, partials);
-}
 __global__ void k_f2d(const float* __restrict__ in, double* __restrict__ out, long long n) {
   GRID_STRIDE(i, n) out[i] = (double)in[i];
 }
@@ -355,6 +344,25 @@ __global__ void k_tfqmr_init(const V* __restrict__ r0, V* __restrict__ w, V* __r
   }
 }
 
+// w = u = rt = (float) r0, d = 0, x = 0, and |w|^2 partials (the start of
+// an inner FP32 solve on an FP64 residual)
+__global__ __launch_bounds__(RED_THREADS) void k_tfqmr_init_d2f(const double* __restrict__ r0, float* __restrict__ w,
+                                                                float* __restrict__ u, float* __restrict__ rt,
+                                                                float* __restrict__ d, float* __restrict__ x,
+                                                                long long n, double* partials) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) {
+    const float r = (float)r0[i];
+    w[i] = r;
+    u[i] = r;
+    rt[i] = r;
+    d[i] = 0.0f;
+    x[i] = 0.0f;
+    acc += (double)r * (double)r;
+  }
+  block_partial(acc, partials);
+}
+
 // v = au (start); v . rt
 template <typename V>
 __global__ __launch_bounds__(RED_THREADS) void k_v0(V* __restrict__ v, const V* __restrict__ au,
@@ -426,9 +434,6 @@ hipError_t vec_add64(const double* a, const double* b, double* out, long long n,
   LAUNCH(k_add64, a, b, out, n, partials);
 }
 hipError_t vec_acc_f2d(double* x, const float* d, long long n, hipStream_t s) { LAUNCH(k_acc_f2d, x, d, n); }
-hipError_t vec_d2f(const double* in, float* out, long long n, double* partials, hipStream_t s) {
-  LAUNCH(k_d2f, in, out, n, partials);
-}
 hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s) { LAUNCH(k_f2d, in, out, n); }
 hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s) { LAUNCH(k_copy, a, out, n); }
 template <typename V>
@@ -438,6 +443,10 @@ hipError_t vec_zero(V* a, long long n, hipStream_t s) {
 template <typename V>
 hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, hipStream_t s) {
   LAUNCH(k_tfqmr_init<V>, r0, w, u, rt, d, x, n);
+}
+hipError_t tfqmr_init_d2f(const double* r0, float* w, float* u, float* rt, float* d, float* x, long long n,
+                          double* partials, hipStream_t s) {
+  LAUNCH(k_tfqmr_init_d2f, r0, w, u, rt, d, x, n, partials);
 }
 template <typename V>
 hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials, hipStream_t s, Gate g) {

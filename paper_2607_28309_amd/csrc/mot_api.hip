@@ -385,8 +385,12 @@ template <> struct KV<float> {
 // iteration enqueued after convergence does nothing.
 // bound_only: the quasi-residual bound alone ends the solve (no true
 // residual products); the pending x update is applied at the end.
+// b64 (FP32 solves only): the right-hand side is the FP64 vector b64 rounded
+// to FP32, formed by the start kernel itself (b is then not read: the
+// rounded copy r~ = r0 stands in for it).
 template <typename V>
-int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, bool bound_only = false) {
+int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, bool bound_only = false,
+          const double* b64 = nullptr) {
   hipStream_t s = c->stream;
   const long long n = c->n3;
   V** v = KV<V>::get(c);
@@ -395,9 +399,19 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   const bool f64 = sizeof(V) == 8;
   const motfft::Gate RUN{sc + S_DONE, 1}, CHK{sc + S_DONE, 2};
   HTP(K_KRY, f64, solver_setup(sc, tol, max_iter, s, bound_only));
-  HTP(K_KRY, f64, dot_partial<V>(b, b, n, P, s));
+  // w = u = r~ = r0 = b, d = 0, x = 0 (also for b = 0)
+  if constexpr (sizeof(V) == 4) {
+    if (b64) {
+      HTP(K_KRY, f64, tfqmr_init_d2f(b64, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, P, s));
+      b = v[V_RT];
+    }
+  }
+  if (!b) return set_err(c, MOT_EINVAL, "TFQMR without a right-hand side%s%d");
+  if (sizeof(V) == 8 || !b64) {
+    HTP(K_KRY, f64, dot_partial<V>(b, b, n, P, s));
+    HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));
+  }
   HTP(K_KRY, f64, reduce_post(P, sc, S_B2, POST_INIT, s));
-  HTP(K_KRY, f64, tfqmr_init<V>(b, v[V_W], v[V_U], v[V_RT], v[V_D], x, n, s));  // x = 0 also for b = 0
   // the solver's operator is Z0 diag(rs) (right scaling by the inverse
   // diagonal of Z0); its solution y gives x = rs y at the end
   const V* rs = f64 ? (const V*)c->rs64 : (const V*)c->rs32;
@@ -678,7 +692,9 @@ int pred_push(mot_ctx* c, const double* x, const double* zx) {
 //   MOT_F32:         FP32 TFQMR (FP64 inner products), FP32 FFTs.
 //   MOT_F32_REFINED: repeated FP32 inner solves of Z0 e = r on the FP64
 //                    residual r = b - Z0 x (FP64 FFT product), x += e.
-int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_stats* st) {
+// b2_partials: the reduction partials of |b|^2 are already in c->partials
+// (left by the kernel that formed b).
+int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_stats* st, bool b2_partials = false) {
   SolveOut so;
   int rc = MOT_OK;
   int refinements = 0;
@@ -688,28 +704,27 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
   if (c->prec == MOT_F64) {
     rc = tfqmr<double>(c, b, x, tol, max_iter, &so);
   } else if (c->prec == MOT_F32) {
-    HTP(K_KRY, false, vec_d2f(b, c->kf[V_B], n, P, s));
-    rc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tol, max_iter, &so);
+    rc = tfqmr<float>(c, nullptr, c->kf[V_X], tol, max_iter, &so, false, b);
     HTP(K_KRY, false, vec_f2d(c->kf[V_X], x, n, s));
   } else {
     double** v = c->kv;
-    double bnorm = 0.0, rnorm = 0.0;
+    // without a guess, |b| stays on the device until the first FP64
+    // residual comes back (the first inner tolerance does not depend on it;
+    // the inner solve itself stops at once on b = 0 or a non-finite b)
+    double bnorm = -1.0, rnorm = -1.0;
     const double* r = b;  // residual of the initial x
     const bool guess = c->pred_k > 0 && c->pred_count > 0;
     if (guess) {
       TRY(pred_guess(c, b, x, v[V_RO], bnorm, rnorm));
       r = v[V_RO];
+      if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
     } else {
-      HTP(K_KRY, true, dot_partial<double>(b, b, n, P, s));
-      HTP(K_KRY, true, reduce_post(P, c->scal, S_B2, POST_NONE, s));
-      TRY(reduce_sync(c));
-      bnorm = rnorm = sqrt(c->hscal[S_B2]);
-      HTP(K_KRY, true, vec_zero<double>(x, n, s));
+      if (!b2_partials) HTP(K_KRY, true, dot_partial<double>(b, b, n, P, s));
+      HTP(K_KRY, true, reduce_post(P, c->scal, S_OB2, POST_NONE, s));
     }
-    if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
     if (bnorm == 0.0) {
       so.relres = 0.0;
-      if (guess) HTP(K_KRY, true, vec_zero<double>(x, n, s));
+      HTP(K_KRY, true, vec_zero<double>(x, n, s));
     } else {
       const int max_ref = 12;
       // an FP32 TFQMR can stagnate (its recurrence residual keeps falling while
@@ -719,32 +734,43 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
       constexpr int kInnerCap = 40;
       while (true) {
         ++refinements;
-        double tin = rnorm > 0.0 ? 0.5 * tol * bnorm / rnorm : 1.0;
+        double tin = bnorm < 0.0 ? 0.5 * tol : rnorm > 0.0 ? 0.5 * tol * bnorm / rnorm : 1.0;
         // FP32 floor of the inner tolerance: the solve stops on its bound,
         // which sits well above the true residual, and the FP64 residual
         // below decides (a looser floor would risk second sweeps)
         if (tin < 3e-6) tin = 3e-6;
         SolveOut inner;
-        HTP(K_KRY, false, vec_d2f(r, c->kf[V_B], n, P, s));
         const int left = max_iter - so.iters;
         const int cap = left < kInnerCap ? (left > 1 ? left : 1) : kInnerCap;
-        // the inner solve stops on its quasi-residual bound: the FP64
-        // residual below is its check
-        int irc = tfqmr<float>(c, c->kf[V_B], c->kf[V_X], tin, cap, &inner, true);
+        // the inner solve (on r rounded to FP32) stops on its quasi-residual
+        // bound: the FP64 residual below is its check
+        int irc = tfqmr<float>(c, nullptr, c->kf[V_X], tin, cap, &inner, true, r);
         so.iters += inner.iters;
         so.matvecs += inner.matvecs;
         if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
-        HTP(K_KRY, true, vec_acc_f2d(x, c->kf[V_X], n, s));
+        // x = e on the first sweep from x = 0, else x += e
+        if (refinements == 1 && !guess)
+          HTP(K_KRY, true, vec_f2d(c->kf[V_X], x, n, s));
+        else
+          HTP(K_KRY, true, vec_acc_f2d(x, c->kf[V_X], n, s));
         TRY(apply_z0(c, x, v[V_TMP]));
         so.matvecs++;
         so.matvecs64++;
         HTP(K_KRY, true, vec_sub<double>(b, v[V_TMP], v[V_RO], n, P, s));
         HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s));
         TRY(reduce_sync(c));
+        if (bnorm < 0.0) {
+          bnorm = sqrt(c->hscal[S_OB2]);
+          if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
+        }
         rnorm = sqrt(c->hscal[S_R2]);
         r = v[V_RO];
-        so.relres = rnorm / bnorm;
         if (!std::isfinite(rnorm)) return set_err(c, MOT_ENONFINITE, "refined residual is not finite%s%d");
+        if (bnorm == 0.0) {  // b = 0: the inner solve left x = 0
+          so.relres = 0.0;
+          break;
+        }
+        so.relres = rnorm / bnorm;
         if (so.relres <= tol) break;
         if (refinements >= max_ref || so.iters >= max_iter) {
           rc = set_err(c, MOT_ENOCONV, "refinement did not reach the tolerance%s%d");
@@ -1366,7 +1392,7 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
   double* x = c->kv[V_X];
   if (st) HT(hipEventRecord(c->ev[0], s));
   HTP(K_KRY, true, vec_add64(einc, c->hrhs, b, c->n3, c->partials, s));
-  int rc = solve(c, b, x, tol, max_iter, st);
+  int rc = solve(c, b, x, tol, max_iter, st, true);
   if (rc != MOT_OK && rc != MOT_ENOCONV && rc != MOT_EBREAKDOWN) return rc;
   if (c->prec == MOT_F32_REFINED || rc == MOT_OK || rc == MOT_ENOCONV || rc == MOT_EBREAKDOWN)
     HT(hipMemcpyAsync(J_n, x, sizeof(double) * c->n3, hipMemcpyDeviceToDevice, s));

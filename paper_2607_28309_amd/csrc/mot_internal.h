@@ -30,6 +30,7 @@ enum Slot {
   S_X2,
   S_ETAP,  // coefficient of an x update still to be applied (x += etap d)
   S_BOUND_ONLY,  // 1: the quasi-residual bound ends the solve (no true residual)
+  S_OB2,         // |b|^2 of the refined solve's FP64 right-hand side
   // device-side convergence state of a solve (S_CHECK must follow S_DONE:
   // the launch gates read the pair)
   S_DONE,
@@ -104,10 +105,12 @@ template <typename V> hipError_t vec_zero(V* a, long long n, hipStream_t s);
 hipError_t vec_add64(const double* a, const double* b, double* out, long long n, double* partials,
                      hipStream_t s);  // out = a + b, partials of |out|^2
 hipError_t vec_acc_f2d(double* x, const float* d, long long n, hipStream_t s);  // x += d
-hipError_t vec_d2f(const double* in, float* out, long long n, double* partials, hipStream_t s);
 hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s);
 hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s);
 template <typename V> hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, hipStream_t s);
+// the same start from an FP64 r0 rounded to FP32, with |r0|^2 partials
+hipError_t tfqmr_init_d2f(const double* r0, float* w, float* u, float* rt, float* d, float* x, long long n,
+                          double* partials, hipStream_t s);
 template <typename V> hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long long n, double* partials,
                                           hipStream_t s, Gate g);
 
