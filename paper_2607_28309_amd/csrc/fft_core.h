@@ -44,7 +44,7 @@ template <bool INV, typename C> __device__ __forceinline__ C mul_i(C a) {
 }
 
 // cos/sin of 2 pi j / 8 (j < 4): the rotations of the radix-2 split of a
-// length-8 DFT (lengths 6 and 10 use the prime-factor mapping, no rotations)
+// length-8 DFT (lengths 6, 10 and 12 use the prime-factor mapping, no rotations)
 __host__ __device__ constexpr double rot_cos(int, int j) {
   return j == 0 ? 1.0 : j == 1 ? 0.70710678118654752440 : j == 2 ? 0.0 : -0.70710678118654752440;
 }
@@ -65,7 +65,7 @@ __device__ __forceinline__ cpx<T> rotate(cpx<T> d, int j) {
 // run_half: the same with v[R/2..R-1] = 0 (those registers are not read).
 template <int R, bool INV, typename T> struct Dft {
   // radix 8 = 2 x 4: radix-2 split, rotate the odd half, two DFT_4
-  static_assert(R == 8, "composite radices: 8 here, 6 and 10 by PfaDft");
+  static_assert(R == 8, "composite radices: 8 here, 6 and 10 by PfaDft, 12 by its own prime-factor form");
   static constexpr int Q = R / 2;
   static __device__ __forceinline__ void finish(cpx<T>* v, cpx<T>* a, cpx<T>* b) {
     Dft<Q, INV, T>::run(a);
@@ -198,6 +198,29 @@ template <int Q, bool INV, typename T> struct PfaDft {
   }
 };
 template <bool INV, typename T> struct Dft<6, INV, T> : PfaDft<3, INV, T> {};
+
+// Length 12 = 3 x 4 by the prime-factor mapping: input n = (4 n1 + 3 n2) mod
+// 12, output k = (4 k1 + 9 k2) mod 12 give W_12^{nk} = W_3^{n1 k1} W_4^{n2 k2}
+// (4 = 1 mod 3, 9 = 1 mod 4), so four length-3 DFTs over n1 feed three
+// length-4 DFTs over n2 with no rotations between them.
+template <bool INV, typename T> struct Dft<12, INV, T> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> a[4][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 3; ++n1) a[n2][n1] = v[(4 * n1 + 3 * n2) % 12];
+      Dft<3, INV, T>::run(a[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      cpx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, INV, T>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[(4 * k1 + 9 * k2) % 12] = b[k2];
+    }
+  }
+};
 template <bool INV, typename T> struct Dft<10, INV, T> : PfaDft<5, INV, T> {};
 
 template <int... Rs> struct RadixList {};
@@ -297,7 +320,7 @@ MOT_PLAN(40, 4, 10)
 MOT_PLAN(48, 4, 4, 3)
 MOT_PLAN(64, 8, 8)
 MOT_PLAN(80, 4, 4, 5)
-MOT_PLAN(96, 4, 4, 6)
+MOT_PLAN(96, 8, 12)
 MOT_PLAN(120, 2, 2, 6, 5)
 MOT_PLAN(128, 8, 4, 4)
 MOT_PLAN(160, 4, 4, 10)

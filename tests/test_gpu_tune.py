@@ -19,7 +19,8 @@ pytestmark = pytest.mark.gpu
 
 KNOBS = ("x", "y", "z_history", "z_fused")
 # grids whose tiles end in ragged tails, with tile widths that differ between variants
-GRIDS = [((40, 12, 6), 2), ((80, 24, 10), 4), ((48, 40, 24), 2), ((16, 16, 48), 4)]
+# (96, 48, 4): the 96-point plan (radices 8 and 12) in the x and y passes
+GRIDS = [((40, 12, 6), 2), ((80, 24, 10), 4), ((48, 40, 24), 2), ((16, 16, 48), 4), ((96, 48, 4), 2)]
 
 
 def _t(a, dtype=None):
