@@ -250,13 +250,6 @@ __global__ __launch_bounds__(RED_THREADS) void k_add64(const double* __restrict_
   block_partial(acc, partials);
 }
 
-// x (FP64) += d (FP32)
-__global__ void k_acc_f2d(double* __restrict__ x, const float* __restrict__ d, long long n) {
-  GRID_STRIDE(i, n) x[i] += (double)d[i];
-}
-__global__ void k_f2d(const float* __restrict__ in, double* __restrict__ out, long long n) {
-  GRID_STRIDE(i, n) out[i] = (double)in[i];
-}
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ out, long long n) {
   GRID_STRIDE(i, n) out[i] = a[i];
 }
@@ -320,6 +313,26 @@ __global__ void k_pred_combine(Combo cb, const double* __restrict__ b, double* _
 template <typename V>
 __global__ void k_scale_voxel(V* __restrict__ x, const V* __restrict__ rs, long long n, long long nvox) {
   GRID_STRIDE(i, n) x[i] *= rs[i % nvox];
+}
+
+// The end of an inner FP32 solve handed to the FP64 iterate: per voxel v and
+// component, t = (x32 + coef d) rs[v] in FP32 (coef null: no update), then
+// x64 = t or x64 += t.
+__global__ void k_finish_f2d(const float* __restrict__ x32, const float* __restrict__ d,
+                             const double* __restrict__ coef, const float* __restrict__ rs,
+                             double* __restrict__ x64, long long nvox, int acc) {
+  const float a = coef ? (float)*coef : 0.0f;
+  GRID_STRIDE(v, nvox) {
+    const float r = rs[v];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const long long i = c * nvox + v;
+      float t = x32[i];
+      if (coef) t += a * d[i];
+      t *= r;
+      x64[i] = acc ? x64[i] + (double)t : (double)t;
+    }
+  }
 }
 
 // x += coef d (coef read on the device)
@@ -414,6 +427,10 @@ template <typename V>
 hipError_t vec_scale_voxel(V* x, const V* rs, long long n, long long nvox, hipStream_t s) {
   LAUNCH(k_scale_voxel<V>, x, rs, n, nvox);
 }
+hipError_t finish_f2d(const float* x32, const float* d, const double* coef, const float* rs, double* x64,
+                      long long nvox, bool acc, hipStream_t s) {
+  LAUNCH(k_finish_f2d, x32, d, coef, rs, x64, nvox, acc ? 1 : 0);
+}
 hipError_t multidot(const DotSet& ds, long long n, double* partials, double* out, hipStream_t s) {
   if (ds.nu < 1 || ds.nu > 2 || ds.nw < 0 || ds.nw > PRED_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_multidot, RG(), RB(), 0, s, ds, n, partials);
@@ -433,8 +450,6 @@ hipError_t vec_sub(const V* a, const V* b, V* out, long long n, double* partials
 hipError_t vec_add64(const double* a, const double* b, double* out, long long n, double* partials, hipStream_t s) {
   LAUNCH(k_add64, a, b, out, n, partials);
 }
-hipError_t vec_acc_f2d(double* x, const float* d, long long n, hipStream_t s) { LAUNCH(k_acc_f2d, x, d, n); }
-hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s) { LAUNCH(k_f2d, in, out, n); }
 hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s) { LAUNCH(k_copy, a, out, n); }
 template <typename V>
 hipError_t vec_zero(V* a, long long n, hipStream_t s) {

@@ -387,10 +387,11 @@ template <> struct KV<float> {
 // residual products); the pending x update is applied at the end.
 // b64 (FP32 solves only): the right-hand side is the FP64 vector b64 rounded
 // to FP32, formed by the start kernel itself (b is then not read: the
-// rounded copy r~ = r0 stands in for it).
+// rounded copy r~ = r0 stands in for it).  x64 (FP32 solves only): the
+// solution goes to x64 (x64_acc: added to it) instead of x.
 template <typename V>
 int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, bool bound_only = false,
-          const double* b64 = nullptr) {
+          const double* b64 = nullptr, double* x64 = nullptr, bool x64_acc = false) {
   hipStream_t s = c->stream;
   const long long n = c->n3;
   V** v = KV<V>::get(c);
@@ -554,10 +555,21 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
       h = bank;
     }
   }
+  // a solve ended by the bound leaves the second half step's x update
+  // pending; the solution is x = rs y
+  bool finished = false;
+  if constexpr (sizeof(V) == 4) {
+    if (x64) {
+      HTP(K_KRY, f64, finish_f2d(x, v[V_D], bound_only ? sc + S_ETAP : nullptr, (const float*)rs, x64, c->N,
+                                 x64_acc, s));
+      finished = true;
+    }
+  }
+  if (!finished) {
+    if (bound_only) HTP(K_KRY, f64, vec_axpy_scal<V>(x, v[V_D], sc + S_ETAP, n, s));
+    HTP(K_KRY, f64, vec_scale_voxel<V>(x, rs, n, c->N, s));
+  }
   if (!h || h[S_DONE] == 0.0) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
-  // a solve ended by the bound leaves the second half step's x update pending
-  if (bound_only) HTP(K_KRY, f64, vec_axpy_scal<V>(x, v[V_D], sc + S_ETAP, n, s));
-  HTP(K_KRY, f64, vec_scale_voxel<V>(x, rs, n, c->N, s));
   so->iters = (int)h[S_ITER];
   so->matvecs += (int)h[S_NMV];
   if (f64) so->matvecs64 += (int)h[S_NMV];
@@ -704,8 +716,7 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
   if (c->prec == MOT_F64) {
     rc = tfqmr<double>(c, b, x, tol, max_iter, &so);
   } else if (c->prec == MOT_F32) {
-    rc = tfqmr<float>(c, nullptr, c->kf[V_X], tol, max_iter, &so, false, b);
-    HTP(K_KRY, false, vec_f2d(c->kf[V_X], x, n, s));
+    rc = tfqmr<float>(c, nullptr, c->kf[V_X], tol, max_iter, &so, false, b, x);
   } else {
     double** v = c->kv;
     // without a guess, |b| stays on the device until the first FP64
@@ -744,15 +755,11 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
         const int cap = left < kInnerCap ? (left > 1 ? left : 1) : kInnerCap;
         // the inner solve (on r rounded to FP32) stops on its quasi-residual
         // bound: the FP64 residual below is its check
-        int irc = tfqmr<float>(c, nullptr, c->kf[V_X], tin, cap, &inner, true, r);
+        // (x = e on the first sweep from x = 0, else x += e)
+        int irc = tfqmr<float>(c, nullptr, c->kf[V_X], tin, cap, &inner, true, r, x, refinements > 1 || guess);
         so.iters += inner.iters;
         so.matvecs += inner.matvecs;
         if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
-        // x = e on the first sweep from x = 0, else x += e
-        if (refinements == 1 && !guess)
-          HTP(K_KRY, true, vec_f2d(c->kf[V_X], x, n, s));
-        else
-          HTP(K_KRY, true, vec_acc_f2d(x, c->kf[V_X], n, s));
         TRY(apply_z0(c, x, v[V_TMP]));
         so.matvecs++;
         so.matvecs64++;

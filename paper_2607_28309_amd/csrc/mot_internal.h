@@ -104,10 +104,12 @@ template <typename V> hipError_t vec_sub(const V* a, const V* b, V* out, long lo
 template <typename V> hipError_t vec_zero(V* a, long long n, hipStream_t s);
 hipError_t vec_add64(const double* a, const double* b, double* out, long long n, double* partials,
                      hipStream_t s);  // out = a + b, partials of |out|^2
-hipError_t vec_acc_f2d(double* x, const float* d, long long n, hipStream_t s);  // x += d
-hipError_t vec_f2d(const float* in, double* out, long long n, hipStream_t s);
 hipError_t vec_copy(const double* a, double* out, long long n, hipStream_t s);
 template <typename V> hipError_t tfqmr_init(const V* r0, V* w, V* u, V* rt, V* d, V* x, long long n, hipStream_t s);
+// x64 (= or +=) (x32 + coef d) rs per voxel (3 components of nvox voxels);
+// coef may be null (no update)
+hipError_t finish_f2d(const float* x32, const float* d, const double* coef, const float* rs, double* x64,
+                      long long nvox, bool acc, hipStream_t s);
 // the same start from an FP64 r0 rounded to FP32, with |r0|^2 partials
 hipError_t tfqmr_init_d2f(const double* r0, float* w, float* u, float* rt, float* d, float* x, long long n,
                           double* partials, hipStream_t s);
