@@ -242,10 +242,16 @@ template <int M, int R, int... Rest> struct FirstRadix<M, RadixList<R, Rest...>>
 // Run the stages of RadixList on registers v (inputs of the first remaining
 // stage already loaded).  `store(p, jt, u, value)` receives the outputs of
 // the last stage, element jt + u.
-template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, typename L> struct Stages;
+//
+// SPLIT: the exchanges move the real parts and then the imaginary parts
+// through an LDS buffer of M * np reals (half the bytes of a complex buffer,
+// so twice the pencils fit a CU's LDS; four barriers per exchange instead of
+// two).  The registers a phase reads into hold values already written out.
+template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, typename L, bool SPLIT = false>
+struct Stages;
 
-template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, int R, int... Rest>
-struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>> {
+template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, int R, int... Rest, bool SPLIT>
+struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>, SPLIT> {
   template <typename Store>
   static __device__ __forceinline__ void run(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt,
                                              int np, Store&& store) {
@@ -283,23 +289,49 @@ struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>> {
           store(p, jt, u, v[t * R + r]);
         }
     } else {
-#pragma unroll
-      for (int t = 0; t < B; ++t) {
-        const int j = jt + t * TJ;
-        const int base = (j / NS) * NS * R + (j % NS);
-#pragma unroll
-        for (int r = 0; r < R; ++r) lds[(base + r * NS) * np + p] = v[t * R + r];
-      }
-      __syncthreads();
       constexpr int R2 = FirstRadix<M, RadixList<Rest...>>::value;
       constexpr int B2 = M / (R2 * TJ);
       constexpr int MR2 = M / R2;
+      if constexpr (!SPLIT) {
 #pragma unroll
-      for (int t = 0; t < B2; ++t)
+        for (int t = 0; t < B; ++t) {
+          const int j = jt + t * TJ;
+          const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[(jt + t * TJ + r * MR2) * np + p];
-      __syncthreads();
-      Stages<T, M, TJ, INV, NS * R, false, HOUT, RadixList<Rest...>>::run(v, lds, tw, p, jt, np, store);
+          for (int r = 0; r < R; ++r) lds[(base + r * NS) * np + p] = v[t * R + r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < B2; ++t)
+#pragma unroll
+          for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[(jt + t * TJ + r * MR2) * np + p];
+        __syncthreads();
+      } else {
+        T* ldr = reinterpret_cast<T*>(lds);
+#pragma unroll
+        for (int part = 0; part < 2; ++part) {
+#pragma unroll
+          for (int t = 0; t < B; ++t) {
+            const int j = jt + t * TJ;
+            const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+            for (int r = 0; r < R; ++r) ldr[(base + r * NS) * np + p] = part ? v[t * R + r].y : v[t * R + r].x;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int t = 0; t < B2; ++t)
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+              const T val = ldr[(jt + t * TJ + r * MR2) * np + p];
+              if (part)
+                v[t * R2 + r].y = val;
+              else
+                v[t * R2 + r].x = val;
+            }
+          __syncthreads();
+        }
+      }
+      Stages<T, M, TJ, INV, NS * R, false, HOUT, RadixList<Rest...>, SPLIT>::run(v, lds, tw, p, jt, np, store);
     }
   }
 };
@@ -359,11 +391,11 @@ __device__ __forceinline__ void load_first(cpx<T>* v, int p, int jt, Load&& elem
     for (int r = 0; r < (HIN ? R / 2 : R); ++r) v[t * R + r] = elem(p, jt, t * PI::TJ + r * (M / R));
 }
 
-template <typename T, int M, bool INV, bool HIN, bool HOUT, typename Store>
+template <typename T, int M, bool INV, bool HIN, bool HOUT, bool SPLIT = false, typename Store>
 __device__ __forceinline__ void run_fft(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt, int np,
                                         Store&& store) {
   using PI = PlanInfo<M>;
-  Stages<T, M, PI::TJ, INV, 1, HIN, HOUT, typename PI::list>::run(v, lds, tw, p, jt, np, store);
+  Stages<T, M, PI::TJ, INV, 1, HIN, HOUT, typename PI::list, SPLIT>::run(v, lds, tw, p, jt, np, store);
 }
 
 }  // namespace motfft

@@ -28,10 +28,12 @@ constexpr int LDS_BUDGET = 81920;
 //
 // Tile-shape variants (chosen per context by the autotuner): V = 0 is the
 // default shape.  V = 1: the x pass takes 3 (NP0 / 4) rows (whole voxel rows
-// of all three components, fewer rows per workgroup); the y pass doubles its
-// columns when the doubled tile fits a workgroup (full 128-byte lines for
-// narrow tiles), else halves them; the z passes halve their columns (twice
-// the workgroups, half the LDS each).
+// of all three components, fewer rows per workgroup); the y pass exchanges
+// real and imaginary parts in turn through a buffer of half the bytes and
+// doubles its columns when the doubled tile fits a workgroup (twice the
+// pencils in flight per CU); the z passes without the spectral multiply do
+// the same split with their variant-0 tile; the fused z pass halves its
+// columns (twice the workgroups, half the LDS each).
 constexpr size_t LDS_MAX = 160 * 1024;
 template <typename T, int M, int V = 0> struct XCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
@@ -47,22 +49,30 @@ template <typename T, int M, int V = 0> struct YCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
   static constexpr int NP0 = cmax(1, floor_pow2(cmin(cmin(256 / TJ, 32), (LDS_BUDGET - M * SZ) / (M * SZ) - 1)));
-  static constexpr bool DBL = 2 * NP0 * TJ <= 1024 && (size_t)(M * (2 * NP0 + 1) + M) * SZ <= LDS_MAX;
-  static constexpr int NP = V == 0 ? NP0 : (DBL ? 2 * NP0 : cmax(1, NP0 / 2));
+  // variant 1: split exchanges (real parts, then imaginary parts) and twice
+  // the columns when that fits a workgroup
+  static constexpr bool SPLIT = V == 1;
+  static constexpr int NP = V == 0 ? NP0 : (2 * NP0 * TJ <= 1024 ? 2 * NP0 : NP0);
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
-  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
+  static constexpr size_t BUF = (size_t)M * NPS * (SPLIT ? sizeof(T) : sizeof(cpx<T>));  // exchange buffer bytes
+  static constexpr size_t LDS = BUF + (size_t)M * SZ;
+  static_assert(BUF % sizeof(cpx<T>) == 0, "the twiddle table after the buffer is aligned");
 };
 template <typename T, int M, int NC, int V = 0> struct ZCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
   static constexpr int SZ = (int)sizeof(cpx<T>);
   static constexpr int W0 =
       cmax(1, floor_pow2(cmin(cmin(16, 1024 / (NC * TJ)), (LDS_BUDGET - 2 * M * SZ) / (NC * M * SZ))));
-  static constexpr int W = V == 0 ? W0 : cmax(1, W0 / 2);
+  // variant 1: the same tile with split exchanges (half the LDS bytes)
+  static constexpr bool SPLIT = V == 1;
+  static constexpr int W = W0;
   static constexpr int NP = NC * W;
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
-  static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
+  static constexpr size_t BUF = (size_t)M * NPS * (SPLIT ? sizeof(T) : sizeof(cpx<T>));  // exchange buffer bytes
+  static constexpr size_t LDS = BUF + (size_t)M * SZ;
+  static_assert(BUF % sizeof(cpx<T>) == 0, "the twiddle table after the buffer is aligned");
 };
 
 // z pass with the spectral multiply: W kx columns x 3 components x 2 ky rows.

@@ -22,7 +22,7 @@ __global__ __launch_bounds__((ZCfg<T, M, NC, V>::BLOCK)) void k_z_pass(
   const int tile = L % ntx, ky = L / ntx;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + M * NPS;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw + C::BUF);
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
   const int comp = p / W, c = p - comp * W;
   const int kx = tile * W + c;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__((ZCfg<T, M, NC, V>::BLOCK)) void k_z_pass(
   cpx<T> v[PlanInfo<M>::E];
   load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * plane]; });
   load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
-  run_fft<T, M, INV, HIN, HOUT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
+  run_fft<T, M, INV, HIN, HOUT, C::SPLIT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
     if (ok) dst[(size_t)u * plane] = val;
   });
 }
