@@ -12,8 +12,11 @@
 //   P_b = sum_{m>=0} Lambda_{m+b} J^_{n0-m},   b = 1..B,
 // reading every slot and every Lambda_j once (a sliding window of B Lambda
 // values is kept in registers).  Step n0+b-1 then adds only its b-1 newest
-// lags, S_{n0+b} = P_b + sum_{j=1..b-1} Lambda_j J^_{n0+b-j}.  The sums are
-// the same as the plain per-step one, in another order.
+// lags, S_{n0+b} = P_b + sum_{j=1..b-1} Lambda_j J^_{n0+b-j}.  With B = 8 the
+// block has a second level: at step n0+4 one pass of the same kind over the
+// four slots n0+1..n0+4 adds their contributions to P_5..P_8 (the new P_5 is
+// S_{n0+5}), so steps n0+5..n0+7 add at most their three newest lags.  The
+// sums are the same as the plain per-step one, in another order.
 #include <hip/hip_runtime.h>
 
 #include "fft_core.h"
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
       for (int q = 0; q < 3; ++q) out[q * comp + pt.off[i]] = acc[i][q];
 }
 
-// P_b = sum_{m=0..nold-1} Lambda_{m+b} J^_{n0-m} for b = 1..B (Lambda_{>ell} = 0);
+// P_b = init_b + sum_{m=0..nold-1} Lambda_{m+b} J^_{n0-m} for b = 1..B
+// (Lambda_{>ell} = 0; init_b = iblk + (b-1) * slot, or 0 without iblk);
 // P_1 -> out0, P_b -> pblk + (b-2) * slot for b >= 2.  NM = 4: a thread takes
 // all four mirror points of its octant frequency; NM = 2 (for long blocks,
 // whose B accumulators per point would not fit the registers): the two
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
 // (a register budget of 256).
 template <typename T, int B, int NM>
 __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
-                                                   cpx<T>* __restrict__ out0, cpx<T>* __restrict__ pblk, Geo g,
+                                                   cpx<T>* out0, cpx<T>* pblk, const cpx<T>* iblk, Geo g,
                                                    long long n0, int nold) {
   // octant frequencies per workgroup; with NM = 2 the two kz sides of a
   // frequency are neighbouring lanes of one wave, which read its Lambda words
@@ -152,18 +156,27 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
   T w[B][6];  // window: w[b] = Lambda_{m+1+b}
 #pragma unroll
   for (int b = 0; b < B; ++b) lam_at(b + 1, w[b]);
-  cpx<T> acc[B][NM][3];
-#pragma unroll
-  for (int b = 0; b < B; ++b)
-#pragma unroll
-    for (int i = 0; i < NM; ++i)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) acc[b][i][q] = cpx<T>{(T)0, (T)0};
   // With NM = 2 the kz sign sz is known only at run time: the z component of
   // each loaded current is multiplied by sz and the z accumulators carry sz
   // times their value (sz^2 = 1), so that the B multiply-adds per load see
   // compile-time signs only.
   const T sz2 = NM == 2 && pt.a[0] ? (T)-1 : (T)1;
+  cpx<T> acc[B][NM][3];
+#pragma unroll
+  for (int b = 0; b < B; ++b)
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+      if (iblk) {
+        const cpx<T>* I = iblk + (size_t)b * slot;
+        acc[b][i][0] = I[pt.off[i]];
+        acc[b][i][1] = I[comp + pt.off[i]];
+        const cpx<T> z = I[2 * comp + pt.off[i]];
+        acc[b][i][2] = cpx<T>{sz2 * z.x, sz2 * z.y};
+      } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[b][i][q] = cpx<T>{(T)0, (T)0};
+      }
+    }
   for (int m = 0; m < nold; ++m) {
     const cpx<T>* R = ring + (size_t)((n0 - m) % g.nl) * slot;
     cpx<T> jv[NM][3];
@@ -216,15 +229,15 @@ hipError_t launch_mac_recent(const void* ring, const void* lamh, const void* ini
   return hipGetLastError();
 }
 
-hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, int f64, int B, int nl,
-                            long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s) {
+hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, const void* iblk, int f64,
+                            int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s) {
   const Geo g{nx, ny, nz, kxs, nl};
   const dim3 gr = mac_grid(g);
   const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
   const dim3 gr2((unsigned)((cnt + 127) / 128));  // two threads per octant frequency
 #define LB(T, BB, NM, GR)                                                                                 \
   hipLaunchKernelGGL((k_mac_block<T, BB, NM>), GR, dim3(256), 0, s, (const cpx<T>*)ring, (const T*)lamh,   \
-                     (cpx<T>*)out0, (cpx<T>*)pblk, g, n0, nold)
+                     (cpx<T>*)out0, (cpx<T>*)pblk, (const cpx<T>*)iblk, g, n0, nold)
   if (f64) {
     if (B == 1) LB(double, 1, 4, gr);
     else if (B == 2) LB(double, 2, 4, gr);

@@ -820,15 +820,23 @@ int history_update_t(mot_ctx* c, const double* J) {
     // block start: contributions of every slot <= n to the next B right-hand sides
     c->blk_n0 = n;
     const int nold = (int)(n + 1 < c->nl ? n + 1 : c->nl);
-    HTP(K_MAC, d, launch_mac_block(c->ring, c->lamh, c->spec, c->pblk, sizeof(Tr) == 8, c->blk_B, c->nl, n, nold,
-                                   c->nx, c->ny, c->nz, c->kxs, s));
+    HTP(K_MAC, d, launch_mac_block(c->ring, c->lamh, c->spec, c->pblk, nullptr, sizeof(Tr) == 8, c->blk_B, c->nl, n,
+                                   nold, c->nx, c->ny, c->nz, c->kxs, s));
   } else {
-    // inside a block: P_b plus the r = n - n0 newest lags
+    // inside a block: P_{r+1} plus the r = n - n0 newest lags; with B = 8,
+    // step n0 + 4 adds the four slots n0+1..n0+4 to P_5..P_8 in one pass and
+    // later steps add only the lags newer than n0 + 4
     const int r = (int)(n - c->blk_n0);
     const size_t bytes_per_slot = (c->ring_f64 ? 16 : 8) * c->slot_elems;
-    const void* init = (const char*)c->pblk + (size_t)(r - 1) * bytes_per_slot;
-    HTP(K_MACR, d, launch_mac_recent(c->ring, c->lamh, init, c->spec, sizeof(Tr) == 8, c->nl, n, r, c->nx, c->ny,
-                                     c->nz, c->kxs, s));
+    char* pb = (char*)c->pblk;
+    if (c->blk_B == 8 && r == 4) {
+      HTP(K_MACR, d, launch_mac_block(c->ring, c->lamh, c->spec, pb + 4 * bytes_per_slot, pb + 3 * bytes_per_slot,
+                                      sizeof(Tr) == 8, 4, c->nl, n, 4, c->nx, c->ny, c->nz, c->kxs, s));
+    } else {
+      const int nrec = c->blk_B == 8 && r > 4 ? r - 4 : r;
+      HTP(K_MACR, d, launch_mac_recent(c->ring, c->lamh, pb + (size_t)(r - 1) * bytes_per_slot, c->spec,
+                                       sizeof(Tr) == 8, c->nl, n, nrec, c->nx, c->ny, c->nz, c->kxs, s));
+    }
   }
   HTP(K_ZI, d, motfft::z_pass<Tr>(c->spec, c->wsB, c->pz, motfft::Z_INV, 3, c->kx, c->kxs, c->py, c->pz, c->pz,
                                   c->nz, c->nz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));

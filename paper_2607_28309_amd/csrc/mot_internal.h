@@ -120,9 +120,10 @@ template <typename V> hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long l
 // out = init + sum_{j=1..nrec} Lambda_j J^_{n+1-j}   (init may be null)
 hipError_t launch_mac_recent(const void* ring, const void* lamh, const void* init, void* out, int f64, int nl,
                              long long n, int nrec, int nx, int ny, int nz, int kxs, hipStream_t s);
-// P_b = sum_{m<nold} Lambda_{m+b} J^_{n0-m}, b = 1..B: P_1 -> out0, P_b -> pblk + (b-2) slots
-hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, int f64, int B, int nl,
-                            long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s);
+// P_b = init_b + sum_{m<nold} Lambda_{m+b} J^_{n0-m}, b = 1..B: P_1 -> out0,
+// P_b -> pblk + (b-2) slots; init_b = iblk + (b-1) slots (zero if iblk is null)
+hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, const void* iblk, int f64,
+                            int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s);
 
 // ---- mot_api.hip: excitation
 hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* out, int nx, int ny, int nz,
