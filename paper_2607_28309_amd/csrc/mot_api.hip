@@ -524,8 +524,26 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   // can stall for a half step and then drop by orders of magnitude, so the
   // screen is wide: a check that finds nothing costs a few empty launches, a
   // missed one a whole iteration)
-  double tau_last = -1.0, tolb = -1.0;
+  //
+  // The host keeps one iteration enqueued ahead, so a solve that ends in
+  // iteration m leaves iteration m + 1 to run empty behind its gates.  When
+  // the bound extrapolated from the last two known ones (geometric decrease)
+  // says that the iteration in flight will end the solve, the host waits for
+  // it before enqueueing the next: a short idle gap instead of a whole empty
+  // iteration.
+  double tau_last = -1.0, tau_prev = -1.0, tolb = -1.0;
   for (int it = 1; it <= max_iter + 1; ++it) {
+    if (it >= 3 && tau_last > 0.0 && tau_prev > 0.0 && tolb > 0.0 && tau_last < tau_prev) {
+      const double pred = tau_last * (tau_last / tau_prev) * std::sqrt(2.0 * it);
+      if (pred <= 1.5 * tolb) {
+        HT(hipEventSynchronize(c->evq[(it - 1) & 1]));
+        const double* prev = c->hscal + (1 + ((it - 1) & 1)) * S_NSLOT;
+        if (prev[S_DONE] != 0.0) {
+          h = prev;
+          break;
+        }
+      }
+    }
     bool check = !bound_only;
     if (check && tau_last > 0.0 && tolb > 0.0 && it < max_iter)
       check = tau_last * std::sqrt(2.0 * it + 1.0) <= 1e3 * tolb;
@@ -547,6 +565,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
         HTP(K_KRY, f64, vec_sub<V>(b, v[V_TMP], v[V_TMP], n, P, s, CHK));
         HTP(K_KRY, f64, reduce_post(P, sc, S_R2, POST_RESID, s, CHK));
       }
+      tau_prev = tau_last;
       tau_last = prev[S_TAU];
       tolb = prev[S_TOL] * prev[S_BNORM];
     }
