@@ -43,7 +43,10 @@ template <typename T, int M, int V = 0> struct XCfg {
   static constexpr int NP = V == 0 ? NP0 : (NP0 >= 4 ? 3 * (NP0 / 4) : cmax(1, NP0 / 2));
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
-  static constexpr size_t LDS = (size_t)((M + 1) * NPS + 2 * M + 1) * SZ;
+  // FP64: the twiddle tables are read from global memory (L1/L2) instead
+  // of LDS, which leaves room for more rows per CU
+  static constexpr bool TWG = sizeof(T) == 8;
+  static constexpr size_t LDS = (size_t)((M + 1) * NPS + (TWG ? 0 : 2 * M + 1)) * SZ;
 };
 template <typename T, int M, int V = 0> struct YCfg {
   static constexpr int TJ = PlanInfo<M>::TJ;
@@ -56,7 +59,9 @@ template <typename T, int M, int V = 0> struct YCfg {
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
   static constexpr size_t BUF = (size_t)M * NPS * (SPLIT ? sizeof(T) : sizeof(cpx<T>));  // exchange buffer bytes
-  static constexpr size_t LDS = BUF + (size_t)M * SZ;
+  // FP64: the twiddle table is read from global memory (as in XCfg)
+  static constexpr bool TWG = sizeof(T) == 8;
+  static constexpr size_t LDS = BUF + (TWG ? 0 : (size_t)M * SZ);
   static_assert(BUF % sizeof(cpx<T>) == 0, "the twiddle table after the buffer is aligned");
 };
 template <typename T, int M, int NC, int V = 0> struct ZCfg {

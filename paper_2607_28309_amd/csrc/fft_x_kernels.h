@@ -75,8 +75,9 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
   if (gate_closed(gate)) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + (M + 1) * NPS;
-  cpx<T>* tw2 = tw + M;
+  cpx<T>* twl = lds + (M + 1) * NPS;
+  const cpx<T>* tw = C::TWG ? tw_g : twl;
+  const cpx<T>* tw2 = C::TWG ? tw2_g : twl + M;
   using V2 = typename io2<IO>::t;
   const int jt = threadIdx.x % TJ, p = threadIdx.x / TJ;
   const int grow = xrow<NP>(p, ncomp, rows_per_comp, nrows);
@@ -183,8 +184,10 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
       }
     }
   }
-  load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
-  load_table<cpx<T>, M + 1, C::BLOCK>(tw2, tw2_g);
+  if constexpr (!C::TWG) {
+    load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
+    load_table<cpx<T>, M + 1, C::BLOCK>(twl + M, tw2_g);
+  }
   run_fft<T, M, false, HIN, false>(v, lds, tw, p, jt, NPS,
                                    [&](int pp, int, int u, cpx<T> val) { lds[(jt + u) * NPS + pp] = val; });
   __syncthreads();
@@ -227,8 +230,9 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   constexpr int EH = E / 2;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = lds + (M + 1) * NPS;
-  cpx<T>* tw2 = tw + M;
+  cpx<T>* twl = lds + (M + 1) * NPS;
+  const cpx<T>* tw = C::TWG ? tw_g : twl;
+  const cpx<T>* tw2 = C::TWG ? tw2_g : twl + M;
   using V2 = typename io2<IO>::t;
   const int jt = threadIdx.x % TJ, p = threadIdx.x / TJ;
   const int grow = xrow<NP>(p, ncomp, rows_per_comp, nrows);
@@ -257,8 +261,10 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
       if (rsrow) sv[i] = *reinterpret_cast<const V2*>(rsrow + 2 * TJ * i);
     }
   }
-  load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
-  load_table<cpx<T>, M + 1, C::BLOCK>(tw2, tw2_g);
+  if constexpr (!C::TWG) {
+    load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
+    load_table<cpx<T>, M + 1, C::BLOCK>(twl + M, tw2_g);
+  }
   cpx<T>* xr = lds + p;
 #pragma unroll
   for (int i = 0; i < E; ++i) xr[(jt + TJ * i) * NPS] = x[i];

@@ -23,7 +23,8 @@ __global__ __launch_bounds__((YCfg<T, M, V>::BLOCK)) void k_y_pass(const cpx<T>*
   const int tile = L % ntx, plane = L / ntx;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw + C::BUF);
+  cpx<T>* twl = reinterpret_cast<cpx<T>*>(smem_raw + C::BUF);
+  const cpx<T>* tw = C::TWG ? tw_g : twl;
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
   const int kx = tile * NP + p;
   const bool ok = kx < kxn;
@@ -33,7 +34,7 @@ __global__ __launch_bounds__((YCfg<T, M, V>::BLOCK)) void k_y_pass(const cpx<T>*
   cpx<T> v[PlanInfo<M>::E];
   load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * kxs]; });
   // the twiddles are first read after the first exchange's barrier
-  load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
+  if constexpr (!C::TWG) load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
   run_fft<T, M, INV, HIN, HOUT, C::SPLIT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
     if (ok) dst[(size_t)u * kxs] = val;
   });
