@@ -246,9 +246,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f32_refined", choices=["f32_refined", "f64", "f32"])
     ap.add_argument("--matvec-reps", type=int, default=60, help="timed Z0 products per precision (median reported)")
-    ap.add_argument("--f64-steps", type=int, default=3,
-                    help="steps of the FP64 march timed after the main run (0 = skip); its currents also give "
-                         "the field error of the main run against FP64")
+    ap.add_argument("--f64-steps", type=int, default=8,
+                    help="steps of the FP64 march timed after the main run (0 = skip; 8 = one whole history "
+                         "block); its currents also give the field error of the main run against FP64")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")

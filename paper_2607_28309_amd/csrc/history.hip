@@ -7,7 +7,7 @@
 // in ky, xz odd in kz, yz odd in both).
 //
 // Temporal blocking: at the start of a block of B steps (after J^_{n0} is
-// pushed; B = 8 for an FP32 ring, 4 for FP64) one pass over the ring computes
+// pushed; B = 8, halved while B exceeds ell) one pass over the ring computes
 // the contributions of all slots t <= n0 to the next B right-hand sides,
 //   P_b = sum_{m>=0} Lambda_{m+b} J^_{n0-m},   b = 1..B,
 // reading every slot and every Lambda_j once (a sliding window of B Lambda
@@ -31,8 +31,8 @@ struct Geo {
 };
 
 // The mirror points of one octant frequency that a thread takes: NM = 4
-// (both kz sides) or NM = 2 (the kz side `side`, both ky sides); mirror i is
-// kz side a(i), ky side b(i).
+// (both kz sides), NM = 2 (the kz side `side`, both ky sides) or NM = 1 (kz
+// side side >> 1, ky side side & 1); mirror i is kz side a(i), ky side b(i).
 template <int NM>
 struct Point {
   size_t off[NM];
@@ -52,7 +52,7 @@ __device__ __forceinline__ bool octant_point(const Geo& g, long long id, int sid
   const bool dupy = (kyc == 0 || kyc == g.ny), dupz = (kzc == 0 || kzc == g.nz);
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
-    const int a = NM == 4 ? i >> 1 : side, b = i & 1;
+    const int a = NM == 4 ? i >> 1 : NM == 2 ? side : side >> 1, b = NM == 1 ? side & 1 : i & 1;
     const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
     pt.off[i] = (size_t)(kz % pz) * plane + (size_t)(ky % py) * g.kxs + kx;
     pt.keep[i] = !((a && dupz) || (b && dupy));
@@ -125,8 +125,8 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
 // all four mirror points of its octant frequency; NM = 2 (for long blocks,
 // whose B accumulators per point would not fit the registers): the two
 // threads of a frequency take one kz side each and read the same Lambda
-// words.  Two waves per SIMD at least
-// (a register budget of 256).
+// words; NM = 1 (long blocks in FP64): four threads per frequency, one
+// mirror point each.  Two waves per SIMD at least (a register budget of 256).
 template <typename T, int B, int NM>
 __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
                                                    cpx<T>* out0, cpx<T>* pblk, const cpx<T>* iblk, Geo g,
@@ -134,12 +134,12 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
   // octant frequencies per workgroup; with NM = 2 the two kz sides of a
   // frequency are neighbouring lanes of one wave, which read its Lambda words
   // with the same instruction
-  constexpr int PER = NM == 4 ? 256 : 128;
+  constexpr int PER = 256 / (4 / NM);
   size_t lo;
   Point<NM> pt;
   const int t = (int)threadIdx.x;
-  const long long id = (long long)blockIdx.x * PER + (NM == 4 ? t : t >> 1);
-  if (!octant_point<NM>(g, id, NM == 4 ? 0 : (t & 1), lo, pt)) return;
+  const long long id = (long long)blockIdx.x * PER + (NM == 4 ? t : NM == 2 ? t >> 1 : t >> 2);
+  if (!octant_point<NM>(g, id, NM == 4 ? 0 : NM == 2 ? (t & 1) : (t & 3), lo, pt)) return;
   const size_t comp = (size_t)(2 * g.nz) * (2 * g.ny) * g.kxs;
   const size_t slot = 3 * comp;
   const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;
@@ -156,11 +156,13 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
   T w[B][6];  // window: w[b] = Lambda_{m+1+b}
 #pragma unroll
   for (int b = 0; b < B; ++b) lam_at(b + 1, w[b]);
-  // With NM = 2 the kz sign sz is known only at run time: the z component of
-  // each loaded current is multiplied by sz and the z accumulators carry sz
-  // times their value (sz^2 = 1), so that the B multiply-adds per load see
-  // compile-time signs only.
-  const T sz2 = NM == 2 && pt.a[0] ? (T)-1 : (T)1;
+  // With NM = 2 the kz sign sz is known only at run time (with NM = 1 the ky
+  // sign sy too): the z (y) component of each loaded current is multiplied
+  // by sz (sy) and the z (y) accumulators carry sz (sy) times their value
+  // (sz^2 = sy^2 = 1), so that the B multiply-adds per load see compile-time
+  // signs only.
+  const T sz2 = NM <= 2 && pt.a[0] ? (T)-1 : (T)1;
+  const T sy2 = NM == 1 && pt.b[0] ? (T)-1 : (T)1;
   cpx<T> acc[B][NM][3];
 #pragma unroll
   for (int b = 0; b < B; ++b)
@@ -169,7 +171,8 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
       if (iblk) {
         const cpx<T>* I = iblk + (size_t)b * slot;
         acc[b][i][0] = I[pt.off[i]];
-        acc[b][i][1] = I[comp + pt.off[i]];
+        const cpx<T> y = I[comp + pt.off[i]];
+        acc[b][i][1] = cpx<T>{sy2 * y.x, sy2 * y.y};
         const cpx<T> z = I[2 * comp + pt.off[i]];
         acc[b][i][2] = cpx<T>{sz2 * z.x, sz2 * z.y};
       } else {
@@ -184,15 +187,16 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
     for (int i = 0; i < NM; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
-    if constexpr (NM == 2)
+    if constexpr (NM <= 2)
 #pragma unroll
       for (int i = 0; i < NM; ++i) jv[i][2] = cpx<T>{sz2 * jv[i][2].x, sz2 * jv[i][2].y};
+    if constexpr (NM == 1) jv[0][1] = cpx<T>{sy2 * jv[0][1].x, sy2 * jv[0][1].y};
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
       for (int i = 0; i < NM; ++i)
-        mac3<T>(acc[b][i], w[b], (i & 1) ? (T)-1 : (T)1, (NM == 4 && (i >> 1)) ? (T)-1 : (T)1, jv[i][0], jv[i][1],
-                jv[i][2]);
+        mac3<T>(acc[b][i], w[b], (NM != 1 && (i & 1)) ? (T)-1 : (T)1, (NM == 4 && (i >> 1)) ? (T)-1 : (T)1,
+                jv[i][0], jv[i][1], jv[i][2]);
 #pragma unroll
     for (int b = 0; b + 1 < B; ++b)
 #pragma unroll
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
     for (int i = 0; i < NM; ++i)
       if (pt.keep[i]) {
         dst[pt.off[i]] = acc[b][i][0];
-        dst[comp + pt.off[i]] = acc[b][i][1];
+        dst[comp + pt.off[i]] = cpx<T>{sy2 * acc[b][i][1].x, sy2 * acc[b][i][1].y};
         dst[2 * comp + pt.off[i]] = cpx<T>{sz2 * acc[b][i][2].x, sz2 * acc[b][i][2].y};
       }
   }
@@ -235,6 +239,7 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
   const dim3 gr = mac_grid(g);
   const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
   const dim3 gr2((unsigned)((cnt + 127) / 128));  // two threads per octant frequency
+  const dim3 gr4((unsigned)((cnt + 63) / 64));    // four
 #define LB(T, BB, NM, GR)                                                                                 \
   hipLaunchKernelGGL((k_mac_block<T, BB, NM>), GR, dim3(256), 0, s, (const cpx<T>*)ring, (const T*)lamh,   \
                      (cpx<T>*)out0, (cpx<T>*)pblk, (const cpx<T>*)iblk, g, n0, nold)
@@ -242,6 +247,7 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
     if (B == 1) LB(double, 1, 4, gr);
     else if (B == 2) LB(double, 2, 4, gr);
     else if (B == 4) LB(double, 4, 2, gr2);
+    else if (B == 8) LB(double, 8, 1, gr4);
     else return hipErrorInvalidValue;
   } else {
     if (B == 1) LB(float, 1, 4, gr);

@@ -1118,7 +1118,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   if ((rc = dmalloc(c, (void**)&c->lam0_32, sizeof(float) * 6 * c->lam_comp)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->lamh, rsz * 6 * c->lam_comp * c->nl)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->spec, rsz * 2 * c->slot_elems)) != MOT_OK) return fail(rc);
-  c->blk_B = c->ring_f64 ? 4 : 8;
+  c->blk_B = 8;
   while (c->blk_B > c->nl) c->blk_B /= 2;
   c->blk_n0 = -1;
   if (c->blk_B > 1 && (rc = dmalloc(c, &c->pblk, rsz * 2 * c->slot_elems * (c->blk_B - 1))) != MOT_OK)
