@@ -93,6 +93,17 @@ template <typename T, int M, int V = 0> struct ZFCfg {
   static constexpr size_t LDS = (size_t)(M * NPS + M) * SZ;
 };
 
+// The buffer between the y and z passes: element (plane pl, row r, column
+// kx) of P planes (component-major, pl = comp * rows + z) sits at
+//   ((r * NT + kx / 16) * P + pl) * 16 + kx % 16,   NT = kxs / 16,
+// so that a z pass reads and writes each (ky, 16-column block) as one
+// contiguous range of P * 16 values (a z pencil has stride 16); the y passes
+// step from row to row by NT * P * 16.  (kxs is a multiple of 16.)
+__host__ __device__ inline size_t yz_index(int pl, int r, int kx, int kxs, int P) {
+  return (((size_t)r * (kxs >> 4) + (kx >> 4)) * P + pl) * 16 + (kx & 15);
+}
+__host__ __device__ inline size_t yz_row_stride(int kxs, int P) { return (size_t)(kxs >> 4) * P * 16; }
+
 constexpr int NXCD = 8;
 // logical tile of workgroup id b; tiles >= nlog are idle
 __device__ __forceinline__ int xcd_tile(int b, int nlog) {

@@ -28,15 +28,21 @@ __global__ __launch_bounds__((YCfg<T, M, V>::BLOCK)) void k_y_pass(const cpx<T>*
   const int p = threadIdx.x % NP, jt = threadIdx.x / NP;
   const int kx = tile * NP + p;
   const bool ok = kx < kxn;
-  // columns past the last kx load a valid column and store nothing
-  const cpx<T>* src = in + ((size_t)plane * rows_in + jt) * kxs + (ok ? kx : kxn - 1);
-  cpx<T>* dst = out + ((size_t)plane * rows_out + jt) * kxs + kx;
+  // columns past the last kx load a valid column and store nothing; the
+  // complex side (output of the forward pass, input of the inverse) is the
+  // y-z buffer (yz_index) of nlog / ntx planes
+  const int kxc = ok ? kx : kxn - 1;
+  const int P = nlog / ntx;
+  const size_t RS = yz_row_stride(kxs, P);
+  const cpx<T>* src = INV ? in + yz_index(plane, jt, kxc, kxs, P) : in + ((size_t)plane * rows_in + jt) * kxs + kxc;
+  cpx<T>* dst = INV ? out + ((size_t)plane * rows_out + jt) * kxs + kx : out + yz_index(plane, jt, kx, kxs, P);
+  const size_t ss = INV ? RS : (size_t)kxs, ds = INV ? (size_t)kxs : RS;
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * kxs]; });
+  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * ss]; });
   // the twiddles are first read after the first exchange's barrier
   if constexpr (!C::TWG) load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
   run_fft<T, M, INV, HIN, HOUT, C::SPLIT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
-    if (ok) dst[(size_t)u * kxs] = val;
+    if (ok) dst[(size_t)u * ds] = val;
   });
 }
 

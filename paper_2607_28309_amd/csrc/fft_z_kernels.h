@@ -27,14 +27,20 @@ __global__ __launch_bounds__((ZCfg<T, M, NC, V>::BLOCK)) void k_z_pass(
   const int comp = p / W, c = p - comp * W;
   const int kx = tile * W + c;
   const bool ok = kx < kxn;
+  // the y-z buffer (yz_index) is the input of a forward pass and the output
+  // of an inverse one; the other side is the full spectrum [comp][kz][ky][kxs]
   const size_t plane = (size_t)ny * kxs;
-  const cpx<T>* src = in + ((size_t)comp * rows_in + jt) * plane + (size_t)ky * kxs + (ok ? kx : kxn - 1);
-  cpx<T>* dst = out + ((size_t)comp * rows_out + jt) * plane + (size_t)ky * kxs + kx;
+  const int kxc = ok ? kx : kxn - 1;
+  const cpx<T>* src = INV ? in + ((size_t)comp * rows_in + jt) * plane + (size_t)ky * kxs + kxc
+                          : in + yz_index(comp * rows_in + jt, ky, kxc, kxs, NC * rows_in);
+  cpx<T>* dst = INV ? out + yz_index(comp * rows_out + jt, ky, kx, kxs, NC * rows_out)
+                    : out + ((size_t)comp * rows_out + jt) * plane + (size_t)ky * kxs + kx;
+  const size_t ss = INV ? plane : 16, ds = INV ? 16 : plane;
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * plane]; });
+  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * ss]; });
   load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
   run_fft<T, M, INV, HIN, HOUT, C::SPLIT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
-    if (ok) dst[(size_t)u * plane] = val;
+    if (ok) dst[(size_t)u * ds] = val;
   });
 }
 
@@ -70,11 +76,11 @@ __global__ __launch_bounds__((ZFCfg<T, M, V>::BLOCK)) void k_z_fused(
   const bool okx = kx < kxn;
   const bool ok = okx && (h == 0 || two);
   const int ky = ok ? (h ? ny - kyc : kyc) : kyc;
-  const size_t plane = (size_t)ny * kxs;
-  const cpx<T>* src = in + ((size_t)q * rows_in + jt) * plane + (size_t)ky * kxs + (okx ? kx : kxn - 1);
-  cpx<T>* dst = out + ((size_t)q * rows_out + jt) * plane + (size_t)ky * kxs + kx;
+  // both sides are the y-z buffer (yz_index): a z pencil has stride 16
+  const cpx<T>* src = in + yz_index(q * rows_in + jt, ky, okx ? kx : kxn - 1, kxs, 3 * rows_in);
+  cpx<T>* dst = out + yz_index(q * rows_out + jt, ky, kx, kxs, 3 * rows_out);
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M, true>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * plane]; });
+  load_first<T, M, true>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * 16]; });
   // Lambda of this thread's items (component order xx, yy, zz, xy, xz, yz)
   const T* lt = lam + lam_tile_offset(tile * W, kyc, 0, 0, kxn, KZC, W);
   T lv[KI][6];
@@ -114,7 +120,7 @@ __global__ __launch_bounds__((ZFCfg<T, M, V>::BLOCK)) void k_z_fused(
   load_first<T, M, false>(v, p, jt, [&](int pp, int, int u) { return lds[(jt + u) * NPS + pp]; });
   __syncthreads();
   run_fft<T, M, true, false, true>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
-    if (ok) dst[(size_t)u * plane] = val;
+    if (ok) dst[(size_t)u * 16] = val;
   });
 }
 
