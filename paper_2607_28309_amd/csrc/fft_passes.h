@@ -47,11 +47,13 @@ __device__ __forceinline__ bool gate_closed(const Gate& g) {
 //       d = u2 + dcoef d; partials |w|^2 and w . rt.
 //   KRY_V (x inverse; y = au):  v = au + beta (au2 + beta v); partial v . rt.
 //   KRY_SCALE (either pass): no vector work, only the scale below.
+//   KRY_RESID (x inverse; y = b - Z0 J with b in `v`): the residual of the
+//       product's input, written in place of the product; partial |y|^2.
 // rs (optional with every mode but KRY_NONE; per voxel, indexed like the
 // epilogue's permittivity): right diagonal scaling of the solver's operator,
 // Z0 diag(rs): the product's input (forward pass) and the diagonal term's
 // current (inverse pass) are multiplied by rs.
-enum KryMode { KRY_NONE = 0, KRY_HALF0, KRY_U, KRY_XFIX, KRY_HALF1, KRY_V, KRY_SCALE };
+enum KryMode { KRY_NONE = 0, KRY_HALF0, KRY_U, KRY_XFIX, KRY_HALF1, KRY_V, KRY_SCALE, KRY_RESID };
 struct Krylov {
   int mode = KRY_NONE;
   const double* alpha = nullptr;  // solver scalars (device)

@@ -34,6 +34,8 @@ MOT_X_EXT_SOLVER(float, 0)
 MOT_X_EXT_SOLVER(double, 0)
 MOT_X_EXT_SOLVER(float, 1)
 MOT_X_EXT_SOLVER(double, 1)
+MOT_X_EXT_INV(double, double, 0, KRY_RESID)
+MOT_X_EXT_INV(double, double, 1, KRY_RESID)
 
 namespace {
 const Krylov kNoSolver{};
@@ -76,6 +78,7 @@ hipError_t x_inverse_k(const void* in, IO* y, const IO* J, const double* eps, Ep
     F(KRY_HALF1)
     F(KRY_V)
     F(KRY_SCALE)
+    if constexpr (sizeof(T) == 8) F(KRY_RESID)
 #undef F
   }
   return hipErrorInvalidValue;

@@ -250,9 +250,10 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   V2 jv[EH];
   double2 ev[EH];
   // right scaling of the solver's operator: the diagonal term's current is rs J
-  constexpr bool SCALED = KM != KRY_NONE;
+  constexpr bool SCALED = KM != KRY_NONE && KM != KRY_RESID;
   const IO* rsrow = SCALED && kry.rs ? (const IO*)kry.rs + eoff : nullptr;
   V2 sv[SCALED ? EH : 1];
+  V2 bv[KM == KRY_RESID ? EH : 1];  // right-hand side pairs (residual form)
 #pragma unroll
   for (int i = 0; i < EH; ++i) {
     jv[i] = *reinterpret_cast<const V2*>(J + roff + 2 * TJ * i);
@@ -260,6 +261,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     if constexpr (SCALED) {
       if (rsrow) sv[i] = *reinterpret_cast<const V2*>(rsrow + 2 * TJ * i);
     }
+    if constexpr (KM == KRY_RESID) bv[i] = *reinterpret_cast<const V2*>((const IO*)kry.v + roff + 2 * TJ * i);
   }
   if constexpr (!C::TWG) {
     load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
@@ -304,8 +306,13 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     V2 r;
     r.x = (IO)(((T)(ep.ca * e2.x + ep.c0)) * (T)j2.x + ((T)(ep.cb * e2.x + ep.cb0)) * z.x);
     r.y = (IO)(((T)(ep.ca * e2.y + ep.c0)) * (T)j2.y + ((T)(ep.cb * e2.y + ep.cb0)) * z.y);
+    if constexpr (KM == KRY_RESID) {
+      r.x = bv[i].x - r.x;
+      r.y = bv[i].y - r.y;
+      acc1 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+    }
     *reinterpret_cast<V2*>(yrow + 2 * u) = r;
-    if constexpr (KM != KRY_NONE && KM != KRY_SCALE) yo[i] = r;
+    if constexpr (KM == KRY_HALF1 || KM == KRY_V) yo[i] = r;
   });
   if constexpr (KM == KRY_HALF1 || KM == KRY_V) {
     // pairs n = jt + TJ i of the row, in chunks of CH: all operand loads of a
@@ -365,7 +372,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   if constexpr (KM == KRY_HALF1) {
     const double val[2] = {acc1, acc2};
     wg_sums<C::BLOCK, 2>(val, reinterpret_cast<double*>(smem_raw), kry.partials, kry.stride);
-  } else if constexpr (KM == KRY_V) {
+  } else if constexpr (KM == KRY_V || KM == KRY_RESID) {
     const double val[1] = {acc1};
     wg_sums<C::BLOCK, 1>(val, reinterpret_cast<double*>(smem_raw), kry.partials, kry.stride);
   }
@@ -463,6 +470,7 @@ int x_pass_blocks_v(int M, bool f64, int nrows, int rows_per_comp, int ncomp) {
   MOT_X_INV(float, float, V, KRY_NONE)                                                                         \
   MOT_X_INV(float, double, V, KRY_NONE)                                                                        \
   MOT_X_INV(double, double, V, KRY_NONE)
+#define MOT_X_RESID(V) MOT_X_INV(double, double, V, KRY_RESID)
 #define MOT_X_SOLVER_T(T, V)                                                                                   \
   MOT_X_FWD(T, T, V, KRY_HALF0)                                                                                \
   MOT_X_FWD(T, T, V, KRY_U)                                                                                    \

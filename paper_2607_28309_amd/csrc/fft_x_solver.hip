@@ -4,4 +4,5 @@
 namespace motfft {
 MOT_X_SOLVER_T(float, 0)
 MOT_X_SOLVER_T(double, 0)
+MOT_X_RESID(0)
 }  // namespace motfft

@@ -4,4 +4,5 @@
 namespace motfft {
 MOT_X_SOLVER_T(float, 1)
 MOT_X_SOLVER_T(double, 1)
+MOT_X_RESID(1)
 }  // namespace motfft

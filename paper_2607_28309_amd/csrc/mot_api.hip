@@ -779,11 +779,25 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
         so.iters += inner.iters;
         so.matvecs += inner.matvecs;
         if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
-        TRY(apply_z0(c, x, v[V_TMP]));
+        // r = b - Z0 x: the product's inverse x pass writes the residual and
+        // its partials (the predictor keeps Z0 x itself)
+        if (c->pred_k > 0) {
+          TRY(apply_z0(c, x, v[V_TMP]));
+          HTP(K_KRY, true, vec_sub<double>(b, v[V_TMP], v[V_RO], n, P, s));
+          HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s));
+        } else {
+          const int xb = motfft::x_pass_blocks(c->nx, true, c->tune[1][TUNE_X], 3 * c->nz * c->ny, c->nz * c->ny, 3);
+          if (xb < 1 || (size_t)xb > c->partials_n) return set_err(c, MOT_EINVAL, "x pass grid outside the partials%s%d");
+          motfft::Krylov kr;
+          kr.mode = motfft::KRY_RESID;
+          kr.v = (void*)b;
+          kr.partials = P;
+          kr.stride = xb;
+          TRY(apply_z0(c, x, v[V_RO], motfft::Gate{}, nullptr, &kr));
+          HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s, motfft::Gate{}, xb));
+        }
         so.matvecs++;
         so.matvecs64++;
-        HTP(K_KRY, true, vec_sub<double>(b, v[V_TMP], v[V_RO], n, P, s));
-        HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s));
         TRY(reduce_sync(c));
         if (bnorm < 0.0) {
           bnorm = sqrt(c->hscal[S_OB2]);
