@@ -214,13 +214,13 @@ def sources_sha256(paths):
 
 
 def measured_traffic(kernel, variant=0):
-    """HBM bytes per launch from the committed counter runs, or None when the
-    kernel's sources changed since they were taken, the counters were taken
-    for another tile variant, or none were taken."""
+    """HBM bytes per launch from the committed counter runs (entry
+    "<kernel>/v<variant>"), or None when the kernel's sources changed since
+    they were taken or none were taken for that tile variant."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(kernel)
+    rec = json.load(open(path)).get(f"{kernel}/v{variant}")
     if not rec or rec.get("tile_variant", 0) != variant:
         return None
     if sources_sha256(rec["sources"]) != rec["sources_sha256"]:
