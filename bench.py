@@ -265,7 +265,7 @@ def main():
                          "(reference for the HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build", file=sys.stderr)
+        print(f"bench.py runs the single-GPU path only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
