@@ -171,14 +171,16 @@ __device__ void post_op(double* scal, int post) {
   }
 }
 
-// Sum of nparts partials in a fixed order (every thread returns it).
+// Sum of nparts partials in a fixed order by a block of NT threads (every
+// thread returns it).
+template <int NT = RED_THREADS>
 __device__ __forceinline__ double sum_partials(const double* __restrict__ partials, int nparts) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += RED_THREADS) acc += partials[i];
-  __shared__ double red[RED_THREADS];
+  for (int i = threadIdx.x; i < nparts; i += NT) acc += partials[i];
+  __shared__ double red[NT];
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
@@ -187,10 +189,14 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
   return r;
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
+// The final sums of the solver's reductions run in one workgroup of
+// FIN_THREADS threads: a wide block, so that each thread adds few partials.
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
                                                         int slot, int post, Gate g, int nparts) {
   if (motfft::gate_closed(g)) return;
-  const double sum = sum_partials(partials, nparts);
+  const double sum = sum_partials<FIN_THREADS>(partials, nparts);
   if (threadIdx.x == 0) {
     scal[slot] = sum;
     post_op(scal, post);
@@ -199,12 +205,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const double* __restrict
 
 // Two sums (partials[0, nparts) and [stride, stride + nparts)), then their
 // scalar recurrences in order.
-__global__ __launch_bounds__(RED_THREADS) void k_reduce2(const double* __restrict__ partials, double* scal,
+__global__ __launch_bounds__(FIN_THREADS) void k_reduce2(const double* __restrict__ partials, double* scal,
                                                          int slot1, int post1, int slot2, int post2, Gate g,
                                                          int nparts, int stride) {
   if (motfft::gate_closed(g)) return;
-  const double s1 = sum_partials(partials, nparts);
-  const double s2 = sum_partials(partials + stride, nparts);
+  const double s1 = sum_partials<FIN_THREADS>(partials, nparts);
+  const double s2 = sum_partials<FIN_THREADS>(partials + stride, nparts);
   if (threadIdx.x == 0) {
     scal[slot1] = s1;
     scal[slot2] = s2;
@@ -405,14 +411,14 @@ hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hi
 hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g,
                        int nparts) {
   if (nparts < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, dim3(1), RB(), 0, s, partials, scal, slot, post, g, nparts);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(FIN_THREADS), 0, s, partials, scal, slot, post, g, nparts);
   return hipGetLastError();
 }
 hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,
                         hipStream_t s, Gate g, int nparts, int stride) {
   if (nparts < 1 || stride < nparts) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce2, dim3(1), RB(), 0, s, partials, scal, slot1, post1, slot2, post2, g, nparts,
-                     stride);
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(FIN_THREADS), 0, s, partials, scal, slot1, post1, slot2, post2, g,
+                     nparts, stride);
   return hipGetLastError();
 }
 hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only) {
