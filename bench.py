@@ -38,7 +38,8 @@ def log(msg):
 
 
 def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid, blk=1):
-    """Minimal HBM bytes of one launch of a pass (roofline)."""
+    """Minimal HBM bytes of one launch of a pass: each input and output
+    array touched once (FP32 complex = 2 t_bytes, voxel vectors io_bytes)."""
     nx, ny, nz = n
     kx, py, pz = nx + 1, 2 * ny, 2 * nz
     N = nx * ny * nz

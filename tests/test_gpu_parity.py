@@ -1,12 +1,12 @@
 """Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
 
-Tolerances (derived in the design doc):
+Tolerances (from the arithmetic of each comparison):
   * integer work (masks, lag counts, support of G_k): bit-exact;
   * G_k tables: |lib - oracle| <= 1e-11 max|G_k| (two independent FP64
     quadratures of the same integrals, each accurate to ~1e-13), widened by
     (|extent|/20)^2 on grids wider than 20 voxels (cancellation at far offsets);
   * FP64 products: relative L2 <= 1e-10;
-  * FP32 products: relative L2 <= 1e-5 (the FP32 bar of the build);
+  * FP32 products: relative L2 <= 1e-5 (FP32 FFT rounding over ~25 stages, with margin);
   * marched fields: max_n ||J_n - J_n^ref|| / max_n ||J_n^ref|| <= 1e-4.
 """
 
