@@ -18,10 +18,21 @@
 
 namespace motfft {
 
-// Streaming (nontemporal) store of an element pair.  The solver's vectors are
-// next read a whole product later; streaming stores keep them from pushing
-// the pass's own output (read by the next pass) out of the caches
-// (measured: y forward pass after a solver x pass 2-3 us faster).
+// Streaming (nontemporal) loads and stores of an element pair.  The solver's
+// vectors are read and written once per pass and next touched a whole
+// product later; streaming accesses keep them from pushing the data that
+// the next pass reads (this pass's output) out of the caches (measured:
+// 79.45 -> 82 steps/s on the 320x320x48 pillars).
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v t = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return float2{t.x, t.y};
+}
+__device__ __forceinline__ double2 load_stream(const double2* p) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v t = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return double2{t.x, t.y};
+}
 __device__ __forceinline__ void store_stream(float2* p, float2 v) {
   typedef float f2v __attribute__((ext_vector_type(2)));
   const f2v t = {v.x, v.y};
@@ -141,18 +152,18 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
         if (l >= NL) break;
         const int u = (l / HR) * TJ + (l % HR) * MR;
         const size_t o = ro + 2 * u;
-        a0[cc] = *reinterpret_cast<const V2*>(kin + o);
+        a0[cc] = load_stream(reinterpret_cast<const V2*>(kin + o));
         if (srow) sc[cc] = *reinterpret_cast<const V2*>(srow + 2 * u);
         if constexpr (KM == KRY_HALF0) {
-          a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.v + o);
-          a2[cc] = *reinterpret_cast<const V2*>((const IO*)kry.w + o);
-          a3[cc] = *reinterpret_cast<const V2*>((const IO*)kry.au + o);
-          a4[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
-          a5[cc] = *reinterpret_cast<const V2*>((const IO*)kry.x + o);
+          a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.v + o));
+          a2[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.w + o));
+          a3[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.au + o));
+          a4[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.d + o));
+          a5[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.x + o));
         } else if constexpr (KM == KRY_U) {
-          a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.u2 + o);
+          a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.u2 + o));
         } else if constexpr (KM == KRY_XFIX) {
-          a4[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
+          a4[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.d + o));
         }
       }
 #pragma unroll
@@ -276,7 +287,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     if constexpr (SCALED) {
       if (rsrow) sv[i] = *reinterpret_cast<const V2*>(rsrow + 2 * TJ * i);
     }
-    if constexpr (KM == KRY_RESID) bv[i] = *reinterpret_cast<const V2*>((const IO*)kry.v + roff + 2 * TJ * i);
+    if constexpr (KM == KRY_RESID) bv[i] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.v + roff + 2 * TJ * i));
   }
   if constexpr (!C::TWG) {
     load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
@@ -343,14 +354,14 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
           if (i >= EH) break;
           const size_t o = roff + 2 * TJ * i;
           if constexpr (KM == KRY_HALF1) {
-            a0[cc] = *reinterpret_cast<const V2*>((const IO*)kry.x + o);
-            a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.w + o);
-            a2[cc] = *reinterpret_cast<const V2*>((const IO*)kry.d + o);
-            a3[cc] = *reinterpret_cast<const V2*>((const IO*)kry.rt + o);
+            a0[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.x + o));
+            a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.w + o));
+            a2[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.d + o));
+            a3[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.rt + o));
           } else {
-            a0[cc] = *reinterpret_cast<const V2*>((const IO*)kry.au + o);
-            a1[cc] = *reinterpret_cast<const V2*>((const IO*)kry.v + o);
-            a3[cc] = *reinterpret_cast<const V2*>((const IO*)kry.rt + o);
+            a0[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.au + o));
+            a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.v + o));
+            a3[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.rt + o));
           }
         }
 #pragma unroll
