@@ -72,6 +72,7 @@ struct Krylov {
   double* partials = nullptr;  // partials[b] (and partials[stride + b] for a second sum)
   int stride = 0;
   const void* rs = nullptr;    // right scaling (see above), IO values
+  int stream = 0;              // 1: the vectors are read and written with streaming accesses
 };
 
 // Precision tags: T = compute type; IO = element type of real vectors.

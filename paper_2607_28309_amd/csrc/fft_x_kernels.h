@@ -20,9 +20,11 @@ namespace motfft {
 
 // Streaming (nontemporal) loads and stores of an element pair.  The solver's
 // vectors are read and written once per pass and next touched a whole
-// product later; streaming accesses keep them from pushing the data that
-// the next pass reads (this pass's output) out of the caches (measured:
-// 79.45 -> 82 steps/s on the 320x320x48 pillars).
+// product later; on grids whose vectors far exceed the caches, streaming
+// accesses keep them from pushing the data that the next pass reads (this
+// pass's output) out of the caches (measured: 79.45 -> 82 steps/s on the
+// 320x320x48 pillars).  On small grids everything stays cached and plain
+// accesses are faster, so Krylov::stream selects them per launch.
 __device__ __forceinline__ float2 load_stream(const float2* p) {
   typedef float f2v __attribute__((ext_vector_type(2)));
   const f2v t = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
@@ -42,6 +44,17 @@ __device__ __forceinline__ void store_stream(double2* p, double2 v) {
   typedef double d2v __attribute__((ext_vector_type(2)));
   const d2v t = {v.x, v.y};
   __builtin_nontemporal_store(t, reinterpret_cast<d2v*>(p));
+}
+template <typename V2>
+__device__ __forceinline__ V2 load_kv(const V2* p, int stream) {
+  return stream ? load_stream(p) : *p;
+}
+template <typename V2>
+__device__ __forceinline__ void store_kv(V2* p, V2 v, int stream) {
+  if (stream)
+    store_stream(p, v);
+  else
+    *p = v;
 }
 
 // Row of local slot p in this workgroup.  With 3 components a workgroup
@@ -152,18 +165,18 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
         if (l >= NL) break;
         const int u = (l / HR) * TJ + (l % HR) * MR;
         const size_t o = ro + 2 * u;
-        a0[cc] = load_stream(reinterpret_cast<const V2*>(kin + o));
+        a0[cc] = load_kv(reinterpret_cast<const V2*>(kin + o), kry.stream);
         if (srow) sc[cc] = *reinterpret_cast<const V2*>(srow + 2 * u);
         if constexpr (KM == KRY_HALF0) {
-          a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.v + o));
-          a2[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.w + o));
-          a3[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.au + o));
-          a4[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.d + o));
-          a5[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.x + o));
+          a1[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.v + o), kry.stream);
+          a2[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.w + o), kry.stream);
+          a3[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.au + o), kry.stream);
+          a4[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.d + o), kry.stream);
+          a5[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.x + o), kry.stream);
         } else if constexpr (KM == KRY_U) {
-          a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.u2 + o));
+          a1[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.u2 + o), kry.stream);
         } else if constexpr (KM == KRY_XFIX) {
-          a4[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.d + o));
+          a4[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.d + o), kry.stream);
         }
       }
 #pragma unroll
@@ -185,20 +198,20 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
           dd.x = a0[cc].x + kdc * a4[cc].x;
           dd.y = a0[cc].y + kdc * a4[cc].y;
           if (valid) {
-            store_stream(reinterpret_cast<V2*>((IO*)kry.x + o), xx);
-            store_stream(reinterpret_cast<V2*>((IO*)kry.out + o), pr);
-            store_stream(reinterpret_cast<V2*>((IO*)kry.w + o), ww);
-            store_stream(reinterpret_cast<V2*>((IO*)kry.d + o), dd);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.x + o), xx, kry.stream);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.out + o), pr, kry.stream);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.w + o), ww, kry.stream);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.d + o), dd, kry.stream);
             acc += (double)ww.x * (double)ww.x + (double)ww.y * (double)ww.y;
           }
         } else if constexpr (KM == KRY_U) {  // a0 = w, a1 = u2
           pr.x = a0[cc].x + kb * a1[cc].x;
           pr.y = a0[cc].y + kb * a1[cc].y;
-          if (valid) store_stream(reinterpret_cast<V2*>((IO*)kry.out + o), pr);
+          if (valid) store_kv(reinterpret_cast<V2*>((IO*)kry.out + o), pr, kry.stream);
         } else if constexpr (KM == KRY_XFIX) {  // a0 = x, a4 = d
           pr.x = a0[cc].x + kep * a4[cc].x;
           pr.y = a0[cc].y + kep * a4[cc].y;
-          if (valid) store_stream(reinterpret_cast<V2*>((IO*)kry.x + o), pr);
+          if (valid) store_kv(reinterpret_cast<V2*>((IO*)kry.x + o), pr, kry.stream);
         } else {  // KRY_SCALE
           pr = a0[cc];
         }
@@ -287,7 +300,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     if constexpr (SCALED) {
       if (rsrow) sv[i] = *reinterpret_cast<const V2*>(rsrow + 2 * TJ * i);
     }
-    if constexpr (KM == KRY_RESID) bv[i] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.v + roff + 2 * TJ * i));
+    if constexpr (KM == KRY_RESID) bv[i] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.v + roff + 2 * TJ * i), kry.stream);
   }
   if constexpr (!C::TWG) {
     load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
@@ -354,14 +367,14 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
           if (i >= EH) break;
           const size_t o = roff + 2 * TJ * i;
           if constexpr (KM == KRY_HALF1) {
-            a0[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.x + o));
-            a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.w + o));
-            a2[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.d + o));
-            a3[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.rt + o));
+            a0[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.x + o), kry.stream);
+            a1[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.w + o), kry.stream);
+            a2[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.d + o), kry.stream);
+            a3[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.rt + o), kry.stream);
           } else {
-            a0[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.au + o));
-            a1[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.v + o));
-            a3[cc] = load_stream(reinterpret_cast<const V2*>((const IO*)kry.rt + o));
+            a0[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.au + o), kry.stream);
+            a1[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.v + o), kry.stream);
+            a3[cc] = load_kv(reinterpret_cast<const V2*>((const IO*)kry.rt + o), kry.stream);
           }
         }
 #pragma unroll
@@ -378,16 +391,16 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
             ww.y = a1[cc].y - ka * r.y;
             dd.x = jv[i].x + kdc * a2[cc].x;
             dd.y = jv[i].y + kdc * a2[cc].y;
-            store_stream(reinterpret_cast<V2*>((IO*)kry.x + o), xx);
-            store_stream(reinterpret_cast<V2*>((IO*)kry.w + o), ww);
-            store_stream(reinterpret_cast<V2*>((IO*)kry.d + o), dd);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.x + o), xx, kry.stream);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.w + o), ww, kry.stream);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.d + o), dd, kry.stream);
             acc1 += (double)ww.x * (double)ww.x + (double)ww.y * (double)ww.y;
             acc2 += (double)ww.x * (double)a3[cc].x + (double)ww.y * (double)a3[cc].y;
           } else {  // KRY_V: r = au; a0 = au2, a1 = v, a3 = rt
             V2 vv;
             vv.x = r.x + kb * (a0[cc].x + kb * a1[cc].x);
             vv.y = r.y + kb * (a0[cc].y + kb * a1[cc].y);
-            store_stream(reinterpret_cast<V2*>((IO*)kry.v + o), vv);
+            store_kv(reinterpret_cast<V2*>((IO*)kry.v + o), vv, kry.stream);
             acc1 += (double)vv.x * (double)a3[cc].x + (double)vv.y * (double)a3[cc].y;
           }
         }

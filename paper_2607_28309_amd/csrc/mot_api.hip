@@ -441,6 +441,8 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   kb.partials = P;
   kb.stride = xb;
   kb.rs = rs;
+  // streaming vector accesses once a vector outgrows the caches' share
+  kb.stream = (size_t)n * sizeof(V) >= ((size_t)32 << 20) ? 1 : 0;
   motfft::Krylov kh0 = kb, kh1 = kb, ku = kb, kvv = kb, kfix = kb;
   kh0.mode = motfft::KRY_HALF0;  // in = u
   kh0.v = v[V_V];
@@ -793,6 +795,7 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
           kr.v = (void*)b;
           kr.partials = P;
           kr.stride = xb;
+          kr.stream = (size_t)n * sizeof(double) >= ((size_t)32 << 20) ? 1 : 0;
           TRY(apply_z0(c, x, v[V_RO], motfft::Gate{}, nullptr, &kr));
           HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s, motfft::Gate{}, xb));
         }
