@@ -41,8 +41,22 @@ __global__ __launch_bounds__((YCfg<T, M, V>::BLOCK)) void k_y_pass(const cpx<T>*
   load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * ss]; });
   // the twiddles are first read after the first exchange's barrier
   if constexpr (!C::TWG) load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
+  // the forward pass's output is read once, by the z pass, after the whole
+  // pass has ended: past 32 MB it is written with streaming (nontemporal)
+  // stores so that it does not evict the lines the pass still reads
+  const bool nts = !INV && (size_t)M * RS * sizeof(cpx<T>) >= ((size_t)32 << 20);
   run_fft<T, M, INV, HIN, HOUT, C::SPLIT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
-    if (ok) dst[(size_t)u * ds] = val;
+    if (!ok) return;
+    cpx<T>* q = dst + (size_t)u * ds;
+    if constexpr (!INV) {
+      if (nts) {
+        typedef T tv2 __attribute__((ext_vector_type(2)));
+        const tv2 t = {val.x, val.y};
+        __builtin_nontemporal_store(t, reinterpret_cast<tv2*>(q));
+        return;
+      }
+    }
+    *q = val;
   });
 }
 
