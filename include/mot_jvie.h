@@ -145,10 +145,10 @@ int gk_matvec(mot_ctx* ctx, int32_t k, const void* J, void* y, mot_precision dty
  *   h_{n+1} = -sum_{k=1..ell} Z_k J_{n+1-k}
  *           = -(eps_r/2) J_n + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
  * using the spectra of past currents (each current is transformed once).
- * The spectral sums are blocked in time: every B steps (B = 4 for an FP32
- * ring, 2 for FP64) one pass over the ring accumulates the contributions of
- * all stored currents to the next B right-hand sides; the steps in between
- * add only their newest lags.  Errors: MOT_ESTATE, MOT_EHIP. */
+ * The spectral sums are blocked in time: every B steps (B = 8, halved while
+ * B > ell) one pass over the ring accumulates the contributions of all
+ * stored currents to the next B right-hand sides; the steps in between add
+ * only their newest lags.  Errors: MOT_ESTATE, MOT_EHIP. */
 int history_update(mot_ctx* ctx, const double* J_n);
 
 /* Copy the prepared history right-hand side (FP64, 3N) to `out` (device). */

@@ -336,6 +336,65 @@ def test_z0_matvec_pillars_full_size(gpu_lib, dtype):
     assert err <= (1e-10 if dtype == "f64" else 1e-5) * scale
 
 
+def test_march_pillars_full_size(gpu_lib):
+    # The benchmarked march: 8x8 pillars, 320x320x48 voxels, dt = 16 dt_CFL,
+    # autotuned tile shapes, started at step ell with zero past currents,
+    # tol 1e-6, over 10 steps (one history block of 8 with its second-level
+    # block, and the next block start); its vectors are large enough for the
+    # streaming accesses.  At this size it is held to properties: every
+    # current meets the residual bound under a separate FP64 product; the
+    # history right-hand side from the blocked multiply-accumulate equals the
+    # sum of the lag products (one FFT product per lag); the FP32-refined and
+    # FP64 marches agree.
+    import torch
+    w = W.PILLARS
+    n, alpha = w.n, w.alpha
+    eps = w.eps()
+    N3 = 3 * math.prod(n)
+    p = W.pulse(w.ppw)
+    L = basis.cdt_from_alpha(alpha)
+    eps3 = _t(np.tile(eps.ravel(), 3))
+    steps, tol = 10, 1e-6
+    marches = {}
+    for prec in ("f64", "f32_refined"):
+        c = _ctx(gpu_lib, n, alpha, prec, eps)
+        c.autotune()
+        nl = c.info()["nlags"]
+        c.reset()
+        c.set_step(nl)
+        einc, h, y, g = (torch.empty(N3, dtype=torch.float64, device="cuda") for _ in range(4))
+        htol = 1e-10 if prec == "f64" else 1e-5
+        gdt = "f64" if prec == "f64" else "f32_refined"
+        Js = []                          # newest first
+        for s in range(steps):
+            c.history_rhs(h)
+            if not Js:
+                assert float(torch.abs(h).max()) == 0.0
+            else:
+                acc = torch.zeros_like(h)
+                for k in range(1, min(len(Js), nl) + 1):
+                    c.gk_matvec(k, Js[k - 1], g, gdt)
+                    acc += g
+                ref = -0.5 * eps3 * Js[0] + (eps3 - 1.0) * acc
+                rel = float(torch.linalg.vector_norm(h - ref) / torch.linalg.vector_norm(ref))
+                assert rel <= htol, (prec, s, rel)
+            c.excitation(p, (22 + s) * L, einc)
+            J = torch.empty_like(einc)
+            status, st = c.step(einc, J, tol=tol)
+            assert status == 0 and st["iters"] > 0, (prec, s, st)
+            b = einc + h
+            c.z0_matvec(J, y, "f64")
+            rr = float(torch.linalg.vector_norm(y - b) / torch.linalg.vector_norm(b))
+            assert rr <= 1.01 * tol, (prec, s, rr)
+            Js.insert(0, J)
+        marches[prec] = Js
+        c.close()
+    a, b = marches["f32_refined"], marches["f64"]
+    num = max(float(torch.linalg.vector_norm(x - z)) for x, z in zip(a, b))
+    den = max(float(torch.linalg.vector_norm(z)) for z in b)
+    assert num <= 2e-5 * den, num / den
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32_refined"])
 def test_graph_replay_matches_stream_launches(gpu_lib, prec):
     # TFQMR iterations replayed from HIP graphs give the same currents, bit for bit
