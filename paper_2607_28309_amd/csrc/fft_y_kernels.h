@@ -37,20 +37,33 @@ __global__ __launch_bounds__((YCfg<T, M, V>::BLOCK)) void k_y_pass(const cpx<T>*
   const cpx<T>* src = INV ? in + yz_index(plane, jt, kxc, kxs, P) : in + ((size_t)plane * rows_in + jt) * kxs + kxc;
   cpx<T>* dst = INV ? out + ((size_t)plane * rows_out + jt) * kxs + kx : out + yz_index(plane, jt, kx, kxs, P);
   const size_t ss = INV ? RS : (size_t)kxs, ds = INV ? (size_t)kxs : RS;
+  // the y-z buffer is produced once and read once per product: past 32 MB
+  // the forward pass writes it and the inverse pass reads it with streaming
+  // (nontemporal) accesses, so that it does not evict the lines the next
+  // pass reads (the x inverse pass's input, which the inverse pass writes);
+  // only by tiles whose columns fill whole 128-byte lines (narrower streaming
+  // accesses reach HBM as partial lines)
+  constexpr bool NT_TILE = C::NP * sizeof(cpx<T>) >= 128;
+  const bool big = NT_TILE && (size_t)M * RS * sizeof(cpx<T>) >= ((size_t)32 << 20);
+  typedef T tv2 __attribute__((ext_vector_type(2)));
   cpx<T> v[PlanInfo<M>::E];
-  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) { return src[(size_t)u * ss]; });
+  load_first<T, M, HIN>(v, p, jt, [&](int, int, int u) {
+    const cpx<T>* q = src + (size_t)u * ss;
+    if constexpr (INV) {
+      if (big) {
+        const tv2 t = __builtin_nontemporal_load(reinterpret_cast<const tv2*>(q));
+        return cpx<T>{t.x, t.y};
+      }
+    }
+    return *q;
+  });
   // the twiddles are first read after the first exchange's barrier
   if constexpr (!C::TWG) load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
-  // the forward pass's output is read once, by the z pass, after the whole
-  // pass has ended: past 32 MB it is written with streaming (nontemporal)
-  // stores so that it does not evict the lines the pass still reads
-  const bool nts = !INV && (size_t)M * RS * sizeof(cpx<T>) >= ((size_t)32 << 20);
   run_fft<T, M, INV, HIN, HOUT, C::SPLIT>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> val) {
     if (!ok) return;
     cpx<T>* q = dst + (size_t)u * ds;
     if constexpr (!INV) {
-      if (nts) {
-        typedef T tv2 __attribute__((ext_vector_type(2)));
+      if (big) {
         const tv2 t = {val.x, val.y};
         __builtin_nontemporal_store(t, reinterpret_cast<tv2*>(q));
         return;
