@@ -280,8 +280,18 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   // bins k = jt + TJ i and k = M of row p, all loads issued before any wait
   const cpx<T>* srow = in + (size_t)growc * kxs;
   cpx<T> x[E];
+  // the spectrum is read once: past 32 MB with streaming (nontemporal) loads
+  const bool big = (size_t)nrows * kxs * sizeof(cpx<T>) >= ((size_t)32 << 20);
+  typedef T tv2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int i = 0; i < E; ++i) x[i] = srow[jt + TJ * i];
+  for (int i = 0; i < E; ++i) {
+    if (big) {
+      const tv2 t = __builtin_nontemporal_load(reinterpret_cast<const tv2*>(srow + jt + TJ * i));
+      x[i] = cpx<T>{t.x, t.y};
+    } else {
+      x[i] = srow[jt + TJ * i];
+    }
+  }
   const cpx<T> xM = srow[M];
   // epilogue operands of the pairs n = jt + TJ i (i < E/2) this lane writes
   const size_t roff = (size_t)growc * row_len + 2 * jt;
