@@ -180,13 +180,31 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
         for (int q = 0; q < 3; ++q) acc[b][i][q] = cpx<T>{(T)0, (T)0};
       }
     }
-  for (int m = 0; m < nold; ++m) {
+  auto load_slot = [&](int m, cpx<T> (&jv)[NM][3]) {
     const cpx<T>* R = ring + (size_t)((n0 - m) % g.nl) * slot;
-    cpx<T> jv[NM][3];
 #pragma unroll
     for (int i = 0; i < NM; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
+  };
+  // FP32: the next slot's currents and the next window value are loaded
+  // before this slot's multiply-adds, so that their latency overlaps them
+  // (FP64 has no registers to spare for it)
+  constexpr bool PREFETCH = sizeof(T) == 4;
+  cpx<T> jv[NM][3];
+  if (PREFETCH && nold > 0) load_slot(0, jv);
+  // the loop starts with no load in flight (vmcnt 0): the wait counts inside
+  // the loop then follow its own loads only
+  if constexpr (PREFETCH) __builtin_amdgcn_s_waitcnt(0x0F70);
+  for (int m = 0; m < nold; ++m) {
+    cpx<T> jn[NM][3];
+    T ln[6];
+    if constexpr (PREFETCH) {
+      load_slot(m + 1 < nold ? m + 1 : m, jn);
+      lam_at(m + 1 + B, ln);
+    } else {
+      load_slot(m, jv);
+    }
     if constexpr (NM <= 2)
 #pragma unroll
       for (int i = 0; i < NM; ++i) jv[i][2] = cpx<T>{sz2 * jv[i][2].x, sz2 * jv[i][2].y};
@@ -201,7 +219,16 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
     for (int b = 0; b + 1 < B; ++b)
 #pragma unroll
       for (int c = 0; c < 6; ++c) w[b][c] = w[b + 1][c];
-    lam_at(m + 1 + B, w[B - 1]);
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) w[B - 1][c] = ln[c];
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) jv[i][q] = jn[i][q];
+    } else {
+      lam_at(m + 1 + B, w[B - 1]);
+    }
   }
 #pragma unroll
   for (int b = 0; b < B; ++b) {
