@@ -205,6 +205,112 @@ def batch_leg(args, log_fn):
     return res
 
 
+# a march whose current passes this magnitude has left the physical range (the
+# incident field and the currents it drives are of order one) and is stopped
+GROWTH_LIMIT = 1e6
+
+
+def sweep_leg(args, log_fn):
+    """Large-time-step sweep on the 96^3 nested cube (layers 6 / 4 / 2.5 by
+    Chebyshev distance, +-5 % seeded noise, seed 3): dt = alpha * dt_CFL over
+    one physical window of `--sweep-window` dt_CFL (window / alpha steps from
+    t = 0), every step with its statistics.  Per alpha: lags (Eq. 4), Z0
+    nonzeros from the mask, TFQMR iterations and products per step, solve
+    (LHS) against right-hand-side (history) time per step, wall time of the
+    window, the largest |J| per quarter of the window, the step at which the
+    march left the physical range (|J| > GROWTH_LIMIT or a non-finite
+    residual; the run of that alpha stops there), and the x current at the
+    central voxel at the times all runs share, compared with that of the
+    smallest alpha whose march stayed bounded."""
+    import torch
+    import workloads as W
+    from paper_2607_28309_amd import native
+    w = W.CUBE96
+    n = w.n
+    N = n[0] * n[1] * n[2]
+    eps = torch.from_numpy(w.eps().ravel()).cuda()
+    p = W.pulse(w.ppw)
+    probe = n[0] // 2 + n[0] * (n[1] // 2 + n[1] * (n[2] // 2))   # x component, central voxel
+    common = math.lcm(*args.sweep_alphas)
+    rows, probes = [], {}
+    for alpha in args.sweep_alphas:
+        steps = args.sweep_window // alpha
+        L = alpha / math.sqrt(3.0)
+        t0 = time.perf_counter()
+        c = native.Context(*n, alpha=alpha, precision=args.precision)
+        c.set_material(eps)
+        c.build_green_spectra()
+        if not args.no_autotune:
+            c.autotune(reps=5)
+        c.reset()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        info = c.info()
+        E = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        J = torch.empty_like(E)
+        st, pr, amax = [], [], []
+        diverged = None
+        t = time.perf_counter()
+        for k in range(steps):
+            c.excitation(p, k * L, E)
+            rc, s_ = c.step(E, J, tol=args.tol, allow=(native.MOT_ENONFINITE, native.MOT_ENOCONV))
+            if rc != 0:
+                diverged = k
+                break
+            st.append(s_)
+            amax.append(float(J.abs().max()))
+            if amax[-1] > GROWTH_LIMIT:
+                diverged = k
+                break
+            if (k * alpha) % common == 0:
+                pr.append(float(J[probe]))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        probes[alpha] = pr
+        done = len(st)
+        mv = sum(s_["matvecs"] for s_ in st)
+        q = max(steps // 4, 1)
+        quarters = [max(amax[i:i + q], default=None) for i in range(0, steps, q)][:4]
+        peak = max(amax, default=0.0)
+        # bounded: ran the whole window and the last quarter stays below the
+        # peak of the earlier ones (ringing after the pulse, no growth)
+        bounded = diverged is None and len(quarters) == 4 and quarters[-1] <= max(quarters[:3])
+        row = {"alpha": alpha, "steps": steps, "steps_done": done, "diverged_at_step": diverged,
+               "bounded": bounded, "max_abs_J_per_quarter": quarters,
+               "nlags": info["nlags"], "z0_nnz": native.zk_nnz(*n, k=0, alpha=alpha),
+               "history_block": info["history_block"], "device_bytes": info["bytes"], "setup_s": setup,
+               "window_s": el, "steps_per_s": done / el,
+               "iters_per_step": {"mean": sum(s_["iters"] for s_ in st) / max(done, 1),
+                                  "max": max((s_["iters"] for s_ in st), default=0)},
+               "matvecs_per_step": mv / max(done, 1),
+               "ms_lhs_per_step": sum(s_["ms_lhs"] for s_ in st) / max(done, 1),
+               "ms_rhs_per_step": sum(s_["ms_rhs"] for s_ in st) / max(done, 1),
+               "ms_per_matvec_in_solve": sum(s_["ms_lhs"] for s_ in st) / max(mv, 1),
+               "relres_max": max((s_["relres"] for s_ in st), default=None)}
+        rows.append(row)
+        log_fn(f"sweep alpha {alpha}: {done} of {steps} steps in {el:.2f} s (diverged at {diverged}), "
+               f"ell {info['nlags']}, "
+               f"{row['iters_per_step']['mean']:.2f} iterations/step, LHS {row['ms_lhs_per_step']:.2f} ms/step, "
+               f"RHS {row['ms_rhs_per_step']:.2f} ms/step")
+        c.close()
+        del c
+        torch.cuda.empty_cache()
+    # the march's own time-step convergence, against the smallest alpha whose
+    # current stayed bounded over the whole window
+    ok = [r["alpha"] for r in rows if r["bounded"]]
+    a0 = min(ok) if ok else None
+    if a0 is not None:
+        ref = probes[a0]
+        scale = max(abs(v) for v in ref) or 1.0
+        for row in rows:
+            pr = probes[row["alpha"]]
+            m = min(len(pr), len(ref))
+            row["probe_diff_vs_ref"] = (max(abs(a - b) for a, b in zip(pr[:m], ref[:m])) / scale) if m else None
+    return {"workload": "nested_cube_96x96x96_fixed_window", "precision": args.precision,
+            "tol": args.tol, "window_dt_cfl": args.sweep_window, "probe": "J_x at voxel (48, 48, 48)",
+            "probe_ref_alpha": a0, "rows": rows}
+
+
 def sources_sha256(paths):
     """sha256 over the concatenated contents of the given repository files."""
     import hashlib
@@ -257,6 +363,11 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="also time a batch of 32 independent cubes (sides 24..80, alpha 4) stepped together")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the time-step sweep on the 96^3 nested cube (alpha 1..16, one physical window)")
+    ap.add_argument("--sweep-only", action="store_true", help="run only the time-step sweep and print its JSON line")
+    ap.add_argument("--sweep-alphas", type=int, nargs="+", default=[1, 2, 4, 8, 16])
+    ap.add_argument("--sweep-window", type=int, default=1600, help="window length in dt_CFL")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no timing events in the timed region (the roofline then uses the breakdown steps)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -283,9 +394,13 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4, "launches": 3}))
         return
 
+    torch.cuda.set_device(0)
+    if args.sweep_only:
+        print(json.dumps({"sweep": sweep_leg(args, log)}), flush=True)
+        return
+
     w = W.PILLARS
     n = w.n
-    torch.cuda.set_device(0)
     eps = w.eps()
     N = n[0] * n[1] * n[2]
     t0 = time.perf_counter()
@@ -457,6 +572,8 @@ def main():
         out.update(f64_march(args, w, eps, p, L, Js, n_keep, log))
     if args.batch:
         out["batch"] = batch_leg(args, log)
+    if args.sweep:
+        out["sweep"] = sweep_leg(args, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, eps, out["matvecs_per_step"], nl, log)
     print(json.dumps(out), flush=True)

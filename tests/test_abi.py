@@ -63,6 +63,14 @@ def test_zk_nnz_bit_exact(n, k, alpha, cdt):
     assert native.zk_nnz(*n, k=k, alpha=alpha, cdt=cdt) == ref
 
 
+@pytest.mark.parametrize("alpha", [1, 2, 4, 8, 16])
+def test_z0_nnz_nested_cube_sweep(alpha):
+    """Z0 nonzeros of the 96^3 time-step sweep, library against the oracle's
+    mask count (the growth of the causal region with the time step)."""
+    from paper_2607_28309_amd import native
+    assert native.zk_nnz(96, 96, 96, k=0, alpha=alpha) == masks.zk_nnz(96, 96, 96, k=0, alpha=alpha)
+
+
 def test_table3_rows_from_library():
     # Table III (Sec. III-B): 40^3/alpha=4 -> 9.24e6 and 80^3/alpha=2 -> 76.09e6
     from paper_2607_28309_amd import native
