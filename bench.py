@@ -306,6 +306,9 @@ def sweep_leg(args, log_fn):
             pr = probes[row["alpha"]]
             m = min(len(pr), len(ref))
             row["probe_diff_vs_ref"] = (max(abs(a - b) for a, b in zip(pr[:m], ref[:m])) / scale) if m else None
+            h = min(m, len(ref) // 2)   # first half of the window: the pulse itself, before the ringing
+            row["probe_diff_vs_ref_first_half"] = (max(abs(a - b) for a, b in zip(pr[:h], ref[:h])) /
+                                                   (max(abs(v) for v in ref[:h]) or 1.0)) if h else None
     return {"workload": "nested_cube_96x96x96_fixed_window", "precision": args.precision,
             "tol": args.tol, "window_dt_cfl": args.sweep_window, "probe": "J_x at voxel (48, 48, 48)",
             "probe_ref_alpha": a0, "rows": rows}
