@@ -405,8 +405,8 @@ def test_march_cube64_refined_vs_f64_full_length(gpu_lib):
     # pulse's first 100 steps: after them the difference between the two
     # marches, seeded by each solve's 1e-6 tolerance, grows by about 5.6 % per
     # step (3 % on a 32^3 cube of this medium, where the FP64 march follows
-    # the oracle's) while the field decays, and it reaches the size of the
-    # field by the last steps.
+    # the oracle's over all 300 steps) while the field decays, and it reaches
+    # the size of the field by the last steps.
     import torch
     w = W.CUBE64
     n, alpha = w.n, w.alpha
