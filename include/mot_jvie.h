@@ -95,7 +95,8 @@ typedef struct {
 } mot_pulse;
 
 /* Create a context for `grid` with the given precision on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  Allocates the FFT workspaces,
+ * (a hipStream_t; NULL = the default stream): one MOT system of Eq. 3 on the
+ * voxel grid of Sec. II, with dt = alpha dt_CFL (Eq. 9) and ell lags (Eq. 4).  Allocates the FFT workspaces,
  * the Krylov vectors, the spectra and the history ring (ell spectra of past
  * currents: 3*(2nz)*(2ny)*(nx+1) complex each, FP64 for MOT_F64, else FP32).
  * Errors: MOT_EINVAL (shape, lengths, alpha/cdt), MOT_ENOMEM, MOT_EHIP. */
@@ -123,11 +124,15 @@ int build_green_spectra(mot_ctx* ctx);
  * to rounding because every component is even or odd-odd per axis). */
 double mot_spectra_imag(const mot_ctx* ctx);
 
-/* Set eps_r per voxel (device pointer, nx*ny*nz FP64, copied).  Voxels with
- * eps_r = 1 carry no current.  Errors: MOT_EINVAL. */
+/* Set eps_r per voxel (device pointer, nx*ny*nz FP64, copied): the relative
+ * permittivity eps(r)/eps0 of Eq. 1 (Sec. II), piecewise constant on the
+ * voxels; it sets D = diag(eps_r)/2 and X = diag(eps_r - 1) of Eq. 10.  Voxels
+ * with eps_r = 1 carry no current (the contrast current of Eq. 2 vanishes
+ * there).  Errors: MOT_EINVAL. */
 int mot_set_material(mot_ctx* ctx, const double* eps_r);
 
-/* y = Z0 J (Eq. 12) with the FFT product of Eq. 11.
+/* y = Z0 J (Eq. 12) with the FFT product of Eq. 11 (D = diag(eps_r)(1/2 +
+ * delta) with the regularization of mot_set_regularization, delta = 0 by default).
  *   dtype MOT_F64:         J, y FP64 device vectors, FP64 transforms;
  *   dtype MOT_F32:         J, y FP32 device vectors, FP32 transforms;
  *   dtype MOT_F32_REFINED: J, y FP64 device vectors, FP32 transforms (the
@@ -141,9 +146,9 @@ int z0_matvec(mot_ctx* ctx, const void* J, void* y, mot_precision dtype);
 int gk_matvec(mot_ctx* ctx, int32_t k, const void* J, void* y, mot_precision dtype);
 
 /* Push J_n (FP64 device vector) into the history ring and prepare the
- * history right-hand side of the next step,
+ * history right-hand side of the next step (Eq. 3, Eq. 6 RHS),
  *   h_{n+1} = -sum_{k=1..ell} Z_k J_{n+1-k}
- *           = -(eps_r/2) J_n + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
+ *           = -(1/2 - delta) eps_r J_n + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
  * using the spectra of past currents (each current is transformed once).
  * The spectral sums are blocked in time: every B steps (B = 8, halved while
  * B > ell) one pass over the ring accumulates the contributions of all
@@ -227,7 +232,22 @@ int mot_autotune(mot_ctx* ctx, int32_t reps, double* ms);
  * call.  Errors: MOT_EINVAL (k outside 0..8, or k > 0 for another precision). */
 int mot_set_predictor(mot_ctx* ctx, int32_t k);
 
-/* n = 0, history ring and history right-hand side zeroed (J_{n<0} = 0). */
+/* Regularized interaction matrices in the delta-notation of Sec. II
+ * (Z^delta_n = Z_n + delta_n I; the paper runs with delta_n = 0).  Here
+ * delta_0 = +delta diag(eps_r), delta_1 = -delta diag(eps_r), delta_n = 0 for
+ * n >= 2: the constitutive term eps_r J of Eq. 1 is weighted (1/2 + delta,
+ * 1/2 - delta) on (J_n, J_{n-1}) instead of the spline's (1/2, 1/2), which
+ * damps the current pattern that alternates in sign from step to step (it is
+ * invisible to the spline at the testing instants).  Z0 = diag(eps_r)(1/2 +
+ * delta) - X G_0 in z0_matvec, mot_step and the adjoint calls; the history
+ * right-hand side uses (1/2 - delta) eps_r J_{n-1}.  Default delta = 0 (the
+ * paper's operator).  May be called at any time; the next step uses it.
+ * Drops captured iteration graphs and the initial-guess pairs.
+ * Errors: MOT_EINVAL (NULL, delta outside [0, 1/2)). */
+int mot_set_regularization(mot_ctx* ctx, double delta);
+
+/* Start a new march of Eq. 3: n = 0, history ring and history right-hand
+ * side zeroed (J_{n<0} = 0: the causal start of the recursion). */
 int mot_reset(mot_ctx* ctx);
 
 /* Set the step counter to n >= 0 without touching the history ring or the
@@ -279,7 +299,8 @@ int mot_profile_kinds(mot_ctx* ctx, int32_t kind_mask);
  * r_m the voxel centre relative to the grid centre, T' the derivative of the
  * temporal basis in step units.  For W = dt sum_j |e_j|^2 the adjoint sources
  * are g_n = mot_farfield_adjoint(2 dt e) and
- *   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - (J_n(m) + J_{n-1}(m))/2 + u_n(m)),
+ *   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - (1/2 + delta) J_n(m)
+ *                                  - (1/2 - delta) J_{n-1}(m) + u_n(m)),
  * u_n = sum_{k=0..ell} G_k J_{n-k} = (mot_history_gfield read just before
  * step n) + gk_matvec(0, J_n). */
 
@@ -289,7 +310,7 @@ int mot_profile_kinds(mot_ctx* ctx, int32_t kind_mask);
  * Errors: MOT_EINVAL. */
 int mot_set_adjoint(mot_ctx* ctx, int32_t on);
 
-/* y = Z0^T v = (eps_r/2) v - G_0 ((eps_r - 1) v), dtypes as z0_matvec.
+/* y = Z0^T v = (1/2 + delta) eps_r v - G_0 ((eps_r - 1) v), dtypes as z0_matvec.
  * Errors: MOT_EINVAL, MOT_ESTATE, MOT_EHIP. */
 int z0t_matvec(mot_ctx* ctx, const void* v, void* y, mot_precision dtype);
 
@@ -315,7 +336,8 @@ int mot_farfield(mot_ctx* ctx, const double* Jhist, int32_t nsteps, const double
 int mot_farfield_adjoint(mot_ctx* ctx, const double* w, int32_t j0, int32_t nj, const double* rhat, double scale,
                          int64_t n, double* g_n);
 
-/* grad[m] += sum_p lam_n[p,m] (d_t E^i_p(r_m, t) - (J_n[p,m] + J_prev[p,m])/2 + uh_n[p,m] + u0_n[p,m])
+/* grad[m] += sum_p lam_n[p,m] (d_t E^i_p(r_m, t) - (1/2 + delta) J_n[p,m] - (1/2 - delta) J_prev[p,m]
+ *                               + uh_n[p,m] + u0_n[p,m])
  * for every voxel m: the step-n term of dW/d eps with u_n = uh_n + u0_n split
  * into its history part (mot_history_gfield before step n) and its present
  * part (gk_matvec(0, J_n)).  FP64 device vectors: lam_n, J_n, J_prev, uh_n,

@@ -7,6 +7,9 @@ the transpose of Z_k = T(k) diag(eps_r) - diag(eps_r - 1) G_k (Eq. 10 form) is
     Z_k^T = T(k) diag(eps_r) - G_k diag(eps_r - 1):
 the contrast acts on the input.  In particular
     Z0^T v = (eps_r/2) v - G_0 ((eps_r - 1) v).
+With the regularization of ``operators`` the diagonal weights 1/2 of Z0 and
+Z1 become 1/2 + delta and 1/2 - delta (they are diagonal, so the transpose
+keeps them).
 
 Far field (reading; the paper does not use one).  The current radiates
 through the retarded vector potential of Eq. 1; far from the scatterer, with
@@ -24,9 +27,11 @@ system sum_{k=0..ell} Z_k J_{n-k} = E_n, n = 0..Nt-1.  Its transpose,
 sum_k Z_k^T lam_{n+k} = g_n with g_n = dW/dJ_n, is solved backwards in time
 from n = Nt-1 (lam_{n >= Nt} = 0):
     Z0^T lam_n = g_n - (eps_r/2) lam_{n+1} + sum_{k>=1} G_k ((eps_r - 1) lam_{n+k}).
+(with delta: (1/2 + delta) eps_r in Z0^T, (1/2 - delta) eps_r on lam_{n+1}).
 
 Gradient.  E_n = (eps_r - 1) d_t E^i(r_m, t_n) and the Z_k depend on eps_r, so
     dW/d eps_m = sum_n lam_n(m) . [d_t E^i(r_m, t_n) - (J_n(m) + J_{n-1}(m))/2 + u_n(m)],
+(with delta: -(1/2 + delta) J_n(m) - (1/2 - delta) J_{n-1}(m) in the bracket),
     u_n = sum_{k=0..ell} G_k J_{n-k}.
 
 Pins (tests/test_oracle_adjoint.py): the transpose against the dense Z0 and
@@ -45,9 +50,9 @@ from .march import Mot, dt_einc, voxel_centres
 from .operators import gconv_fft
 
 
-def z0t_apply(g0_oct, eps, v, lam=None):
-    """Z0^T v = (eps_r/2) v - G_0 ((eps_r - 1) v); v shape (3, nz, ny, nx)."""
-    return 0.5 * eps[None] * v - gconv_fft(g0_oct, (eps[None] - 1.0) * v, lam=lam)
+def z0t_apply(g0_oct, eps, v, lam=None, delta=0.0):
+    """Z0^T v = (1/2 + delta) eps_r v - G_0 ((eps_r - 1) v); v shape (3, nz, ny, nx)."""
+    return (0.5 + delta) * eps[None] * v - gconv_fft(g0_oct, (eps[None] - 1.0) * v, lam=lam)
 
 
 def dspline(s):
@@ -123,9 +128,9 @@ def gfield(greens, Jhist, n):
     return u
 
 
-def forward(eps, greens, dt, pulse, nsteps, tol=1e-12, max_iter=1000):
+def forward(eps, greens, dt, pulse, nsteps, tol=1e-12, max_iter=1000, delta=0.0):
     """The MOT march of ``march.Mot``; returns Jhist (nsteps, 3, nz, ny, nx)."""
-    mot = Mot(eps, greens, dt)
+    mot = Mot(eps, greens, dt, delta=delta)
     out = []
     for n in range(nsteps):
         J, _ = mot.step(dt_einc(pulse, mot.eps, n * dt), tol=tol, max_iter=max_iter)
@@ -133,7 +138,7 @@ def forward(eps, greens, dt, pulse, nsteps, tol=1e-12, max_iter=1000):
     return np.array(out)
 
 
-def adjoint_march(eps, greens, g, tol=1e-12, max_iter=1000):
+def adjoint_march(eps, greens, g, tol=1e-12, max_iter=1000, delta=0.0):
     """lam_n for n = Nt-1 .. 0 from the sources g (Nt, 3, nz, ny, nx)."""
     eps = np.asarray(eps, dtype=np.float64)
     nt = g.shape[0]
@@ -143,11 +148,11 @@ def adjoint_march(eps, greens, g, tol=1e-12, max_iter=1000):
     for n in range(nt - 1, -1, -1):
         rhs = g[n].copy()
         if n + 1 < nt:
-            rhs -= 0.5 * eps[None] * lam[n + 1]
+            rhs -= (0.5 - delta) * eps[None] * lam[n + 1]
         for k in range(1, nl + 1):
             if n + k < nt:
                 rhs += gconv_fft(greens[k], (eps[None] - 1.0) * lam[n + k])
-        res = tfqmr(lambda v: z0t_apply(greens[0], eps, v.reshape(shape)).ravel(), rhs.ravel(), tol=tol,
+        res = tfqmr(lambda v: z0t_apply(greens[0], eps, v.reshape(shape), delta=delta).ravel(), rhs.ravel(), tol=tol,
                     max_iter=max_iter)
         lam[n] = res.x.reshape(shape)
     return lam
@@ -158,25 +163,25 @@ def incident_dt(pulse, shape, t):
     return dt_einc(pulse, np.full(shape, 2.0), t)
 
 
-def energy_of(eps, greens, dt, pulse, nsteps, rhat, j0, nj, tol=1e-12):
+def energy_of(eps, greens, dt, pulse, nsteps, rhat, j0, nj, tol=1e-12, delta=0.0):
     """W for permittivity eps (forward march, far field, energy)."""
-    J = forward(eps, greens, dt, pulse, nsteps, tol=tol)
+    J = forward(eps, greens, dt, pulse, nsteps, tol=tol, delta=delta)
     return energy(farfield(J, rhat, dt, j0, nj), dt)
 
 
-def gradient(eps, greens, dt, pulse, nsteps, rhat, j0, nj, tol=1e-12):
+def gradient(eps, greens, dt, pulse, nsteps, rhat, j0, nj, tol=1e-12, delta=0.0):
     """(W, dW/d eps) by the adjoint march; dW/d eps has the shape of eps."""
     eps = np.asarray(eps, dtype=np.float64)
-    J = forward(eps, greens, dt, pulse, nsteps, tol=tol)
+    J = forward(eps, greens, dt, pulse, nsteps, tol=tol, delta=delta)
     e = farfield(J, rhat, dt, j0, nj)
     W = energy(e, dt)
     g = farfield_adjoint(2.0 * dt * e, rhat, dt, j0, nsteps, eps.shape)
-    lam = adjoint_march(eps, greens, g, tol=tol)
+    lam = adjoint_march(eps, greens, g, tol=tol, delta=delta)
     grad = np.zeros(eps.shape)
     for n in range(nsteps):
         q = incident_dt(pulse, eps.shape, n * dt) + gfield(greens, J, n)
-        q -= 0.5 * J[n]
+        q -= (0.5 + delta) * J[n]
         if n > 0:
-            q -= 0.5 * J[n - 1]
+            q -= (0.5 - delta) * J[n - 1]
         grad += np.sum(lam[n] * q, axis=0)
     return W, grad

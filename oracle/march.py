@@ -14,6 +14,9 @@ MOT recursion (Eq. 3, Eq. 6):
     Z_k    = T(k) diag(eps_r) - diag(eps_r - 1) G_k,
 so with T(1) = 1/2 and T(k >= 2) = 0 the history term is
     sum_{k>=1} Z_k J_{n-k} = (eps_r/2) J_{n-1} - (eps_r - 1) sum_{k>=1} G_k * J_{n-k}.
+With the regularization of ``operators`` (delta_0 = +delta eps_r,
+delta_1 = -delta eps_r) the local weights become (1/2 + delta) on J_n in Z0
+and (1/2 - delta) on J_{n-1} in the history term.
 Each Z0 system is solved by ``krylov.tfqmr``; each Green convolution uses the
 FFT form of Eq. 11 (``operators``), with the spectra of past currents kept so
 that each current is transformed once.
@@ -56,8 +59,9 @@ class Mot:
     ``greens`` is the list [G_0, ..., G_ell] of octant tables (``green``).
     """
 
-    def __init__(self, eps, greens, cdt):
+    def __init__(self, eps, greens, cdt, delta=0.0):
         self.eps = np.asarray(eps, dtype=np.float64)
+        self.delta = float(delta)
         self.nz, self.ny, self.nx = self.eps.shape
         self.cdt = float(cdt)
         self.nl = len(greens) - 1
@@ -83,7 +87,7 @@ class Mot:
     def z0(self, J):
         """Z0 J (Eq. 12)."""
         gj = self._back(self._apply_spec(self.lams[0], self._spec(J)))
-        return 0.5 * self.eps[None] * J - (self.eps[None] - 1.0) * gj
+        return (0.5 + self.delta) * self.eps[None] * J - (self.eps[None] - 1.0) * gj
 
     def history_rhs(self):
         """-sum_{k>=1} Z_k J_{n-k} for the current n."""
@@ -92,7 +96,7 @@ class Mot:
             if k - 1 < len(self.hist):
                 S += self._apply_spec(self.lams[k], self.hist[k - 1])
         h = self._back(S)
-        return -0.5 * self.eps[None] * self.jprev + (self.eps[None] - 1.0) * h
+        return -(0.5 - self.delta) * self.eps[None] * self.jprev + (self.eps[None] - 1.0) * h
 
     def step(self, einc, tol=1e-6, max_iter=1000):
         """One MOT step: returns (J_n, TfqmrResult)."""
@@ -108,9 +112,9 @@ class Mot:
         return J, res
 
 
-def run(eps, greens, cdt, pulse, nsteps, tol=1e-6, max_iter=1000, probe=None):
+def run(eps, greens, cdt, pulse, nsteps, tol=1e-6, max_iter=1000, probe=None, delta=0.0):
     """March ``nsteps`` steps; returns (J history or probe trace, iteration counts)."""
-    mot = Mot(eps, greens, cdt)
+    mot = Mot(eps, greens, cdt, delta=delta)
     out, iters = [], []
     for n in range(nsteps):
         J, res = mot.step(dt_einc(pulse, mot.eps, n * cdt), tol=tol, max_iter=max_iter)

@@ -4,6 +4,14 @@ Eq. 10: Z0 = D - X G with D = diag(eps_r) T(0) = diag(eps_r)/2 and
 X = diag(eps_r - 1) (reading of Eq. 1: the constitutive term eps_r J is
 tested at t_n, where the spline basis gives J(t_n) = (J_n + J_{n-1})/2).
 
+Regularization (Sec. II, the delta-notation Z^delta_n = Z_n + delta_n I of
+the regularized MOT formulation the paper cites; the paper itself runs with
+delta_n = 0).  Reading used here: delta_0 = +delta diag(eps_r),
+delta_1 = -delta diag(eps_r), delta_n = 0 for n >= 2, i.e. the constitutive
+term is tested with the weights (1/2 + delta, 1/2 - delta) on (J_n, J_{n-1}).
+delta = 0 (the default everywhere) is the paper's unregularized operator;
+then D = diag(eps_r)(1/2 + delta).
+
 Three forms of the same product, all FP64:
 
 * ``z0_dense``     -- the 3N x 3N matrix assembled entry by entry (tiny grids);
@@ -20,7 +28,7 @@ import numpy as np
 from .green import PAIR, green_full
 
 
-def z0_dense(g0_oct, eps):
+def z0_dense(g0_oct, eps, delta=0.0):
     """Dense Z0 for a grid with eps of shape (nz, ny, nx); row/col = p*N + m."""
     nz, ny, nx = eps.shape
     N = eps.size
@@ -36,7 +44,7 @@ def z0_dense(g0_oct, eps):
         for p in range(3):
             for q in range(3):
                 Z[p * N + m, q * N:(q + 1) * N] = -(e[m] - 1.0) * full[p, q, dz, dy, dx]
-            Z[p * N + m, p * N + m] += e[m] / 2.0
+            Z[p * N + m, p * N + m] += e[m] * (0.5 + delta)
     return Z
 
 
@@ -107,12 +115,12 @@ def gconv_fft(g_oct, J, lam=None):
     return out
 
 
-def z0_apply(g0_oct, eps, J, method="fft", lam=None):
-    """Z0 J = D J - X (G J), Eq. 12."""
+def z0_apply(g0_oct, eps, J, method="fft", lam=None, delta=0.0):
+    """Z0 J = D J - X (G J), Eq. 12 (D = diag(eps_r)(1/2 + delta))."""
     if method == "fft":
         gj = gconv_fft(g0_oct, J, lam=lam)
     elif method == "direct":
         gj = gconv_direct(g0_oct, J)
     else:
         raise ValueError(method)
-    return 0.5 * eps[None] * J - (eps[None] - 1.0) * gj
+    return (0.5 + delta) * eps[None] * J - (eps[None] - 1.0) * gj

@@ -128,7 +128,8 @@ __global__ void k_farfield_adj(const double* __restrict__ w, int j0, int nj, lon
 
 __global__ void k_adjoint_grad(mot_pulse pl, double t, const double* __restrict__ lam, const double* __restrict__ J,
                                const double* __restrict__ Jprev, const double* __restrict__ uh,
-                               const double* __restrict__ u0, double* __restrict__ grad, int nx, int ny, int nz) {
+                               const double* __restrict__ u0, double* __restrict__ grad, double delta, int nx, int ny,
+                               int nz) {
   const long long N = (long long)nx * ny * nz;
   const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= N) return;
@@ -139,8 +140,8 @@ __global__ void k_adjoint_grad(mot_pulse pl, double t, const double* __restrict_
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const long long i = p * N + m;
-    const double jj = Jprev ? J[i] + Jprev[i] : J[i];
-    acc += lam[i] * (di * pl.e[p] - 0.5 * jj + (uh[i] + u0[i]));
+    const double jj = Jprev ? (0.5 + delta) * J[i] + (0.5 - delta) * Jprev[i] : (0.5 + delta) * J[i];
+    acc += lam[i] * (di * pl.e[p] - jj + (uh[i] + u0[i]));
   }
   grad[m] += acc;
 }
@@ -171,11 +172,11 @@ hipError_t launch_farfield_adjoint(const double* w, int j0, int nj, long long n,
 }
 
 hipError_t launch_adjoint_grad(const mot_pulse* p, double t, const double* lam, const double* J,
-                               const double* Jprev, const double* uh, const double* u0, double* grad, int nx, int ny,
-                               int nz, hipStream_t s) {
+                               const double* Jprev, const double* uh, const double* u0, double* grad, double delta,
+                               int nx, int ny, int nz, hipStream_t s) {
   const long long N = (long long)nx * ny * nz;
   hipLaunchKernelGGL(k_adjoint_grad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, *p, t, lam, J, Jprev, uh,
-                     u0, grad, nx, ny, nz);
+                     u0, grad, delta, nx, ny, nz);
   return hipGetLastError();
 }
 

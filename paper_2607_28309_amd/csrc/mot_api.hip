@@ -80,6 +80,9 @@ struct mot_ctx {
   double spectra_imag;
   void* lam_tile;      // scratch: one history lag in the z-pass layout (gk_matvec)
   int adjoint;         // 1: transposed operators Z_k^T (adjoint march)
+  // regularization Z^delta_0 = Z_0 + delta diag(eps_r), Z^delta_1 = Z_1 -
+  // delta diag(eps_r) (0: the unregularized operator)
+  double delta;
   double* ffpart;      // scratch: far-field block partials
   size_t ffpart_n;
   int tune[2][TUNE_N]; // tile variants of the FFT passes (0 or 1)
@@ -257,12 +260,12 @@ __global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int n
       src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
 }
 
-// rs = 1 / (eps/2 - (eps - 1) g0), the inverse diagonal of Z0 per voxel
-__global__ void k_right_scale(const double* __restrict__ eps, double g0, float* __restrict__ rs32,
+// rs = 1 / ((1/2 + delta) eps - (eps - 1) g0), the inverse diagonal of Z0 per voxel
+__global__ void k_right_scale(const double* __restrict__ eps, double g0, double delta, float* __restrict__ rs32,
                               double* __restrict__ rs64, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double r = 1.0 / (eps[i] * (0.5 - g0) + g0);
+  const double r = 1.0 / (eps[i] * (0.5 + delta - g0) + g0);
   rs64[i] = r;
   rs32[i] = (float)r;
 }
@@ -329,12 +332,14 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
   return MOT_OK;
 }
 
-const motfft::Epilogue EP_Z0{0.5, 0.0, -1.0, 1.0};      // D J - X (G J)
-const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};        // G J
-const motfft::Epilogue EP_HIST{-0.5, 0.0, 1.0, -1.0};   // -(eps/2) J + X (G J)
+// Epilogues of the products.  D = (1/2 + delta) eps_r is the diagonal of Z0,
+// (1/2 - delta) eps_r that of Z1 (delta = c->delta, 0 without regularization).
+motfft::Epilogue ep_z0(const mot_ctx* c) { return {0.5 + c->delta, 0.0, -1.0, 1.0}; }    // D J - X (G J)
+const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};                                          // G J
+motfft::Epilogue ep_hist(const mot_ctx* c) { return {-(0.5 - c->delta), 0.0, 1.0, -1.0}; } // -(diag Z1) J + X (G J)
 // transposed operators (contrast on the input, applied by the forward x pass)
-const motfft::Epilogue EP_Z0T{0.5, 0.0, 0.0, -1.0};     // (eps/2) v - G (X v)
-const motfft::Epilogue EP_ADJ_HIST{-0.5, 0.0, 0.0, 1.0}; // -(eps/2) v + G (X v)
+motfft::Epilogue ep_z0t(const mot_ctx* c) { return {0.5 + c->delta, 0.0, 0.0, -1.0}; }     // D v - G (X v)
+motfft::Epilogue ep_adj_hist(const mot_ctx* c) { return {-(0.5 - c->delta), 0.0, 0.0, 1.0}; } // -(diag Z1) v + G (X v)
 
 int reduce_sync(mot_ctx* c) {
   HT(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->stream));
@@ -356,15 +361,15 @@ template <typename Mid = NoMid>
 int apply_z0(mot_ctx* c, const double* in, double* out, motfft::Gate g = motfft::Gate{},
              const motfft::Krylov* kf = nullptr, const motfft::Krylov* ki = nullptr, const double* jd = nullptr,
              Mid mid = Mid{}) {
-  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0T, c->eps, g, kf, ki, jd, mid);
-  return green_product<double, double>(c, in, out, c->lam0_64, EP_Z0, nullptr, g, kf, ki, jd, mid);
+  if (c->adjoint) return green_product<double, double>(c, in, out, c->lam0_64, ep_z0t(c), c->eps, g, kf, ki, jd, mid);
+  return green_product<double, double>(c, in, out, c->lam0_64, ep_z0(c), nullptr, g, kf, ki, jd, mid);
 }
 template <typename Mid = NoMid>
 int apply_z0(mot_ctx* c, const float* in, float* out, motfft::Gate g = motfft::Gate{},
              const motfft::Krylov* kf = nullptr, const motfft::Krylov* ki = nullptr, const float* jd = nullptr,
              Mid mid = Mid{}) {
-  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0T, c->eps, g, kf, ki, jd, mid);
-  return green_product<float, float>(c, in, out, c->lam0_32, EP_Z0, nullptr, g, kf, ki, jd, mid);
+  if (c->adjoint) return green_product<float, float>(c, in, out, c->lam0_32, ep_z0t(c), c->eps, g, kf, ki, jd, mid);
+  return green_product<float, float>(c, in, out, c->lam0_32, ep_z0(c), nullptr, g, kf, ki, jd, mid);
 }
 
 template <typename V> struct KV;
@@ -878,7 +883,7 @@ int history_update_t(mot_ctx* c, const double* J) {
                                   c->nz, c->nz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
                                   c->ny, c->twy[ti], s, {}, tv[TUNE_Y]));
-  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, c->adjoint ? EP_ADJ_HIST : EP_HIST, c->nx,
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, c->adjoint ? ep_adj_hist(c) : ep_hist(c), c->nx,
                                               rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
                                               tv[TUNE_X])));
@@ -926,7 +931,7 @@ void drop_graphs(mot_ctx* c) {
 int update_right_scale(mot_ctx* c) {
   if (!c->have_eps || !c->have_spectra) return MOT_OK;
   hipLaunchKernelGGL(k_right_scale, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, c->stream, c->eps,
-                     c->g0self, c->rs32, c->rs64, c->N);
+                     c->g0self, c->delta, c->rs32, c->rs64, c->N);
   HT(hipGetLastError());
   return MOT_OK;
 }
@@ -1005,8 +1010,8 @@ int autotune_impl(mot_ctx* c, int reps, double* ms) {
   };
   for (int ti = 1; ti >= 0; --ti) {
     auto product = [&]() -> int {
-      return ti == 1 ? green_product<double, double>(c, in, out, c->lam0_64, EP_Z0)
-                     : green_product<float, float>(c, (const float*)in, (float*)out, c->lam0_32, EP_Z0);
+      return ti == 1 ? green_product<double, double>(c, in, out, c->lam0_64, ep_z0(c))
+                     : green_product<float, float>(c, (const float*)in, (float*)out, c->lam0_32, ep_z0(c));
     };
     for (int knob : {TUNE_X, TUNE_Y, TUNE_ZF}) TRY(tune_knob(ti, knob, product));
     if (ti == c->ring_f64) {
@@ -1317,11 +1322,11 @@ int z0_matvec(mot_ctx* c, const void* J, void* y, mot_precision dtype) {
   if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
   switch (dtype) {
     case MOT_F64:
-      return green_product<double, double>(c, (const double*)J, (double*)y, c->lam0_64, EP_Z0);
+      return green_product<double, double>(c, (const double*)J, (double*)y, c->lam0_64, ep_z0(c));
     case MOT_F32:
-      return green_product<float, float>(c, (const float*)J, (float*)y, c->lam0_32, EP_Z0);
+      return green_product<float, float>(c, (const float*)J, (float*)y, c->lam0_32, ep_z0(c));
     case MOT_F32_REFINED:
-      return green_product<float, double>(c, (const double*)J, (double*)y, c->lam0_32, EP_Z0);
+      return green_product<float, double>(c, (const double*)J, (double*)y, c->lam0_32, ep_z0(c));
     default:
       return MOT_EINVAL;
   }
@@ -1493,6 +1498,17 @@ int mot_set_predictor(mot_ctx* c, int32_t k) {
   return MOT_OK;
 }
 
+int mot_set_regularization(mot_ctx* c, double delta) {
+  if (!c || !(delta >= 0.0 && delta < 0.5)) return MOT_EINVAL;
+  if (delta == c->delta) return MOT_OK;
+  c->delta = delta;
+  // the diagonal of Z0 changed: the right scaling, the captured iteration
+  // graphs (their epilogue arguments) and the stored Z0 J_i are stale
+  drop_graphs(c);
+  pred_clear(c);
+  return update_right_scale(c);
+}
+
 int mot_set_graphs(mot_ctx* c, int32_t on) {
   if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
   c->use_graphs = on;
@@ -1540,11 +1556,11 @@ int z0t_matvec(mot_ctx* c, const void* v, void* y, mot_precision dtype) {
   if (!c->have_eps || !c->have_spectra) return set_err(c, MOT_ESTATE, "material or spectra missing%s%d");
   switch (dtype) {
     case MOT_F64:
-      return green_product<double, double>(c, (const double*)v, (double*)y, c->lam0_64, EP_Z0T, c->eps);
+      return green_product<double, double>(c, (const double*)v, (double*)y, c->lam0_64, ep_z0t(c), c->eps);
     case MOT_F32:
-      return green_product<float, float>(c, (const float*)v, (float*)y, c->lam0_32, EP_Z0T, c->eps);
+      return green_product<float, float>(c, (const float*)v, (float*)y, c->lam0_32, ep_z0t(c), c->eps);
     case MOT_F32_REFINED:
-      return green_product<float, double>(c, (const double*)v, (double*)y, c->lam0_32, EP_Z0T, c->eps);
+      return green_product<float, double>(c, (const double*)v, (double*)y, c->lam0_32, ep_z0t(c), c->eps);
     default:
       return MOT_EINVAL;
   }
@@ -1603,7 +1619,7 @@ int mot_farfield_adjoint(mot_ctx* c, const double* w, int32_t j0, int32_t nj, co
 int mot_adjoint_gradient(mot_ctx* c, const mot_pulse* p, double t, const double* lam_n, const double* J_n,
                          const double* J_prev, const double* uh_n, const double* u0_n, double* grad) {
   if (!c || !p || !lam_n || !J_n || !uh_n || !u0_n || !grad) return MOT_EINVAL;
-  HT(launch_adjoint_grad(p, t, lam_n, J_n, J_prev, uh_n, u0_n, grad, c->nx, c->ny, c->nz, c->stream));
+  HT(launch_adjoint_grad(p, t, lam_n, J_n, J_prev, uh_n, u0_n, grad, c->delta, c->nx, c->ny, c->nz, c->stream));
   return MOT_OK;
 }
 

@@ -30,7 +30,7 @@ EXPORTS = (
     "mot_length_supported", "mot_strerror", "mot_last_error", "mot_profile", "mot_profile_read",
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
-    "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor",
+    "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor", "mot_set_regularization",
 )
 TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
 PROF_NCLASS = 22
@@ -100,6 +100,7 @@ def _load():
         "mot_get_variants": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
         "mot_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
         "mot_set_predictor": (ctypes.c_int, [vp, i32]),
+        "mot_set_regularization": (ctypes.c_int, [vp, dbl]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -252,6 +253,10 @@ class Context:
 
     def set_adjoint(self, on=True):
         self._check(LIB.mot_set_adjoint(self.h, 1 if on else 0), "mot_set_adjoint")
+
+    def set_regularization(self, delta):
+        """delta of the regularized Z_0, Z_1 (0 = the unregularized operator)."""
+        self._check(LIB.mot_set_regularization(self.h, float(delta)), "mot_set_regularization")
 
     def set_predictor(self, k):
         """Initial guess of the refined solve from the last k solutions (0 = off)."""

@@ -1,0 +1,71 @@
+"""Write the oracle's reference traces used by the GPU parity tests and the
+benchmark's field-error figure.  Calls only ``oracle`` and the input recipes
+of ``workloads``; run it on the CPU:
+
+    python tests/golden/make_oracle_traces.py [cube32 | pillars80]
+
+Each trace is an FP64 march of Eq. 3 from t = 0 with the regularized
+operator (delta = DELTA_HAT / alpha, Sec. II delta-notation), TFQMR to 1e-10,
+saved as an .npz (no pickles) holding: the step count, alpha, delta, the
+per-step norm ||J_n||, the sampled voxel indices (flat, [z][y][x]) and J_n at
+those voxels for every step, shape (steps, 3, nsamples).
+"""
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle import basis, green, march  # noqa: E402
+
+CASES = {
+    # a 32^3 cut of the 64^3 i.i.d. eps_r ~ U[2, 6] medium, dt = 8 dt_CFL, 300 steps
+    "cube32": dict(eps=lambda: np.ascontiguousarray(W.CUBE64.eps()[:32, :32, :32]), alpha=8, steps=300,
+                   ppw=W.CUBE64.ppw, nsamples=192, seed=11),
+    # a 2x2-pillar cut (80 x 80 x 48) of the 8x8 pillar array, dt = 16 dt_CFL, 120 steps
+    "pillars80": dict(eps=lambda: np.ascontiguousarray(W.PILLARS.eps()[:, :80, :80]), alpha=16, steps=120,
+                      ppw=W.PILLARS.ppw, nsamples=192, seed=12),
+}
+
+
+def path(name):
+    return os.path.join(HERE, f"oracle_trace_{name}.npz")
+
+
+def make(name):
+    cs = CASES[name]
+    eps = cs["eps"]()
+    nz, ny, nx = eps.shape
+    alpha = cs["alpha"]
+    delta = W.delta_for(alpha)
+    L = basis.cdt_from_alpha(alpha)
+    nl = basis.nlags(nx, ny, nz, alpha=alpha)
+    t0 = time.time()
+    G = green.green_all(nx, ny, nz, nl, alpha=alpha)
+    print(f"{name}: {nx}x{ny}x{nz}, alpha {alpha}, ell {nl}, delta {delta}: Green {time.time() - t0:.0f}s", flush=True)
+    rng = np.random.default_rng(cs["seed"])
+    mat = np.flatnonzero(eps.ravel() != 1.0)
+    idx = np.sort(rng.choice(mat, size=cs["nsamples"], replace=False))
+    p = W.pulse(cs["ppw"])
+    mot = march.Mot(eps, G, L, delta=delta)
+    norms, samp = [], []
+    for s in range(cs["steps"]):
+        J, res = mot.step(march.dt_einc(p, eps, s * L), tol=1e-10)
+        norms.append(np.linalg.norm(J))
+        samp.append(J.reshape(3, -1)[:, idx])
+        if s % 10 == 0:
+            print(f"  step {s}: |J| {norms[-1]:.4e}, {res.iterations} it, {time.time() - t0:.0f}s", flush=True)
+    np.savez(path(name), steps=cs["steps"], alpha=alpha, delta=delta, shape=np.array([nx, ny, nz]),
+             norms=np.array(norms), idx=idx, samples=np.array(samp))
+    print(f"wrote {path(name)}", flush=True)
+
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or list(CASES)):
+        make(n)

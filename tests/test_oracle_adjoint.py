@@ -22,18 +22,19 @@ def _dense_g(g_oct, shape):
     return np.eye(3 * int(np.prod(shape))) - operators.z0_dense(g_oct, W.eps_uniform(shape, 2.0))
 
 
+@pytest.mark.parametrize("delta", [0.0, 0.07])
 @pytest.mark.parametrize("n,alpha", [((3, 2, 2), 1), ((4, 3, 2), 4)])
-def test_z0t_is_dense_transpose(n, alpha):
+def test_z0t_is_dense_transpose(n, alpha, delta):
     g0 = green.green_octant(*n, 0, alpha=alpha)
     eps = W.eps_iid(n, 1.5, 6.0, seed=21)
     v = W.random_current(n, seed=22)
     u = W.random_current(n, seed=23)
-    Z = operators.z0_dense(g0, eps)
-    yt = adjoint.z0t_apply(g0, eps, v)
+    Z = operators.z0_dense(g0, eps, delta=delta)
+    yt = adjoint.z0t_apply(g0, eps, v, delta=delta)
     assert np.linalg.norm(yt.ravel() - Z.T @ v.ravel()) <= 1e-13 * np.linalg.norm(yt)
     # <Z0^T v, u> = <v, Z0 u>
     lhs = np.sum(yt * u)
-    rhs = np.sum(v * operators.z0_apply(g0, eps, u))
+    rhs = np.sum(v * operators.z0_apply(g0, eps, u, delta=delta))
     assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
 
 
@@ -84,14 +85,16 @@ def test_farfield_adjoint_dot_product():
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-def test_adjoint_march_solves_transposed_spacetime_system():
+@pytest.mark.parametrize("delta", [0.0, 0.07])
+def test_adjoint_march_solves_transposed_spacetime_system(delta):
     n, alpha, nt = (2, 2, 2), 1, 7
     nl = basis.nlags(*n, alpha=alpha)
     greens = green.green_all(*n, nl, alpha=alpha)
     eps = W.eps_iid(n, 2.0, 5.0, seed=41)
     shape = eps.shape
     m3 = 3 * eps.size
-    Tk = [0.5, 0.5] + [0.0] * (nl - 1)
+    # local weights of Z_0, Z_1: the spline's T(0) = T(1) = 1/2, shifted by +-delta
+    Tk = [0.5 + delta, 0.5 - delta] + [0.0] * (nl - 1)
     d = np.tile(eps.ravel(), 3)
     x = d - 1.0
     Zk = [Tk[k] * np.diag(d) - x[:, None] * _dense_g(greens[k], n) for k in range(nl + 1)]
@@ -101,11 +104,18 @@ def test_adjoint_march_solves_transposed_spacetime_system():
             A[r * m3:(r + 1) * m3, (r - k) * m3:(r - k + 1) * m3] = Zk[k]
     g = np.random.default_rng(42).standard_normal((nt, 3) + shape)
     lam_dense = np.linalg.solve(A.T, g.ravel()).reshape(g.shape)
-    lam = adjoint.adjoint_march(eps, greens, g, tol=1e-14)
+    lam = adjoint.adjoint_march(eps, greens, g, tol=1e-14, delta=delta)
     assert np.linalg.norm(lam - lam_dense) <= 1e-10 * np.linalg.norm(lam_dense)
+    # the forward march solves the same (untransposed) block-Toeplitz system
+    from oracle import march
+    J_dense = np.linalg.solve(A, g.ravel()).reshape(g.shape)
+    mot = march.Mot(eps, greens, basis.cdt_from_alpha(alpha), delta=delta)
+    J = np.array([mot.step(g[r], tol=1e-14)[0] for r in range(nt)])
+    assert np.linalg.norm(J - J_dense) <= 1e-10 * np.linalg.norm(J_dense)
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("delta", [0.0, 0.05])
+def test_gradient_matches_central_differences(delta):
     n, alpha, nt = (3, 2, 2), 2, 12
     dt = basis.cdt_from_alpha(alpha)
     nl = basis.nlags(*n, alpha=alpha)
@@ -114,16 +124,16 @@ def test_gradient_matches_central_differences():
     eps[0, 1, 2] = 1.0   # one air voxel: the gradient there is that of adding material
     rhat = np.array([0.48, -0.6, 0.64])
     j0, nj = -8, nt + 16
-    W0, grad = adjoint.gradient(eps, greens, dt, PULSE, nt, rhat, j0, nj)
+    W0, grad = adjoint.gradient(eps, greens, dt, PULSE, nt, rhat, j0, nj, delta=delta)
     assert W0 > 0.0
-    assert abs(W0 - adjoint.energy_of(eps, greens, dt, PULSE, nt, rhat, j0, nj)) <= 1e-12 * W0
+    assert abs(W0 - adjoint.energy_of(eps, greens, dt, PULSE, nt, rhat, j0, nj, delta=delta)) <= 1e-12 * W0
     h = 1e-4
     fd = np.zeros_like(eps)
     for idx in np.ndindex(eps.shape):
         ep, em = eps.copy(), eps.copy()
         ep[idx] += h
         em[idx] -= h
-        fd[idx] = (adjoint.energy_of(ep, greens, dt, PULSE, nt, rhat, j0, nj)
-                   - adjoint.energy_of(em, greens, dt, PULSE, nt, rhat, j0, nj)) / (2 * h)
+        fd[idx] = (adjoint.energy_of(ep, greens, dt, PULSE, nt, rhat, j0, nj, delta=delta)
+                   - adjoint.energy_of(em, greens, dt, PULSE, nt, rhat, j0, nj, delta=delta)) / (2 * h)
     assert np.abs(fd - grad).max() <= 1e-6 * np.abs(grad).max()
     assert np.abs(grad).max() > 0.0

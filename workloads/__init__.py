@@ -88,6 +88,17 @@ def sparse_current(n, seed, count):
     return J, idx
 
 
+# Regularization used for every march of these workloads: delta = DELTA_HAT *
+# dt_CFL / dt (the delta_0 = +delta eps_r, delta_1 = -delta eps_r form of the
+# regularized interaction matrices; 0 would be the unregularized operator).
+DELTA_HAT = 0.1
+
+
+def delta_for(alpha):
+    """delta for dt = alpha dt_CFL."""
+    return DELTA_HAT / float(alpha)
+
+
 @dataclass
 class Workload:
     name: str
