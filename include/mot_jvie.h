@@ -329,6 +329,19 @@ int mot_history_gfield(mot_ctx* ctx, double* out);
 int mot_farfield(mot_ctx* ctx, const double* Jhist, int32_t nsteps, const double* rhat, int32_t j0, int32_t nj,
                  double* e, double* energy);
 
+/* mot_farfield for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same samples and energy, bit for bit, with the block partials in a
+ * static device array of the library (6 MiB per GPU, held until the process
+ * ends) instead of a context buffer grown on first use.  Allocates nothing.
+ * 1 <= nj <= 1024 (larger nj: MOT_EINVAL).  The array belongs to the calling
+ * thread's current device, which must be the context's.  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (other streams or
+ * threads) race.  Nothing in it needs to start at zero (each call writes the
+ * partials it reads).  Errors: MOT_EINVAL, MOT_EHIP. */
+int mot_farfield_static(mot_ctx* ctx, const double* Jhist, int32_t nsteps, const double* rhat, int32_t j0,
+                        int32_t nj, double* e, double* energy);
+
 /* g_n (FP64 device, 3N) = scale * (transpose of mot_farfield applied to the
  * weights w (FP64 device, [nj][3]) for step n): scale times the derivative
  * of sum_j w_j . e_j with respect to J_n (w = e, scale = 2 dt gives

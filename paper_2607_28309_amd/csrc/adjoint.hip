@@ -17,6 +17,8 @@
 // the diagonal and contrast parts of every Z_k with respect to eps_m.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "mot_internal.h"
 
 namespace motimpl {
@@ -25,6 +27,18 @@ namespace {
 
 constexpr int FF_THREADS = 256;
 constexpr int FF_BLOCKS = 256;  // fixed partial count per sample: deterministic sums
+
+// Far-field partials of the allocation-free entry point: one copy per GPU,
+// held until the process ends.  Host code never uses this name as an
+// address: it resolves each device's copy with hipGetSymbolAddress once
+// (farfield_scratch) and passes that pointer to the kernels.
+constexpr size_t FF_SCRATCH_DOUBLES = (size_t)FF_NJ_MAX * FF_BLOCKS * 3;
+static __device__ __align__(256) double scratch[FF_SCRATCH_DOUBLES];
+
+constexpr int FF_MAX_DEVICES = 64;
+std::once_flag scratch_once[FF_MAX_DEVICES];
+double* scratch_ptr[FF_MAX_DEVICES];
+hipError_t scratch_err[FF_MAX_DEVICES];
 
 __device__ __forceinline__ double dspline(double s) {
   if (s >= -1.0 && s < 0.0) return s + 1.0;
@@ -149,6 +163,23 @@ __global__ void k_adjoint_grad(mot_pulse pl, double t, const double* __restrict_
 }  // namespace
 
 size_t farfield_partials(long long, int nj) { return (size_t)nj * FF_BLOCKS * 3; }
+
+hipError_t farfield_scratch(double** p) {
+  *p = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= FF_MAX_DEVICES) return hipErrorInvalidDevice;
+  // once per device, with that device current (it is the caller's current one)
+  std::call_once(scratch_once[dev], [dev] {
+    void* q = nullptr;
+    scratch_err[dev] = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    scratch_ptr[dev] = scratch_err[dev] == hipSuccess ? (double*)q : nullptr;
+  });
+  if (scratch_err[dev] != hipSuccess) return scratch_err[dev];
+  *p = scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_farfield(const double* Jhist, int nsteps, int nx, int ny, int nz, const FarGeom& g, int j0, int nj,
                            double* partials, double* e, double* W, hipStream_t s) {

@@ -1607,6 +1607,18 @@ int mot_farfield(mot_ctx* c, const double* Jhist, int32_t nsteps, const double* 
   return MOT_OK;
 }
 
+int mot_farfield_static(mot_ctx* c, const double* Jhist, int32_t nsteps, const double* rhat, int32_t j0, int32_t nj,
+                        double* e, double* energy) {
+  if (!c || !Jhist || !e || nsteps < 1 || nj < 1) return MOT_EINVAL;
+  if (nj > FF_NJ_MAX) return set_err(c, MOT_EINVAL, "mot_farfield_static takes at most 1024 samples%s%d");
+  FarGeom g;
+  TRY(far_geom(c, rhat, &g));
+  double* part = nullptr;
+  HT(farfield_scratch(&part));
+  HT(launch_farfield(Jhist, nsteps, c->nx, c->ny, c->nz, g, j0, nj, part, e, energy, c->stream));
+  return MOT_OK;
+}
+
 int mot_farfield_adjoint(mot_ctx* c, const double* w, int32_t j0, int32_t nj, const double* rhat, double scale,
                          int64_t n, double* g_n) {
   if (!c || !w || !g_n || nj < 1 || n < 0) return MOT_EINVAL;

@@ -156,6 +156,12 @@ struct FarGeom {
 // e[nj][3] = far-field samples j0 .. j0+nj-1 of Jhist[nsteps][3N] and, if W is
 // not null, W[0] = dt sum_j |e_j|^2; partials: scratch of farfield_partials(N, nj) doubles.
 size_t farfield_partials(long long N, int nj);
+// Largest nj of the allocation-free far field (mot_farfield_static): its
+// partials live in a static device array of FF_NJ_MAX * 256 * 3 doubles (6 MiB).
+constexpr int FF_NJ_MAX = 1024;
+// This device's copy of that array (resolved once per device on first use;
+// the calling thread's current device).
+hipError_t farfield_scratch(double** p);
 hipError_t launch_farfield(const double* Jhist, int nsteps, int nx, int ny, int nz, const FarGeom& g, int j0, int nj,
                            double* partials, double* e, double* W, hipStream_t s);
 // g_n[3N] = scale * (transpose of the far field applied to the weights w[nj][3]), step n.

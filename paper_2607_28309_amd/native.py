@@ -31,6 +31,7 @@ EXPORTS = (
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
     "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor", "mot_set_regularization",
+    "mot_farfield_static",
 )
 TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
 PROF_NCLASS = 22
@@ -94,6 +95,7 @@ def _load():
         "z0t_matvec": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
         "mot_history_gfield": (ctypes.c_int, [vp, vp]),
         "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
+        "mot_farfield_static": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
         "mot_farfield_adjoint": (ctypes.c_int, [vp, vp, i32, i32, ctypes.POINTER(dbl), dbl, i64, vp]),
         "mot_adjoint_gradient": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp, vp, vp, vp, vp, vp]),
         "mot_set_variants": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
@@ -308,6 +310,16 @@ class Context:
         en = _ptr(energy, torch.float64, 1) if energy is not None else None
         self._check(LIB.mot_farfield(self.h, _ptr(Jhist, torch.float64, nsteps * 3 * self.N), int(nsteps), r,
                                      int(j0), int(nj), _ptr(e, torch.float64, 3 * int(nj)), en), "mot_farfield")
+
+    def farfield_static(self, Jhist, rhat, j0, nj, e, energy=None):
+        """mot_farfield without any device allocation (partials in the library's static array)."""
+        import torch
+        nsteps = Jhist.numel() // (3 * self.N)
+        r = (ctypes.c_double * 3)(*[float(v) for v in rhat])
+        en = _ptr(energy, torch.float64, 1) if energy is not None else None
+        self._check(LIB.mot_farfield_static(self.h, _ptr(Jhist, torch.float64, nsteps * 3 * self.N), int(nsteps),
+                                            r, int(j0), int(nj), _ptr(e, torch.float64, 3 * int(nj)), en),
+                    "mot_farfield_static")
 
     def farfield_adjoint(self, w, j0, rhat, n, g_n, scale=1.0):
         import torch
