@@ -62,40 +62,62 @@ def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid, blk=1):
 
 def cpu_baseline(w, eps, mv_per_step, nl, log_fn):
     """The FP64 oracle's MOT step rate at the benchmark size, from a bounded
-    sample: two oracle Z0 products, one spectral lag multiply-accumulate and
-    the transforms of one step, each timed once.  A step of the oracle's march
-    is mv_per_step Z0 products (the count the GPU run measured) plus nl lag
-    multiply-accumulates, one inverse and one forward transform of the
-    history (oracle.march.Mot.step)."""
+    sample (a whole oracle step at this size needs its ell = 52 history
+    spectra in complex FP64, about 100 GB of host memory, so it is not run):
+    two oracle Z0 products, one spectral lag multiply-accumulate and the two
+    transforms of one step, each timed once, first with the oracle's
+    transforms on one thread, then on every host core (scipy.fft workers).  A
+    step of the oracle's march is mv_per_step Z0 products (the count the GPU
+    run measured) plus nl lag multiply-accumulates, one inverse and one
+    forward transform of the history (oracle.march.Mot.step)."""
     import numpy as np
+    import scipy.fft
     import workloads as W
     from oracle import green, march
     log_fn("cpu baseline: oracle spectra of G_0 (untimed set-up)")
     g0 = green.green_octant(*w.n, 0, alpha=w.alpha)
     mot = march.Mot(eps, [g0], w.alpha / math.sqrt(3.0))
     J = W.random_current(w.n, seed=1)
-    log_fn("cpu baseline: timing the oracle sample")
-    t = time.perf_counter()
-    mot.z0(J)
-    mot.z0(J)
-    t_z0 = (time.perf_counter() - t) / 2
-    t = time.perf_counter()
-    Jh = mot._spec(J)
-    t_spec = time.perf_counter() - t
-    t = time.perf_counter()
-    S = mot._apply_spec(mot.lams[0], Jh)
-    t_mac = time.perf_counter() - t
-    t = time.perf_counter()
-    mot._back(S)
-    t_back = time.perf_counter() - t
-    t_step = mv_per_step * t_z0 + nl * t_mac + t_back + t_spec
-    sample_s = 2 * t_z0 + t_spec + t_mac + t_back
-    return {"value": 1.0 / t_step, "unit": "MOT steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 (NumPy, one thread) at {w.n[0]}x{w.n[1]}x{w.n[2]}: 2 Z0 products "
-                      f"({t_z0:.2f} s each), one lag multiply-accumulate ({t_mac:.2f} s), forward and inverse "
-                      f"transforms ({t_spec:.2f} s, {t_back:.2f} s), {sample_s:.1f} s in all; a step = "
-                      f"{mv_per_step:.1f} Z0 products + {nl} lag MACs + 2 transforms = {t_step:.0f} s",
-            "z0_matvecs_per_s": 1.0 / t_z0, "cpu": _cpu_name()}
+    cores = os.cpu_count() or 1
+
+    def sample(workers):
+        with scipy.fft.set_workers(workers):
+            t = time.perf_counter()
+            mot.z0(J)
+            mot.z0(J)
+            t_z0 = (time.perf_counter() - t) / 2
+            t = time.perf_counter()
+            Jh = mot._spec(J)
+            t_spec = time.perf_counter() - t
+            t = time.perf_counter()
+            S = mot._apply_spec(mot.lams[0], Jh)
+            t_mac = time.perf_counter() - t
+            t = time.perf_counter()
+            mot._back(S)
+            t_back = time.perf_counter() - t
+        t_step = mv_per_step * t_z0 + nl * t_mac + t_back + t_spec
+        return {"z0_s": t_z0, "mac_s": t_mac, "fwd_s": t_spec, "inv_s": t_back, "step_s": t_step,
+                "sample_s": 2 * t_z0 + t_spec + t_mac + t_back}
+
+    log_fn("cpu baseline: timing the oracle sample on one thread")
+    one = sample(1)
+    log_fn(f"cpu baseline: timing the oracle sample with {cores} FFT workers")
+    many = sample(cores)
+    best = many if many["step_s"] < one["step_s"] else one
+
+    def text(r, th):
+        return (f"{th}: 2 Z0 products ({r['z0_s']:.2f} s each), one lag multiply-accumulate ({r['mac_s']:.2f} s), "
+                f"forward and inverse transforms ({r['fwd_s']:.2f} s, {r['inv_s']:.2f} s), {r['sample_s']:.1f} s "
+                f"in all; scaled to a step = {mv_per_step:.1f} Z0 products + {nl} lag MACs + 2 transforms = "
+                f"{r['step_s']:.0f} s")
+    return {"value": 1.0 / best["step_s"], "unit": "MOT steps/s", "cores": cores if best is many else 1,
+            "kind": "oracle",
+            "sample": f"oracle FP64 (NumPy/SciPy) at {w.n[0]}x{w.n[1]}x{w.n[2]}, a scaled sample, not a whole "
+                      f"step; " + text(one, "one thread") + "; " + text(many, f"{cores} FFT workers")
+                      + "; the lag multiply-accumulate is NumPy elementwise work on one thread in both",
+            "single_thread": {"value": 1.0 / one["step_s"], "z0_matvecs_per_s": 1.0 / one["z0_s"]},
+            "all_cores": {"value": 1.0 / many["step_s"], "z0_matvecs_per_s": 1.0 / many["z0_s"], "workers": cores},
+            "z0_matvecs_per_s": 1.0 / best["z0_s"], "cpu": _cpu_name(), "host_cpu_count": cores}
 
 
 def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
@@ -103,12 +125,14 @@ def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
     same state: steps/s over its last f64_steps steps, and the field error of
     the main run, max_n |J_n - J64_n| / max_n |J64_n| over the kept steps."""
     import torch
+    import workloads as W
     from paper_2607_28309_amd import native
     n = w.n
     N = n[0] * n[1] * n[2]
     c = native.Context(*n, alpha=w.alpha, precision="f64")
     c.set_material(torch.from_numpy(eps.ravel()).cuda())
     c.build_green_spectra()
+    c.set_regularization(W.delta_for(w.alpha))
     if not args.no_autotune:
         c.autotune()
     nl = c.info()["nlags"]
@@ -157,6 +181,7 @@ def batch_leg(args, log_fn):
         c = native.Context(*s_.n, alpha=alpha, precision=args.precision, stream=torch.cuda.Stream())
         c.set_material(torch.from_numpy(s_.eps.ravel()).cuda())
         c.build_green_spectra()
+        c.set_regularization(W.delta_for(alpha))
         if not args.no_autotune:
             c.autotune(reps=5)
         c.reset()
@@ -205,6 +230,63 @@ def batch_leg(args, log_fn):
     return res
 
 
+def _trace_march(args, name, eps_full_cut, ppw, log_fn):
+    """The march of the workload of a stored oracle trace (tests/golden/
+    oracle_trace_<name>.npz: the oracle's FP64 march from t = 0, TFQMR to
+    1e-10) in the benchmark's precision: max_n ||J_n - J_n^ref|| /
+    max_n ||J_n^ref|| on the trace's sampled voxels, and the largest relative
+    difference of the full norms ||J_n||."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2607_28309_amd import native
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_trace_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        tr = {k: z[k] for k in z.files}
+    nx, ny, nz = (int(v) for v in tr["shape"])
+    alpha, steps = int(tr["alpha"]), int(tr["steps"])
+    eps = np.ascontiguousarray(eps_full_cut)
+    c = native.Context(nx, ny, nz, alpha=alpha, precision=args.precision)
+    c.set_material(torch.from_numpy(eps.ravel()).cuda())
+    c.build_green_spectra()
+    c.set_regularization(float(tr["delta"]))
+    c.reset()
+    p = W.pulse(ppw)
+    L = alpha / math.sqrt(3.0)
+    N3 = 3 * nx * ny * nz
+    einc = torch.empty(N3, dtype=torch.float64, device="cuda")
+    J = torch.empty(N3, dtype=torch.float64, device="cuda")
+    idx = torch.from_numpy(tr["idx"].astype(np.int64)).cuda()
+    ref = torch.from_numpy(tr["samples"]).cuda()
+    num = den = nerr = 0.0
+    for s in range(steps):
+        c.excitation(p, s * L, einc)
+        c.step(einc, J, tol=args.tol, stats=False)
+        sub = J.view(3, -1)[:, idx]
+        num = max(num, float(torch.linalg.vector_norm(sub - ref[s])))
+        den = max(den, float(torch.linalg.vector_norm(ref[s])))
+        nerr = max(nerr, abs(float(torch.linalg.vector_norm(J)) - float(tr["norms"][s])))
+    c.close()
+    res = {"value": num / den, "norms": nerr / float(tr["norms"].max()), "grid": [nx, ny, nz], "alpha": alpha,
+           "steps": steps, "samples": int(len(tr["idx"])), "precision": args.precision, "tol": args.tol,
+           "delta": float(tr["delta"])}
+    log_fn(f"field error vs the FP64 oracle, {name} ({nx}x{ny}x{nz}, alpha {alpha}, {steps} steps): "
+           f"{res['value']:.2e} (sampled voxels), {res['norms']:.2e} (norms)")
+    return res
+
+
+def oracle_trace_leg(args, log_fn):
+    """Field error against the FP64 oracle on a 2x2-pillar cut (80 x 80 x 48)
+    of the benchmarked array, dt = 16 dt_CFL, 120 steps from t = 0."""
+    import workloads as W
+    res = _trace_march(args, "pillars80", W.PILLARS.eps()[:, :80, :80], W.PILLARS.ppw, log_fn)
+    if res is not None:
+        res["workload"] = "pillars2x2_80x80x48_a16"
+    return res
+
+
 # a march whose current passes this magnitude has left the physical range (the
 # incident field and the currents it drives are of order one) and is stopped
 GROWTH_LIMIT = 1e6
@@ -240,6 +322,7 @@ def sweep_leg(args, log_fn):
         c = native.Context(*n, alpha=alpha, precision=args.precision)
         c.set_material(eps)
         c.build_green_spectra()
+        c.set_regularization(W.delta_for(alpha))
         if not args.no_autotune:
             c.autotune(reps=5)
         c.reset()
@@ -275,7 +358,8 @@ def sweep_leg(args, log_fn):
         # bounded: ran the whole window and the last quarter stays below the
         # peak of the earlier ones (ringing after the pulse, no growth)
         bounded = diverged is None and len(quarters) == 4 and quarters[-1] <= max(quarters[:3])
-        row = {"alpha": alpha, "steps": steps, "steps_done": done, "diverged_at_step": diverged,
+        row = {"alpha": alpha, "delta": W.delta_for(alpha), "steps": steps, "steps_done": done,
+               "diverged_at_step": diverged,
                "bounded": bounded, "max_abs_J_per_quarter": quarters,
                "nlags": info["nlags"], "z0_nnz": native.zk_nnz(*n, k=0, alpha=alpha),
                "history_block": info["history_block"], "device_bytes": info["bytes"], "setup_s": setup,
@@ -309,6 +393,10 @@ def sweep_leg(args, log_fn):
             h = min(m, len(ref) // 2)   # first half of the window: the pulse itself, before the ringing
             row["probe_diff_vs_ref_first_half"] = (max(abs(a - b) for a, b in zip(pr[:h], ref[:h])) /
                                                    (max(abs(v) for v in ref[:h]) or 1.0)) if h else None
+    # the same sweep on a 24^3 cut of this medium against the FP64 oracle
+    cut = w.eps()[24:48, 24:48, 24:48]
+    for row in rows:
+        row["cut24_field_err_vs_oracle"] = _trace_march(args, f"nested24_a{row['alpha']}", cut, w.ppw, log_fn)
     return {"workload": "nested_cube_96x96x96_fixed_window", "precision": args.precision,
             "tol": args.tol, "window_dt_cfl": args.sweep_window, "probe": "J_x at voxel (48, 48, 48)",
             "probe_ref_alpha": a0, "rows": rows}
@@ -363,8 +451,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
     ap.add_argument("--graphs", action="store_true", help="replay TFQMR iterations from HIP graphs")
-    ap.add_argument("--batch", action="store_true",
-                    help="also time a batch of 32 independent cubes (sides 24..80, alpha 4) stepped together")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch of 32 independent cubes (sides 24..80, alpha 4) stepped together")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--sweep", action="store_true",
                     help="also run the time-step sweep on the 96^3 nested cube (alpha 1..16, one physical window)")
@@ -411,6 +499,7 @@ def main():
     ctx.set_material(torch.from_numpy(eps.ravel()).cuda())
     log(f"context: {ctx.info()}")
     imag = ctx.build_green_spectra()
+    ctx.set_regularization(W.delta_for(w.alpha))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = ctx.info()
@@ -553,7 +642,8 @@ def main():
         "dtype": "f32" if args.precision != "f64" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(n), "unknowns": 3 * N, "alpha": w.alpha, "nlags": nl,
-                   "precision": args.precision, "tol": args.tol, "parallelism": "single GPU"},
+                   "delta": W.delta_for(w.alpha), "precision": args.precision, "tol": args.tol,
+                   "parallelism": "single GPU"},
         "z0_matvecs_per_s": {k: v["per_s"] for k, v in mv.items()},
         "z0_matvec_ms": {k: v["ms"] for k, v in mv.items()},
         "z0_pipeline_gbs_f32": pipe_bytes / (mv["f32"]["ms"] / 1e3) / 1e9,
@@ -573,7 +663,8 @@ def main():
     del ctx
     if args.f64_steps > 0:
         out.update(f64_march(args, w, eps, p, L, Js, n_keep, log))
-    if args.batch:
+    out["field_err_vs_oracle"] = oracle_trace_leg(args, log)
+    if not args.no_batch:
         out["batch"] = batch_leg(args, log)
     if args.sweep:
         out["sweep"] = sweep_leg(args, log)

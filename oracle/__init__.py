@@ -24,6 +24,9 @@ Volume Integral Equation for Dielectric Scattering"):
                    the time-reversed adjoint march and the gradient of the
                    energy with respect to eps_r.
 
+Transforms use ``scipy.fft`` (one thread by default; a caller may lend it
+more with ``scipy.fft.set_workers``, which changes nothing but the speed).
+
 Parity status of each function is stated in its docstring; every function is
 pinned by ``tests/test_oracle_*.py`` against values the paper prints, closed
 forms or invariants, unless it says "parity unpinned".

@@ -25,6 +25,7 @@ that each current is transformed once.
 import math
 
 import numpy as np
+import scipy.fft as sfft
 
 from .krylov import tfqmr
 from .operators import PAIR, embed_spectra
@@ -72,7 +73,7 @@ class Mot:
         self.n = 0
 
     def _spec(self, J):
-        return np.stack([np.fft.fftn(J[q], s=self.P, axes=(0, 1, 2)) for q in range(3)])
+        return np.stack([sfft.fftn(J[q], s=self.P, axes=(0, 1, 2)) for q in range(3)])
 
     def _apply_spec(self, lam, Jh):
         out = np.zeros((3,) + self.P, dtype=np.complex128)
@@ -82,7 +83,7 @@ class Mot:
         return out
 
     def _back(self, S):
-        return np.stack([np.fft.ifftn(S[p]).real[:self.nz, :self.ny, :self.nx] for p in range(3)])
+        return np.stack([sfft.ifftn(S[p]).real[:self.nz, :self.ny, :self.nx] for p in range(3)])
 
     def z0(self, J):
         """Z0 J (Eq. 12)."""

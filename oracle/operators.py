@@ -24,6 +24,7 @@ Vectors are laid out [3][nz][ny][nx] (component, then z, y, x; x fastest).
 """
 
 import numpy as np
+import scipy.fft as sfft
 
 from .green import PAIR, green_full
 
@@ -92,7 +93,7 @@ def embed_spectra(g_oct):
     for c, (p, q) in enumerate(PAIR):
         e = np.zeros(P)
         e[np.ix_(iz, iy, ix)] = full[p, q]
-        f = np.fft.fftn(e)
+        f = sfft.fftn(e)
         imag = max(imag, float(np.abs(f.imag).max()))
         lam[c] = f.real
     return lam, imag
@@ -104,14 +105,14 @@ def gconv_fft(g_oct, J, lam=None):
     if lam is None:
         lam, _ = embed_spectra(g_oct)
     P = lam.shape[1:]
-    Jh = [np.fft.fftn(J[q], s=P, axes=(0, 1, 2)) for q in range(3)]
+    Jh = [sfft.fftn(J[q], s=P, axes=(0, 1, 2)) for q in range(3)]
     out = np.zeros(J.shape)
     for p in range(3):
         acc = np.zeros(P, dtype=np.complex128)
         for q in range(3):
             c = PAIR.index((min(p, q), max(p, q)))
             acc += lam[c] * Jh[q]
-        out[p] = np.fft.ifftn(acc).real[:nz, :ny, :nx]
+        out[p] = sfft.ifftn(acc).real[:nz, :ny, :nx]
     return out
 
 

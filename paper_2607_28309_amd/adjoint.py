@@ -59,13 +59,17 @@ class FarFieldMarch:
         self.Jhist = None
         self.UH = None
         self.e = None
+        self.eps = None
+        self.generation = 0   # forward marches run so far; the recorded state is that of the last
 
     def forward(self, eps):
         """Run the march for permittivity eps; returns W (a Python float)."""
         c = self.ctx
         n3 = 3 * c.N
         dev = eps.device
-        c.set_material(eps.detach().contiguous())
+        self.eps = eps.detach().contiguous().clone()
+        self.generation += 1
+        c.set_material(self.eps)
         c.set_adjoint(False)
         c.reset()
         self.Jhist = torch.empty((self.nsteps, n3), dtype=torch.float64, device=dev)
@@ -87,6 +91,8 @@ class FarFieldMarch:
         c = self.ctx
         n3 = 3 * c.N
         dev = self.e.device
+        # the adjoint operators use the material of the recorded march
+        c.set_material(self.eps)
         g = torch.empty(n3, dtype=torch.float64, device=dev)
         lam = torch.empty(n3, dtype=torch.float64, device=dev)
         u0 = torch.empty(n3, dtype=torch.float64, device=dev)
@@ -113,11 +119,19 @@ class FarFieldEnergy(torch.autograd.Function):
     def forward(fctx, eps, march):
         W = march.forward(eps)
         fctx.march = march
+        fctx.generation = march.generation
+        fctx.eps = march.eps
         return torch.tensor(W, dtype=torch.float64, device=eps.device)
 
     @staticmethod
     def backward(fctx, grad_out):
-        return grad_out * fctx.march.gradient(), None
+        m = fctx.march
+        if m.generation != fctx.generation:
+            # another forward ran on this march since this node's: the recorded
+            # currents are not this node's, so march again from its permittivity
+            m.forward(fctx.eps)
+            fctx.generation = m.generation
+        return grad_out * m.gradient(), None
 
 
 def far_field_energy(eps, march):

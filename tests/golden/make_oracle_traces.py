@@ -11,11 +11,13 @@ per-step norm ||J_n||, the sampled voxel indices (flat, [z][y][x]) and J_n at
 those voxels for every step, shape (steps, 3, nsamples).
 """
 
+import concurrent.futures
 import os
 import sys
 import time
 
 import numpy as np
+import scipy.fft
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -32,6 +34,17 @@ CASES = {
     "pillars80": dict(eps=lambda: np.ascontiguousarray(W.PILLARS.eps()[:, :80, :80]), alpha=16, steps=120,
                       ppw=W.PILLARS.ppw, nsamples=192, seed=12),
 }
+# a 24^3 cut (indices 24..47 on every axis: the eps_r = 6 core and the 4 layer)
+# of the 96^3 nested cube of the time-step sweep, over the sweep's window of
+# 1600 dt_CFL for each alpha
+for _a in (1, 2, 4, 8, 16):
+    CASES[f"nested24_a{_a}"] = dict(eps=lambda: np.ascontiguousarray(W.CUBE96.eps()[24:48, 24:48, 24:48]),
+                                    alpha=_a, steps=1600 // _a, ppw=W.CUBE96.ppw, nsamples=16, seed=13)
+
+
+def _octant(a):
+    nx, ny, nz, k, alpha = a
+    return green.green_octant(nx, ny, nz, k, alpha=alpha)
 
 
 def path(name):
@@ -47,7 +60,9 @@ def make(name):
     L = basis.cdt_from_alpha(alpha)
     nl = basis.nlags(nx, ny, nz, alpha=alpha)
     t0 = time.time()
-    G = green.green_all(nx, ny, nz, nl, alpha=alpha)
+    # the lags' tables are independent: one process per lag
+    with concurrent.futures.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        G = list(ex.map(_octant, [(nx, ny, nz, k, alpha) for k in range(nl + 1)]))
     print(f"{name}: {nx}x{ny}x{nz}, alpha {alpha}, ell {nl}, delta {delta}: Green {time.time() - t0:.0f}s", flush=True)
     rng = np.random.default_rng(cs["seed"])
     mat = np.flatnonzero(eps.ravel() != 1.0)
@@ -56,7 +71,8 @@ def make(name):
     mot = march.Mot(eps, G, L, delta=delta)
     norms, samp = [], []
     for s in range(cs["steps"]):
-        J, res = mot.step(march.dt_einc(p, eps, s * L), tol=1e-10)
+        with scipy.fft.set_workers(os.cpu_count() or 1):
+            J, res = mot.step(march.dt_einc(p, eps, s * L), tol=1e-10)
         norms.append(np.linalg.norm(J))
         samp.append(J.reshape(3, -1)[:, idx])
         if s % 10 == 0:

@@ -167,3 +167,32 @@ def test_gradient_vs_oracle_fd_and_autograd(gpu_lib):
         em[idx] -= h
         fd = (march.forward(_t(ep.ravel())) - march.forward(_t(em.ravel()))) / (2 * h)
         assert abs(fd - grad[idx]) <= 1e-5 * np.abs(grad).max(), (idx, fd, grad[idx])
+
+
+def test_gradient_regularized_and_two_forwards(gpu_lib):
+    # with the regularized operators (delta = 0.05) the adjoint gradient
+    # matches the oracle's; and a graph node whose march was overwritten by
+    # a later forward (another permittivity) still returns its own gradient
+    import torch
+    from paper_2607_28309_amd import adjoint as A
+    n, alpha, nt, delta = (8, 4, 4), 2, 12, 0.05
+    eps = _eps(n, 111)
+    eps2 = eps * 1.1
+    c = _ctx(gpu_lib, n, alpha, eps)
+    c.set_regularization(delta)
+    rhat = [0.0, 0.6, 0.8]
+    march = A.FarFieldMarch(c, PULSE, nt, rhat, tol=1e-11)
+    e1 = _t(eps.ravel()).requires_grad_(True)
+    e2 = _t(eps2.ravel()).requires_grad_(True)
+    W1 = A.far_field_energy(e1, march)
+    W2 = A.far_field_energy(e2, march)      # overwrites the recorded march of W1
+    W1.backward()
+    W2.backward()
+    dt = basis.cdt_from_alpha(alpha)
+    greens = green.green_all(*n, march.nlags, alpha=alpha)
+    for e_t, ep, Wt in ((e1, eps, W1), (e2, eps2, W2)):
+        W_ref, g_ref = OA.gradient(ep, greens, dt, PULSE, nt, np.asarray(rhat) / np.linalg.norm(rhat),
+                                   march.j0, march.nj, tol=1e-12, delta=delta)
+        assert abs(float(Wt.item()) - W_ref) <= 1e-8 * W_ref
+        got = _np(e_t.grad).reshape(eps.shape)
+        assert np.abs(got - g_ref).max() <= 1e-6 * np.abs(g_ref).max()

@@ -10,7 +10,7 @@ The regularization delta_0 = +delta eps_r, delta_1 = -delta eps_r damps that
 pattern.  These tests pin (i) the march against the companion matrix of the
 dense Z_k (the same recurrence, assembled from ``operators.z0_dense``), (ii)
 the single-voxel recurrence in closed form with delta, and (iii) boundedness
-of long regularized marches with delta = 0.1 dt_CFL/dt.
+of long regularized marches with the per-alpha delta of the workloads.
 """
 
 import math
@@ -106,13 +106,13 @@ def test_single_voxel_recurrence_with_delta(alpha, eps_r, delta):
 @pytest.mark.parametrize("alpha", [1, 2, 4, 8, 16])
 def test_regularized_march_bounded_1500_steps(alpha, eps_r):
     # the cube of the time-step study at 8^3, x-polarized pulse along +z,
-    # tol 1e-6 (Sec. V-A); delta = 0.1 dt_CFL / dt
+    # tol 1e-6 (Sec. V-A); delta from the workloads' table
     n = (8, 8, 8)
     L = basis.cdt_from_alpha(alpha)
     nl = basis.nlags(*n, alpha=alpha)
     eps = W.eps_uniform(n, eps_r)
     p = W.pulse(20)
-    mot = march.Mot(eps, green.green_all(*n, nl, alpha=alpha), L, delta=0.1 / alpha)
+    mot = march.Mot(eps, green.green_all(*n, nl, alpha=alpha), L, delta=W.delta_for(alpha))
     norms = np.array([np.linalg.norm(mot.step(march.dt_einc(p, eps, s * L), tol=1e-6)[0])
                       for s in range(1500)])
     assert np.all(np.isfinite(norms))
