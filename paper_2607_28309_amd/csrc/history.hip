@@ -40,12 +40,21 @@ struct Point {
   int a[NM], b[NM];
 };
 
+//
+// Frequencies are numbered along the padded rows (kx < kxs, the storage
+// layout of the spectra and of Lambda), so that every wave reads whole
+// 128-byte lines: a wave's frequencies start at a multiple of its width in
+// that numbering.  Numbered along the used kx < nx + 1 instead, waves start
+// anywhere in a row and the lines they share with the neighbouring
+// workgroup, read at another time, are fetched from HBM twice.  The threads
+// of the padding columns kx > nx return at once.
 template <int NM>
 __device__ __forceinline__ bool octant_point(const Geo& g, long long id, int side, size_t& lo, Point<NM>& pt) {
-  const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+  const long long cnt = (long long)g.kxs * (g.ny + 1) * (g.nz + 1);
   if (id >= cnt) return false;
-  const int kx = (int)(id % (g.nx + 1)), kyc = (int)((id / (g.nx + 1)) % (g.ny + 1)),
-            kzc = (int)(id / ((long long)(g.nx + 1) * (g.ny + 1)));
+  const int kx = (int)(id % g.kxs), kyc = (int)((id / g.kxs) % (g.ny + 1)),
+            kzc = (int)(id / ((long long)g.kxs * (g.ny + 1)));
+  if (kx > g.nx) return false;
   const int py = 2 * g.ny, pz = 2 * g.nz;
   const size_t plane = (size_t)py * g.kxs;
   lo = ((size_t)kzc * (g.ny + 1) + kyc) * g.kxs + kx;
@@ -243,10 +252,9 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
   }
 }
 
-static inline dim3 mac_grid(const Geo& g) {
-  const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
-  return dim3((unsigned)((cnt + 255) / 256));
-}
+static inline long long mac_count(const Geo& g) { return (long long)g.kxs * (g.ny + 1) * (g.nz + 1); }
+
+static inline dim3 mac_grid(const Geo& g) { return dim3((unsigned)((mac_count(g) + 255) / 256)); }
 
 hipError_t launch_mac_recent(const void* ring, const void* lamh, const void* init, void* out, int f64, int nl,
                              long long n, int nrec, int nx, int ny, int nz, int kxs, hipStream_t s) {
@@ -264,7 +272,7 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
                             int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s) {
   const Geo g{nx, ny, nz, kxs, nl};
   const dim3 gr = mac_grid(g);
-  const long long cnt = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+  const long long cnt = mac_count(g);
   const dim3 gr2((unsigned)((cnt + 127) / 128));  // two threads per octant frequency
   const dim3 gr4((unsigned)((cnt + 63) / 64));    // four
 #define LB(T, BB, NM, GR)                                                                                 \
