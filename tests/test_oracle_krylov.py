@@ -46,3 +46,11 @@ def test_identity_one_iteration():
     b = np.arange(1.0, 9.0)
     r = krylov.tfqmr(lambda v: 2.0 * v, b, tol=1e-14)
     assert r.iterations == 1 and np.allclose(r.x, b / 2, rtol=1e-15)
+
+
+def test_breakdown_reported():
+    # a skew-symmetric system: sigma = v . r~ = b^T A b = 0 at the first
+    # iteration, which TFQMR cannot pass (the solver's breakdown exit)
+    A = np.array([[0.0, 1.0], [-1.0, 0.0]])
+    res = krylov.tfqmr(lambda v: A @ v, np.array([1.0, 0.0]), tol=1e-12)
+    assert res.breakdown and not res.converged
