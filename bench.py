@@ -132,7 +132,7 @@ def f64_march(args, w, eps, pulse, L, Js, n_keep, log_fn):
     c = native.Context(*n, alpha=w.alpha, precision="f64")
     c.set_material(torch.from_numpy(eps.ravel()).cuda())
     c.build_green_spectra()
-    c.set_regularization(W.delta_for(w.alpha))
+    c.set_regularization(W.regularization_for(w.alpha))
     if not args.no_autotune:
         c.autotune()
     nl = c.info()["nlags"]
@@ -181,7 +181,7 @@ def batch_leg(args, log_fn):
         c = native.Context(*s_.n, alpha=alpha, precision=args.precision, stream=torch.cuda.Stream())
         c.set_material(torch.from_numpy(s_.eps.ravel()).cuda())
         c.build_green_spectra()
-        c.set_regularization(W.delta_for(alpha))
+        c.set_regularization(W.regularization_for(alpha))
         if not args.no_autotune:
             c.autotune(reps=5)
         c.reset()
@@ -251,7 +251,8 @@ def _trace_march(args, name, eps_full_cut, ppw, log_fn):
     c = native.Context(nx, ny, nz, alpha=alpha, precision=args.precision)
     c.set_material(torch.from_numpy(eps.ravel()).cuda())
     c.build_green_spectra()
-    c.set_regularization(float(tr["delta"]))
+    dl = tuple(float(v) for v in np.atleast_1d(tr["delta"]))
+    c.set_regularization(dl if len(dl) == 3 else dl[0])
     c.reset()
     p = W.pulse(ppw)
     L = alpha / math.sqrt(3.0)
@@ -271,7 +272,7 @@ def _trace_march(args, name, eps_full_cut, ppw, log_fn):
     c.close()
     res = {"value": num / den, "norms": nerr / float(tr["norms"].max()), "grid": [nx, ny, nz], "alpha": alpha,
            "steps": steps, "samples": int(len(tr["idx"])), "precision": args.precision, "tol": args.tol,
-           "delta": float(tr["delta"])}
+           "delta": [float(v) for v in np.atleast_1d(tr["delta"])]}
     log_fn(f"field error vs the FP64 oracle, {name} ({nx}x{ny}x{nz}, alpha {alpha}, {steps} steps): "
            f"{res['value']:.2e} (sampled voxels), {res['norms']:.2e} (norms)")
     return res
@@ -322,7 +323,7 @@ def sweep_leg(args, log_fn):
         c = native.Context(*n, alpha=alpha, precision=args.precision)
         c.set_material(eps)
         c.build_green_spectra()
-        c.set_regularization(W.delta_for(alpha))
+        c.set_regularization(W.regularization_for(alpha))
         if not args.no_autotune:
             c.autotune(reps=5)
         c.reset()
@@ -358,7 +359,7 @@ def sweep_leg(args, log_fn):
         # bounded: ran the whole window and the last quarter stays below the
         # peak of the earlier ones (ringing after the pulse, no growth)
         bounded = diverged is None and len(quarters) == 4 and quarters[-1] <= max(quarters[:3])
-        row = {"alpha": alpha, "delta": W.delta_for(alpha), "steps": steps, "steps_done": done,
+        row = {"alpha": alpha, "delta": list(W.regularization_for(alpha)), "steps": steps, "steps_done": done,
                "diverged_at_step": diverged,
                "bounded": bounded, "max_abs_J_per_quarter": quarters,
                "nlags": info["nlags"], "z0_nnz": native.zk_nnz(*n, k=0, alpha=alpha),
@@ -499,7 +500,7 @@ def main():
     ctx.set_material(torch.from_numpy(eps.ravel()).cuda())
     log(f"context: {ctx.info()}")
     imag = ctx.build_green_spectra()
-    ctx.set_regularization(W.delta_for(w.alpha))
+    ctx.set_regularization(W.regularization_for(w.alpha))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = ctx.info()
@@ -642,7 +643,7 @@ def main():
         "dtype": "f32" if args.precision != "f64" else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(n), "unknowns": 3 * N, "alpha": w.alpha, "nlags": nl,
-                   "delta": W.delta_for(w.alpha), "precision": args.precision, "tol": args.tol,
+                   "delta": list(W.regularization_for(w.alpha)), "precision": args.precision, "tol": args.tol,
                    "parallelism": "single GPU"},
         "z0_matvecs_per_s": {k: v["per_s"] for k, v in mv.items()},
         "z0_matvec_ms": {k: v["ms"] for k, v in mv.items()},

@@ -132,7 +132,7 @@ double mot_spectra_imag(const mot_ctx* ctx);
 int mot_set_material(mot_ctx* ctx, const double* eps_r);
 
 /* y = Z0 J (Eq. 12) with the FFT product of Eq. 11 (D = diag(eps_r)(1/2 +
- * delta) with the regularization of mot_set_regularization, delta = 0 by default).
+ * d0) with the regularization of mot_set_regularization, d0 = 0 by default).
  *   dtype MOT_F64:         J, y FP64 device vectors, FP64 transforms;
  *   dtype MOT_F32:         J, y FP32 device vectors, FP32 transforms;
  *   dtype MOT_F32_REFINED: J, y FP64 device vectors, FP32 transforms (the
@@ -148,7 +148,7 @@ int gk_matvec(mot_ctx* ctx, int32_t k, const void* J, void* y, mot_precision dty
 /* Push J_n (FP64 device vector) into the history ring and prepare the
  * history right-hand side of the next step (Eq. 3, Eq. 6 RHS),
  *   h_{n+1} = -sum_{k=1..ell} Z_k J_{n+1-k}
- *           = -(1/2 - delta) eps_r J_n + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
+ *           = -(1/2 + d1) eps_r J_n - d2 eps_r J_{n-1} + (eps_r - 1) sum_{k=1..ell} G_k J_{n+1-k},
  * using the spectra of past currents (each current is transformed once).
  * The spectral sums are blocked in time: every B steps (B = 8, halved while
  * B > ell) one pass over the ring accumulates the contributions of all
@@ -234,17 +234,20 @@ int mot_set_predictor(mot_ctx* ctx, int32_t k);
 
 /* Regularized interaction matrices in the delta-notation of Sec. II
  * (Z^delta_n = Z_n + delta_n I; the paper runs with delta_n = 0).  Here
- * delta_0 = +delta diag(eps_r), delta_1 = -delta diag(eps_r), delta_n = 0 for
- * n >= 2: the constitutive term eps_r J of Eq. 1 is weighted (1/2 + delta,
- * 1/2 - delta) on (J_n, J_{n-1}) instead of the spline's (1/2, 1/2), which
- * damps the current pattern that alternates in sign from step to step (it is
- * invisible to the spline at the testing instants).  Z0 = diag(eps_r)(1/2 +
- * delta) - X G_0 in z0_matvec, mot_step and the adjoint calls; the history
- * right-hand side uses (1/2 - delta) eps_r J_{n-1}.  Default delta = 0 (the
- * paper's operator).  May be called at any time; the next step uses it.
- * Drops captured iteration graphs and the initial-guess pairs.
- * Errors: MOT_EINVAL (NULL, delta outside [0, 1/2)). */
-int mot_set_regularization(mot_ctx* ctx, double delta);
+ * delta_n = d_n diag(eps_r) for n = 0, 1, 2 and 0 beyond: the constitutive
+ * term eps_r J of Eq. 1 is weighted (1/2 + d0, 1/2 + d1, d2) on (J_n,
+ * J_{n-1}, J_{n-2}) instead of the spline's (1/2, 1/2, 0).  With weights
+ * that sum to 1 (d0 + d1 + d2 = 0) the static response is unchanged; a
+ * difference such as (d, -d, 0) or (d/2, -d, d/2) damps the current pattern
+ * that alternates in sign from step to step, which the spline does not see
+ * at the testing instants.  Z0 = diag(eps_r)(1/2 + d0) - X G_0 in z0_matvec,
+ * mot_step and the adjoint calls; the history right-hand side carries
+ * -(1/2 + d1) eps_r J_n - d2 eps_r J_{n-1} (d2 != 0 keeps one more current,
+ * 3N FP64, allocated by this call and zeroed by mot_reset).  Default all
+ * zero (the paper's operator).  May be called at any time; the next step
+ * uses it.  Drops captured iteration graphs and the initial-guess pairs.
+ * Errors: MOT_EINVAL (NULL, a value not finite, 1/2 + d0 <= 0), MOT_ENOMEM. */
+int mot_set_regularization(mot_ctx* ctx, double d0, double d1, double d2);
 
 /* Start a new march of Eq. 3: n = 0, history ring and history right-hand
  * side zeroed (J_{n<0} = 0: the causal start of the recursion). */
@@ -299,8 +302,9 @@ int mot_profile_kinds(mot_ctx* ctx, int32_t kind_mask);
  * r_m the voxel centre relative to the grid centre, T' the derivative of the
  * temporal basis in step units.  For W = dt sum_j |e_j|^2 the adjoint sources
  * are g_n = mot_farfield_adjoint(2 dt e) and
- *   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - (1/2 + delta) J_n(m)
- *                                  - (1/2 - delta) J_{n-1}(m) + u_n(m)),
+ *   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - w0 J_n(m) - w1 J_{n-1}(m)
+ *                                  - w2 J_{n-2}(m) + u_n(m)),
+ * (w0, w1, w2) = (1/2 + d0, 1/2 + d1, d2) with the regularization's d,
  * u_n = sum_{k=0..ell} G_k J_{n-k} = (mot_history_gfield read just before
  * step n) + gk_matvec(0, J_n). */
 
@@ -310,7 +314,7 @@ int mot_profile_kinds(mot_ctx* ctx, int32_t kind_mask);
  * Errors: MOT_EINVAL. */
 int mot_set_adjoint(mot_ctx* ctx, int32_t on);
 
-/* y = Z0^T v = (1/2 + delta) eps_r v - G_0 ((eps_r - 1) v), dtypes as z0_matvec.
+/* y = Z0^T v = (1/2 + d0) eps_r v - G_0 ((eps_r - 1) v), dtypes as z0_matvec.
  * Errors: MOT_EINVAL, MOT_ESTATE, MOT_EHIP. */
 int z0t_matvec(mot_ctx* ctx, const void* v, void* y, mot_precision dtype);
 
@@ -349,15 +353,17 @@ int mot_farfield_static(mot_ctx* ctx, const double* Jhist, int32_t nsteps, const
 int mot_farfield_adjoint(mot_ctx* ctx, const double* w, int32_t j0, int32_t nj, const double* rhat, double scale,
                          int64_t n, double* g_n);
 
-/* grad[m] += sum_p lam_n[p,m] (d_t E^i_p(r_m, t) - (1/2 + delta) J_n[p,m] - (1/2 - delta) J_prev[p,m]
+/* grad[m] += sum_p lam_n[p,m] (d_t E^i_p(r_m, t) - w0 J_n[p,m] - w1 J_prev[p,m] - w2 J_prev2[p,m]
  *                               + uh_n[p,m] + u0_n[p,m])
- * for every voxel m: the step-n term of dW/d eps with u_n = uh_n + u0_n split
- * into its history part (mot_history_gfield before step n) and its present
- * part (gk_matvec(0, J_n)).  FP64 device vectors: lam_n, J_n, J_prev, uh_n,
- * u0_n of 3N, grad of N; J_prev may be NULL for n = 0.
+ * for every voxel m (w as above): the step-n term of dW/d eps with
+ * u_n = uh_n + u0_n split into its history part (mot_history_gfield before
+ * step n) and its present part (gk_matvec(0, J_n)).  FP64 device vectors:
+ * lam_n, J_n, J_prev (J_{n-1}), J_prev2 (J_{n-2}), uh_n, u0_n of 3N, grad of
+ * N; J_prev and J_prev2 may be NULL where the step does not exist.
  * Errors: MOT_EINVAL, MOT_EHIP. */
 int mot_adjoint_gradient(mot_ctx* ctx, const mot_pulse* pulse, double t, const double* lam_n, const double* J_n,
-                         const double* J_prev, const double* uh_n, const double* u0_n, double* grad);
+                         const double* J_prev, const double* J_prev2, const double* uh_n, const double* u0_n,
+                         double* grad);
 
 /* Host helpers (no GPU needed). */
 int32_t mot_nlags(const mot_grid* grid);           /* ell of Eq. 4 (reading above), or < 0 */

@@ -7,8 +7,8 @@ the transpose of Z_k = T(k) diag(eps_r) - diag(eps_r - 1) G_k (Eq. 10 form) is
     Z_k^T = T(k) diag(eps_r) - G_k diag(eps_r - 1):
 the contrast acts on the input.  In particular
     Z0^T v = (eps_r/2) v - G_0 ((eps_r - 1) v).
-With the regularization of ``operators`` the diagonal weights 1/2 of Z0 and
-Z1 become 1/2 + delta and 1/2 - delta (they are diagonal, so the transpose
+With the regularization of ``operators`` the local weights of Z0, Z1, Z2
+become (w0, w1, w2) = (1/2 + d_0, 1/2 + d_1, d_2) (diagonal, so the transpose
 keeps them).
 
 Far field (reading; the paper does not use one).  The current radiates
@@ -27,11 +27,11 @@ system sum_{k=0..ell} Z_k J_{n-k} = E_n, n = 0..Nt-1.  Its transpose,
 sum_k Z_k^T lam_{n+k} = g_n with g_n = dW/dJ_n, is solved backwards in time
 from n = Nt-1 (lam_{n >= Nt} = 0):
     Z0^T lam_n = g_n - (eps_r/2) lam_{n+1} + sum_{k>=1} G_k ((eps_r - 1) lam_{n+k}).
-(with delta: (1/2 + delta) eps_r in Z0^T, (1/2 - delta) eps_r on lam_{n+1}).
+(with the regularization: w0 eps_r in Z0^T, w1 eps_r on lam_{n+1}, w2 eps_r on lam_{n+2}).
 
 Gradient.  E_n = (eps_r - 1) d_t E^i(r_m, t_n) and the Z_k depend on eps_r, so
     dW/d eps_m = sum_n lam_n(m) . [d_t E^i(r_m, t_n) - (J_n(m) + J_{n-1}(m))/2 + u_n(m)],
-(with delta: -(1/2 + delta) J_n(m) - (1/2 - delta) J_{n-1}(m) in the bracket),
+(with the regularization: -w0 J_n(m) - w1 J_{n-1}(m) - w2 J_{n-2}(m) in the bracket),
     u_n = sum_{k=0..ell} G_k J_{n-k}.
 
 Pins (tests/test_oracle_adjoint.py): the transpose against the dense Z0 and
@@ -47,12 +47,12 @@ import numpy as np
 
 from .krylov import tfqmr
 from .march import Mot, dt_einc, voxel_centres
-from .operators import gconv_fft
+from .operators import gconv_fft, reg_weights
 
 
 def z0t_apply(g0_oct, eps, v, lam=None, delta=0.0):
-    """Z0^T v = (1/2 + delta) eps_r v - G_0 ((eps_r - 1) v); v shape (3, nz, ny, nx)."""
-    return (0.5 + delta) * eps[None] * v - gconv_fft(g0_oct, (eps[None] - 1.0) * v, lam=lam)
+    """Z0^T v = w0 eps_r v - G_0 ((eps_r - 1) v); v shape (3, nz, ny, nx)."""
+    return reg_weights(delta)[0] * eps[None] * v - gconv_fft(g0_oct, (eps[None] - 1.0) * v, lam=lam)
 
 
 def dspline(s):
@@ -148,7 +148,9 @@ def adjoint_march(eps, greens, g, tol=1e-12, max_iter=1000, delta=0.0):
     for n in range(nt - 1, -1, -1):
         rhs = g[n].copy()
         if n + 1 < nt:
-            rhs -= (0.5 - delta) * eps[None] * lam[n + 1]
+            rhs -= reg_weights(delta)[1] * eps[None] * lam[n + 1]
+        if n + 2 < nt:
+            rhs -= reg_weights(delta)[2] * eps[None] * lam[n + 2]
         for k in range(1, nl + 1):
             if n + k < nt:
                 rhs += gconv_fft(greens[k], (eps[None] - 1.0) * lam[n + k])
@@ -180,8 +182,11 @@ def gradient(eps, greens, dt, pulse, nsteps, rhat, j0, nj, tol=1e-12, delta=0.0)
     grad = np.zeros(eps.shape)
     for n in range(nsteps):
         q = incident_dt(pulse, eps.shape, n * dt) + gfield(greens, J, n)
-        q -= (0.5 + delta) * J[n]
+        w = reg_weights(delta)
+        q -= w[0] * J[n]
         if n > 0:
-            q -= (0.5 - delta) * J[n - 1]
+            q -= w[1] * J[n - 1]
+        if n > 1:
+            q -= w[2] * J[n - 2]
         grad += np.sum(lam[n] * q, axis=0)
     return W, grad

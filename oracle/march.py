@@ -14,9 +14,9 @@ MOT recursion (Eq. 3, Eq. 6):
     Z_k    = T(k) diag(eps_r) - diag(eps_r - 1) G_k,
 so with T(1) = 1/2 and T(k >= 2) = 0 the history term is
     sum_{k>=1} Z_k J_{n-k} = (eps_r/2) J_{n-1} - (eps_r - 1) sum_{k>=1} G_k * J_{n-k}.
-With the regularization of ``operators`` (delta_0 = +delta eps_r,
-delta_1 = -delta eps_r) the local weights become (1/2 + delta) on J_n in Z0
-and (1/2 - delta) on J_{n-1} in the history term.
+With the regularization of ``operators`` the local weights become
+(w0, w1, w2) = (1/2 + d_0, 1/2 + d_1, d_2): w0 on J_n in Z0, and w1, w2 on
+J_{n-1}, J_{n-2} in the history term.
 Each Z0 system is solved by ``krylov.tfqmr``; each Green convolution uses the
 FFT form of Eq. 11 (``operators``), with the spectra of past currents kept so
 that each current is transformed once.
@@ -28,7 +28,7 @@ import numpy as np
 import scipy.fft as sfft
 
 from .krylov import tfqmr
-from .operators import PAIR, embed_spectra
+from .operators import PAIR, embed_spectra, reg_weights
 
 
 def voxel_centres(nx, ny, nz):
@@ -62,7 +62,7 @@ class Mot:
 
     def __init__(self, eps, greens, cdt, delta=0.0):
         self.eps = np.asarray(eps, dtype=np.float64)
-        self.delta = float(delta)
+        self.w = reg_weights(delta)
         self.nz, self.ny, self.nx = self.eps.shape
         self.cdt = float(cdt)
         self.nl = len(greens) - 1
@@ -70,6 +70,7 @@ class Mot:
         self.P = self.lams[0].shape[1:]
         self.hist = []          # spectra of J_{n-1}, J_{n-2}, ... (newest first)
         self.jprev = np.zeros((3, self.nz, self.ny, self.nx))
+        self.jprev2 = np.zeros((3, self.nz, self.ny, self.nx))
         self.n = 0
 
     def _spec(self, J):
@@ -88,7 +89,7 @@ class Mot:
     def z0(self, J):
         """Z0 J (Eq. 12)."""
         gj = self._back(self._apply_spec(self.lams[0], self._spec(J)))
-        return (0.5 + self.delta) * self.eps[None] * J - (self.eps[None] - 1.0) * gj
+        return self.w[0] * self.eps[None] * J - (self.eps[None] - 1.0) * gj
 
     def history_rhs(self):
         """-sum_{k>=1} Z_k J_{n-k} for the current n."""
@@ -97,7 +98,8 @@ class Mot:
             if k - 1 < len(self.hist):
                 S += self._apply_spec(self.lams[k], self.hist[k - 1])
         h = self._back(S)
-        return -(0.5 - self.delta) * self.eps[None] * self.jprev + (self.eps[None] - 1.0) * h
+        return (-self.eps[None] * (self.w[1] * self.jprev + self.w[2] * self.jprev2)
+                + (self.eps[None] - 1.0) * h)
 
     def step(self, einc, tol=1e-6, max_iter=1000):
         """One MOT step: returns (J_n, TfqmrResult)."""
@@ -108,6 +110,7 @@ class Mot:
         J = res.x.reshape(shape)
         self.hist.insert(0, self._spec(J))
         del self.hist[self.nl:]
+        self.jprev2 = self.jprev
         self.jprev = J
         self.n += 1
         return J, res

@@ -6,11 +6,12 @@ tested at t_n, where the spline basis gives J(t_n) = (J_n + J_{n-1})/2).
 
 Regularization (Sec. II, the delta-notation Z^delta_n = Z_n + delta_n I of
 the regularized MOT formulation the paper cites; the paper itself runs with
-delta_n = 0).  Reading used here: delta_0 = +delta diag(eps_r),
-delta_1 = -delta diag(eps_r), delta_n = 0 for n >= 2, i.e. the constitutive
-term is tested with the weights (1/2 + delta, 1/2 - delta) on (J_n, J_{n-1}).
-delta = 0 (the default everywhere) is the paper's unregularized operator;
-then D = diag(eps_r)(1/2 + delta).
+delta_n = 0).  Reading used here: delta_n = d_n diag(eps_r) for n = 0, 1, 2
+(zero beyond), i.e. the constitutive term eps_r J is tested with the local
+weights (1/2 + d_0, 1/2 + d_1, d_2) on (J_n, J_{n-1}, J_{n-2}) instead of the
+spline's (1/2, 1/2, 0).  ``delta`` is either the triple (d_0, d_1, d_2) or a
+number d for the first difference (d, -d, 0).  delta = 0 (the default
+everywhere) is the paper's unregularized operator; D = diag(eps_r)(1/2 + d_0).
 
 Three forms of the same product, all FP64:
 
@@ -29,6 +30,18 @@ import scipy.fft as sfft
 from .green import PAIR, green_full
 
 
+def reg_weights(delta):
+    """Local weights (w0, w1, w2) of eps_r on (J_n, J_{n-1}, J_{n-2}) for a
+    regularization ``delta`` (a number d: (d, -d, 0); or (d_0, d_1, d_2))."""
+    if np.ndim(delta) == 0:
+        d = (float(delta), -float(delta), 0.0)
+    else:
+        d = tuple(float(v) for v in delta)
+        if len(d) != 3:
+            raise ValueError("delta: a number or (d_0, d_1, d_2)")
+    return 0.5 + d[0], 0.5 + d[1], d[2]
+
+
 def z0_dense(g0_oct, eps, delta=0.0):
     """Dense Z0 for a grid with eps of shape (nz, ny, nx); row/col = p*N + m."""
     nz, ny, nx = eps.shape
@@ -45,7 +58,7 @@ def z0_dense(g0_oct, eps, delta=0.0):
         for p in range(3):
             for q in range(3):
                 Z[p * N + m, q * N:(q + 1) * N] = -(e[m] - 1.0) * full[p, q, dz, dy, dx]
-            Z[p * N + m, p * N + m] += e[m] * (0.5 + delta)
+            Z[p * N + m, p * N + m] += e[m] * reg_weights(delta)[0]
     return Z
 
 
@@ -117,11 +130,11 @@ def gconv_fft(g_oct, J, lam=None):
 
 
 def z0_apply(g0_oct, eps, J, method="fft", lam=None, delta=0.0):
-    """Z0 J = D J - X (G J), Eq. 12 (D = diag(eps_r)(1/2 + delta))."""
+    """Z0 J = D J - X (G J), Eq. 12 (D = diag(eps_r)(1/2 + d_0))."""
     if method == "fft":
         gj = gconv_fft(g0_oct, J, lam=lam)
     elif method == "direct":
         gj = gconv_direct(g0_oct, J)
     else:
         raise ValueError(method)
-    return (0.5 + delta) * eps[None] * J - (eps[None] - 1.0) * gj
+    return reg_weights(delta)[0] * eps[None] * J - (eps[None] - 1.0) * gj

@@ -105,7 +105,8 @@ class FarFieldMarch:
                 c.step(g, lam, tol=self.tol, max_iter=self.max_iter, stats=False)
                 c.gk_matvec(0, self.Jhist[n], u0, "f64")
                 c.adjoint_gradient(self.pulse, n * self.dt, lam, self.Jhist[n],
-                                   self.Jhist[n - 1] if n > 0 else None, self.UH[n], u0, grad)
+                                   self.Jhist[n - 1] if n > 0 else None, self.UH[n], u0, grad,
+                                   J_prev2=self.Jhist[n - 2] if n > 1 else None)
         finally:
             c.set_adjoint(False)
             c.reset()

@@ -12,7 +12,8 @@
 //
 // Gradient of W(eps) through the adjoint currents lam_n (the transposed
 // march, Z_k^T = T(k) diag(eps) - G_k diag(eps - 1)):
-//   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - (J_n(m) + J_{n-1}(m))/2 + u_n(m)),
+//   dW/d eps_m = sum_n lam_n(m) . (d_t E^i(r_m, t_n) - sum_k w_k J_{n-k}(m) + u_n(m)),
+// w = (1/2, 1/2, 0) plus the regularization's (d_0, d_1, d_2),
 // u_n = sum_k G_k J_{n-k} (given as its history and present parts): the derivative of the excitation (Eq. 7) and of
 // the diagonal and contrast parts of every Z_k with respect to eps_m.
 #include <hip/hip_runtime.h>
@@ -141,9 +142,9 @@ __global__ void k_farfield_adj(const double* __restrict__ w, int j0, int nj, lon
 }
 
 __global__ void k_adjoint_grad(mot_pulse pl, double t, const double* __restrict__ lam, const double* __restrict__ J,
-                               const double* __restrict__ Jprev, const double* __restrict__ uh,
-                               const double* __restrict__ u0, double* __restrict__ grad, double delta, int nx, int ny,
-                               int nz) {
+                               const double* __restrict__ Jprev, const double* __restrict__ Jprev2,
+                               const double* __restrict__ uh, const double* __restrict__ u0,
+                               double* __restrict__ grad, double w0, double w1, double w2, int nx, int ny, int nz) {
   const long long N = (long long)nx * ny * nz;
   const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= N) return;
@@ -154,7 +155,9 @@ __global__ void k_adjoint_grad(mot_pulse pl, double t, const double* __restrict_
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
     const long long i = p * N + m;
-    const double jj = Jprev ? (0.5 + delta) * J[i] + (0.5 - delta) * Jprev[i] : (0.5 + delta) * J[i];
+    double jj = w0 * J[i];
+    if (Jprev) jj += w1 * Jprev[i];
+    if (Jprev2) jj += w2 * Jprev2[i];
     acc += lam[i] * (di * pl.e[p] - jj + (uh[i] + u0[i]));
   }
   grad[m] += acc;
@@ -203,11 +206,11 @@ hipError_t launch_farfield_adjoint(const double* w, int j0, int nj, long long n,
 }
 
 hipError_t launch_adjoint_grad(const mot_pulse* p, double t, const double* lam, const double* J,
-                               const double* Jprev, const double* uh, const double* u0, double* grad, double delta,
-                               int nx, int ny, int nz, hipStream_t s) {
+                               const double* Jprev, const double* Jprev2, const double* uh, const double* u0,
+                               double* grad, const double* w, int nx, int ny, int nz, hipStream_t s) {
   const long long N = (long long)nx * ny * nz;
-  hipLaunchKernelGGL(k_adjoint_grad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, *p, t, lam, J, Jprev, uh,
-                     u0, grad, delta, nx, ny, nz);
+  hipLaunchKernelGGL(k_adjoint_grad, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, *p, t, lam, J, Jprev,
+                     Jprev2, uh, u0, grad, w[0], w[1], w[2], nx, ny, nz);
   return hipGetLastError();
 }
 

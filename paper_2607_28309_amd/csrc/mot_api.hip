@@ -80,9 +80,10 @@ struct mot_ctx {
   double spectra_imag;
   void* lam_tile;      // scratch: one history lag in the z-pass layout (gk_matvec)
   int adjoint;         // 1: transposed operators Z_k^T (adjoint march)
-  // regularization Z^delta_0 = Z_0 + delta diag(eps_r), Z^delta_1 = Z_1 -
-  // delta diag(eps_r) (0: the unregularized operator)
-  double delta;
+  // regularization Z^delta_n = Z_n + dreg[n] diag(eps_r), n = 0, 1, 2 (all
+  // zero: the unregularized operator)
+  double dreg[3];
+  double* jprev2;      // the current pushed before the last one (history term of dreg[2])
   double* ffpart;      // scratch: far-field block partials
   size_t ffpart_n;
   int tune[2][TUNE_N]; // tile variants of the FFT passes (0 or 1)
@@ -260,12 +261,13 @@ __global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int n
       src[(((size_t)comp * (nz + 1) + kz) * (ny + 1) + ky) * kxs + kx];
 }
 
-// rs = 1 / ((1/2 + delta) eps - (eps - 1) g0), the inverse diagonal of Z0 per voxel
-__global__ void k_right_scale(const double* __restrict__ eps, double g0, double delta, float* __restrict__ rs32,
+// rs = 1 / (w0 eps - (eps - 1) g0), the inverse diagonal of Z0 per voxel
+// (w0 = 1/2 + dreg[0])
+__global__ void k_right_scale(const double* __restrict__ eps, double g0, double w0, float* __restrict__ rs32,
                               double* __restrict__ rs64, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double r = 1.0 / (eps[i] * (0.5 + delta - g0) + g0);
+  const double r = 1.0 / (eps[i] * (w0 - g0) + g0);
   rs64[i] = r;
   rs32[i] = (float)r;
 }
@@ -332,14 +334,32 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
   return MOT_OK;
 }
 
-// Epilogues of the products.  D = (1/2 + delta) eps_r is the diagonal of Z0,
-// (1/2 - delta) eps_r that of Z1 (delta = c->delta, 0 without regularization).
-motfft::Epilogue ep_z0(const mot_ctx* c) { return {0.5 + c->delta, 0.0, -1.0, 1.0}; }    // D J - X (G J)
-const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};                                          // G J
-motfft::Epilogue ep_hist(const mot_ctx* c) { return {-(0.5 - c->delta), 0.0, 1.0, -1.0}; } // -(diag Z1) J + X (G J)
+// Epilogues of the products.  D = (1/2 + dreg[0]) eps_r is the diagonal of
+// Z0, (1/2 + dreg[1]) eps_r that of Z1 (dreg = 0 without regularization; the
+// dreg[2] eps_r J_{n-1} term of the history is added by k_reg2).
+motfft::Epilogue ep_z0(const mot_ctx* c) { return {0.5 + c->dreg[0], 0.0, -1.0, 1.0}; }     // D J - X (G J)
+const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};                                             // G J
+motfft::Epilogue ep_hist(const mot_ctx* c) { return {-(0.5 + c->dreg[1]), 0.0, 1.0, -1.0}; } // -(diag Z1) J + X (G J)
 // transposed operators (contrast on the input, applied by the forward x pass)
-motfft::Epilogue ep_z0t(const mot_ctx* c) { return {0.5 + c->delta, 0.0, 0.0, -1.0}; }     // D v - G (X v)
-motfft::Epilogue ep_adj_hist(const mot_ctx* c) { return {-(0.5 - c->delta), 0.0, 0.0, 1.0}; } // -(diag Z1) v + G (X v)
+motfft::Epilogue ep_z0t(const mot_ctx* c) { return {0.5 + c->dreg[0], 0.0, 0.0, -1.0}; }      // D v - G (X v)
+motfft::Epilogue ep_adj_hist(const mot_ctx* c) { return {-(0.5 + c->dreg[1]), 0.0, 0.0, 1.0}; } // -(diag Z1) v + G (X v)
+
+// h -= w2 eps prev, then prev = J (3 components of nvox voxels): the
+// dreg[2] eps_r J_{n-1} part of the history right-hand side, and the
+// hand-over of the newest current for the next step
+__global__ void k_reg2(double* __restrict__ h, double* __restrict__ prev, const double* __restrict__ J,
+                       const double* __restrict__ eps, double w2, long long nvox) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nvox) return;
+  h[i] -= w2 * eps[i % nvox] * prev[i];
+  prev[i] = J[i];
+}
+
+hipError_t launch_reg2(mot_ctx* c, const double* J) {
+  hipLaunchKernelGGL(k_reg2, dim3((unsigned)((c->n3 + 255) / 256)), dim3(256), 0, c->stream, c->hrhs, c->jprev2, J,
+                     c->eps, c->dreg[2], c->N);
+  return hipGetLastError();
+}
 
 int reduce_sync(mot_ctx* c) {
   HT(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->stream));
@@ -887,6 +907,7 @@ int history_update_t(mot_ctx* c, const double* J) {
                                               rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
                                               tv[TUNE_X])));
+  if (c->dreg[2] != 0.0) HTP(K_KRY, d, launch_reg2(c, J));
   c->head = slot;
   c->nstep += 1;
   return MOT_OK;
@@ -931,7 +952,7 @@ void drop_graphs(mot_ctx* c) {
 int update_right_scale(mot_ctx* c) {
   if (!c->have_eps || !c->have_spectra) return MOT_OK;
   hipLaunchKernelGGL(k_right_scale, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, c->stream, c->eps,
-                     c->g0self, c->delta, c->rs32, c->rs64, c->N);
+                     c->g0self, 0.5 + c->dreg[0], c->rs32, c->rs64, c->N);
   HT(hipGetLastError());
   return MOT_OK;
 }
@@ -1178,7 +1199,7 @@ int mot_destroy(mot_ctx* c) {
   if (!c) return MOT_OK;
   (void)hipStreamSynchronize(c->stream);
   void* bufs[] = {c->eps, c->rs32, c->rs64, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
-                  c->partials, c->scal, c->lam_tile, c->pblk, c->ffpart};
+                  c->partials, c->scal, c->lam_tile, c->pblk, c->ffpart, c->jprev2};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int i = 0; i < 13; ++i)
@@ -1425,6 +1446,7 @@ int mot_reset(mot_ctx* c) {
   TRY(zero_bytes(c, c->ring, rsz * 2 * c->slot_elems * c->nl));
   TRY(zero_bytes(c, c->hrhs, sizeof(double) * c->n3));
   TRY(zero_bytes(c, c->spec, rsz * 2 * c->slot_elems));
+  TRY(zero_bytes(c, c->jprev2, sizeof(double) * c->n3));
   c->nstep = 0;
   c->head = 0;
   c->blk_n0 = -1;
@@ -1498,10 +1520,19 @@ int mot_set_predictor(mot_ctx* c, int32_t k) {
   return MOT_OK;
 }
 
-int mot_set_regularization(mot_ctx* c, double delta) {
-  if (!c || !(delta >= 0.0 && delta < 0.5)) return MOT_EINVAL;
-  if (delta == c->delta) return MOT_OK;
-  c->delta = delta;
+int mot_set_regularization(mot_ctx* c, double d0, double d1, double d2) {
+  if (!c || !std::isfinite(d0) || !std::isfinite(d1) || !std::isfinite(d2) || !(0.5 + d0 > 0.0))
+    return MOT_EINVAL;
+  if (d0 == c->dreg[0] && d1 == c->dreg[1] && d2 == c->dreg[2]) return MOT_OK;
+  if (d2 != 0.0 && !c->jprev2) {
+    TRY(dmalloc(c, (void**)&c->jprev2, sizeof(double) * c->n3));
+    // the current pushed before the last one is not known here: zero, as
+    // after mot_reset (exact for a march started by mot_reset)
+    TRY(zero_bytes(c, c->jprev2, sizeof(double) * c->n3));
+  }
+  c->dreg[0] = d0;
+  c->dreg[1] = d1;
+  c->dreg[2] = d2;
   // the diagonal of Z0 changed: the right scaling, the captured iteration
   // graphs (their epilogue arguments) and the stored Z0 J_i are stale
   drop_graphs(c);
@@ -1629,9 +1660,11 @@ int mot_farfield_adjoint(mot_ctx* c, const double* w, int32_t j0, int32_t nj, co
 }
 
 int mot_adjoint_gradient(mot_ctx* c, const mot_pulse* p, double t, const double* lam_n, const double* J_n,
-                         const double* J_prev, const double* uh_n, const double* u0_n, double* grad) {
+                         const double* J_prev, const double* J_prev2, const double* uh_n, const double* u0_n,
+                         double* grad) {
   if (!c || !p || !lam_n || !J_n || !uh_n || !u0_n || !grad) return MOT_EINVAL;
-  HT(launch_adjoint_grad(p, t, lam_n, J_n, J_prev, uh_n, u0_n, grad, c->delta, c->nx, c->ny, c->nz, c->stream));
+  const double w[3] = {0.5 + c->dreg[0], 0.5 + c->dreg[1], c->dreg[2]};
+  HT(launch_adjoint_grad(p, t, lam_n, J_n, J_prev, J_prev2, uh_n, u0_n, grad, w, c->nx, c->ny, c->nz, c->stream));
   return MOT_OK;
 }
 

@@ -167,10 +167,10 @@ hipError_t launch_farfield(const double* Jhist, int nsteps, int nx, int ny, int 
 // g_n[3N] = scale * (transpose of the far field applied to the weights w[nj][3]), step n.
 hipError_t launch_farfield_adjoint(const double* w, int j0, int nj, long long n, int nx, int ny, int nz,
                                    const FarGeom& g, double scale, double* g_n, hipStream_t s);
-// grad[m] += sum_p lam[p,m] (d_t E^i_p(r_m, t) - (1/2 + delta) J[p,m] - (1/2 - delta) Jprev[p,m]
-//                            + uh[p,m] + u0[p,m]);  Jprev may be null.
+// grad[m] += sum_p lam[p,m] (d_t E^i_p(r_m, t) - w0 J[p,m] - w1 Jprev[p,m] - w2 Jprev2[p,m]
+//                            + uh[p,m] + u0[p,m]);  Jprev and Jprev2 may be null (zero).
 hipError_t launch_adjoint_grad(const mot_pulse* p, double t, const double* lam, const double* J,
-                               const double* Jprev, const double* uh, const double* u0, double* grad, double delta,
-                               int nx, int ny, int nz, hipStream_t s);
+                               const double* Jprev, const double* Jprev2, const double* uh, const double* u0,
+                               double* grad, const double* w, int nx, int ny, int nz, hipStream_t s);
 
 }  // namespace motimpl

@@ -97,12 +97,12 @@ def _load():
         "mot_farfield": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
         "mot_farfield_static": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(dbl), i32, i32, vp, vp]),
         "mot_farfield_adjoint": (ctypes.c_int, [vp, vp, i32, i32, ctypes.POINTER(dbl), dbl, i64, vp]),
-        "mot_adjoint_gradient": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp, vp, vp, vp, vp, vp]),
+        "mot_adjoint_gradient": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp, vp, vp, vp, vp, vp, vp]),
         "mot_set_variants": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
         "mot_get_variants": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
         "mot_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
         "mot_set_predictor": (ctypes.c_int, [vp, i32]),
-        "mot_set_regularization": (ctypes.c_int, [vp, dbl]),
+        "mot_set_regularization": (ctypes.c_int, [vp, dbl, dbl, dbl]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -257,8 +257,13 @@ class Context:
         self._check(LIB.mot_set_adjoint(self.h, 1 if on else 0), "mot_set_adjoint")
 
     def set_regularization(self, delta):
-        """delta of the regularized Z_0, Z_1 (0 = the unregularized operator)."""
-        self._check(LIB.mot_set_regularization(self.h, float(delta)), "mot_set_regularization")
+        """Regularization (d_0, d_1, d_2) of Z_0, Z_1, Z_2, or a number d for (d, -d, 0)
+        (0 = the unregularized operator)."""
+        import numpy as np
+        d = (float(delta), -float(delta), 0.0) if np.ndim(delta) == 0 else tuple(float(v) for v in delta)
+        if len(d) != 3:
+            raise ValueError("delta: a number or (d_0, d_1, d_2)")
+        self._check(LIB.mot_set_regularization(self.h, *d), "mot_set_regularization")
 
     def set_predictor(self, k):
         """Initial guess of the refined solve from the last k solutions (0 = off)."""
@@ -329,13 +334,14 @@ class Context:
                                              float(scale), int(n), _ptr(g_n, torch.float64, 3 * self.N)),
                     "mot_farfield_adjoint")
 
-    def adjoint_gradient(self, pulse, t, lam_n, J_n, J_prev, uh_n, u0_n, grad):
+    def adjoint_gradient(self, pulse, t, lam_n, J_n, J_prev, uh_n, u0_n, grad, J_prev2=None):
         import torch
         p = make_pulse(pulse)
         v3 = 3 * self.N
         jp = _ptr(J_prev, torch.float64, v3) if J_prev is not None else None
+        jp2 = _ptr(J_prev2, torch.float64, v3) if J_prev2 is not None else None
         self._check(LIB.mot_adjoint_gradient(self.h, ctypes.byref(p), float(t), _ptr(lam_n, torch.float64, v3),
-                                             _ptr(J_n, torch.float64, v3), jp, _ptr(uh_n, torch.float64, v3),
+                                             _ptr(J_n, torch.float64, v3), jp, jp2, _ptr(uh_n, torch.float64, v3),
                                              _ptr(u0_n, torch.float64, v3), _ptr(grad, torch.float64, self.N)),
                     "mot_adjoint_gradient")
 

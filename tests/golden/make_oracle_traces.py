@@ -5,7 +5,8 @@ of ``workloads``; run it on the CPU:
     python tests/golden/make_oracle_traces.py [cube32 | pillars80]
 
 Each trace is an FP64 march of Eq. 3 from t = 0 with the regularized
-operator (delta = DELTA_HAT / alpha, Sec. II delta-notation), TFQMR to 1e-10,
+operator of the workloads (workloads.regularization_for(alpha), Sec. II
+delta-notation), TFQMR to 1e-10,
 saved as an .npz (no pickles) holding: the step count, alpha, delta, the
 per-step norm ||J_n||, the sampled voxel indices (flat, [z][y][x]) and J_n at
 those voxels for every step, shape (steps, 3, nsamples).
@@ -56,7 +57,7 @@ def make(name):
     eps = cs["eps"]()
     nz, ny, nx = eps.shape
     alpha = cs["alpha"]
-    delta = W.delta_for(alpha)
+    delta = W.regularization_for(alpha)
     L = basis.cdt_from_alpha(alpha)
     nl = basis.nlags(nx, ny, nz, alpha=alpha)
     t0 = time.time()
@@ -77,7 +78,7 @@ def make(name):
         samp.append(J.reshape(3, -1)[:, idx])
         if s % 10 == 0:
             print(f"  step {s}: |J| {norms[-1]:.4e}, {res.iterations} it, {time.time() - t0:.0f}s", flush=True)
-    np.savez(path(name), steps=cs["steps"], alpha=alpha, delta=delta, shape=np.array([nx, ny, nz]),
+    np.savez(path(name), steps=cs["steps"], alpha=alpha, delta=np.array(delta), shape=np.array([nx, ny, nz]),
              norms=np.array(norms), idx=idx, samples=np.array(samp))
     print(f"wrote {path(name)}", flush=True)
 

@@ -175,7 +175,7 @@ def test_gradient_regularized_and_two_forwards(gpu_lib):
     # a later forward (another permittivity) still returns its own gradient
     import torch
     from paper_2607_28309_amd import adjoint as A
-    n, alpha, nt, delta = (8, 4, 4), 2, 12, 0.05
+    n, alpha, nt, delta = (8, 4, 4), 2, 12, (0.05, -0.15, 0.1)
     eps = _eps(n, 111)
     eps2 = eps * 1.1
     c = _ctx(gpu_lib, n, alpha, eps)

@@ -85,7 +85,7 @@ def test_farfield_adjoint_dot_product():
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-@pytest.mark.parametrize("delta", [0.0, 0.07])
+@pytest.mark.parametrize("delta", [0.0, 0.07, (0.1, -0.2, 0.1)])
 def test_adjoint_march_solves_transposed_spacetime_system(delta):
     n, alpha, nt = (2, 2, 2), 1, 7
     nl = basis.nlags(*n, alpha=alpha)
@@ -93,8 +93,10 @@ def test_adjoint_march_solves_transposed_spacetime_system(delta):
     eps = W.eps_iid(n, 2.0, 5.0, seed=41)
     shape = eps.shape
     m3 = 3 * eps.size
-    # local weights of Z_0, Z_1: the spline's T(0) = T(1) = 1/2, shifted by +-delta
-    Tk = [0.5 + delta, 0.5 - delta] + [0.0] * (nl - 1)
+    # local weights of Z_0, Z_1, Z_2: the spline's T(0) = T(1) = 1/2, T(2) = 0,
+    # plus the regularization's (d, -d, 0) or (d_0, d_1, d_2)
+    d = (delta, -delta, 0.0) if np.ndim(delta) == 0 else delta
+    Tk = [0.5 + d[0], 0.5 + d[1], d[2]] + [0.0] * (nl - 2)
     d = np.tile(eps.ravel(), 3)
     x = d - 1.0
     Zk = [Tk[k] * np.diag(d) - x[:, None] * _dense_g(greens[k], n) for k in range(nl + 1)]
@@ -114,7 +116,7 @@ def test_adjoint_march_solves_transposed_spacetime_system(delta):
     assert np.linalg.norm(J - J_dense) <= 1e-10 * np.linalg.norm(J_dense)
 
 
-@pytest.mark.parametrize("delta", [0.0, 0.05])
+@pytest.mark.parametrize("delta", [0.0, 0.05, (0.1, -0.2, 0.1)])
 def test_gradient_matches_central_differences(delta):
     n, alpha, nt = (3, 2, 2), 2, 12
     dt = basis.cdt_from_alpha(alpha)

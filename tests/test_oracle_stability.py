@@ -76,11 +76,13 @@ def test_companion_roots_and_march_growth(alpha):
     assert np.abs(np.linalg.eigvals(Cd)).max() < 0.999
 
 
-@pytest.mark.parametrize("alpha,eps_r,delta", [(2, 4.0, 0.05), (16, 4.0, 0.2), (8, 12.0, 0.0125)])
+@pytest.mark.parametrize("alpha,eps_r,delta", [(2, 4.0, (0.05, -0.05, 0.0)), (16, 4.0, (0.2, -0.2, 0.0)),
+                                               (8, 12.0, (0.0125, -0.0125, 0.0)), (2, 12.0, (0.2, -0.4, 0.2))])
 def test_single_voxel_recurrence_with_delta(alpha, eps_r, delta):
     # 1 voxel, alpha >= 3/2: z0 J_n = E_n - z1 J_{n-1} - z2 J_{n-2},
-    # z0 = e (1/2 + delta) - (e-1)(1/3 - c1/a^2), z1 = e (1/2 - delta) - (e-1)(1/3 + 2 c1/a^2),
-    # z2 = (e-1) c1/a^2; the DC gain 1/(z0+z1+z2) = 3/(e+2) does not depend on delta
+    # z0 = e (1/2 + d0) - (e-1)(1/3 - c1/a^2), z1 = e (1/2 + d1) - (e-1)(1/3 + 2 c1/a^2),
+    # z2 = e d2 + (e-1) c1/a^2; the DC gain 1/(z0+z1+z2) = 3/(e+2) does not depend on
+    # a regularization whose weights sum to zero
     n = (1, 1, 1)
     L = basis.cdt_from_alpha(alpha)
     eps = W.eps_uniform(n, eps_r)
@@ -89,9 +91,10 @@ def test_single_voxel_recurrence_with_delta(alpha, eps_r, delta):
     nl = basis.nlags(*n, alpha=alpha)
     J, _ = march.run(eps, green.green_all(*n, nl, alpha=alpha), L, p, steps, tol=1e-14, delta=delta)
     e = eps_r
-    z0 = e * (0.5 + delta) - (e - 1) * (1 / 3 - C1 / alpha ** 2)
-    z1 = e * (0.5 - delta) - (e - 1) * (1 / 3 + 2 * C1 / alpha ** 2)
-    z2 = (e - 1) * C1 / alpha ** 2
+    d0, d1, d2 = delta
+    z0 = e * (0.5 + d0) - (e - 1) * (1 / 3 - C1 / alpha ** 2)
+    z1 = e * (0.5 + d1) - (e - 1) * (1 / 3 + 2 * C1 / alpha ** 2)
+    z2 = e * d2 + (e - 1) * C1 / alpha ** 2
     ref = np.zeros((steps, 3))
     for s in range(steps):
         E = march.dt_einc(p, eps, s * L)[:, 0, 0, 0]
@@ -112,11 +115,13 @@ def test_regularized_march_bounded_1500_steps(alpha, eps_r):
     nl = basis.nlags(*n, alpha=alpha)
     eps = W.eps_uniform(n, eps_r)
     p = W.pulse(20)
-    mot = march.Mot(eps, green.green_all(*n, nl, alpha=alpha), L, delta=W.delta_for(alpha))
+    mot = march.Mot(eps, green.green_all(*n, nl, alpha=alpha), L, delta=W.regularization_for(alpha))
     norms = np.array([np.linalg.norm(mot.step(march.dt_einc(p, eps, s * L), tol=1e-6)[0])
                       for s in range(1500)])
     assert np.all(np.isfinite(norms))
     peak = norms.max()
-    # the pulse has passed long before step 1000: the tail decays and stays small
-    assert norms[1000:].max() <= 1e-3 * peak
-    assert norms[-100:].max() <= norms[1000:1100].max()
+    # the pulse has passed long before step 1000; what is left is the cube's
+    # own ringing, which decays (slowly for eps_r = 12: the second difference
+    # adds no damping in the physical band) and never grows back
+    assert norms[1000:].max() <= 0.1 * peak
+    assert norms[1300:].max() <= norms[1000:1300].max()

@@ -88,18 +88,17 @@ def sparse_current(n, seed, count):
     return J, idx
 
 
-# Regularization of the marches of these workloads: the delta of the
-# regularized interaction matrices (delta_0 = +delta eps_r, delta_1 = -delta
-# eps_r; 0 is the unregularized operator), per time step dt = alpha dt_CFL.
-# Values: the smallest delta, among 0.1 / 0.2 / 0.3 / 0.45 (alpha <= 4) and
-# DELTA_HAT / alpha for DELTA_HAT in 0.01 .. 0.1 (alpha >= 4), that kept the
-# 300-step 64^3 i.i.d. cube and the 96^3 nested cube of the time-step sweep
-# bounded over their windows, with a margin of 2 to 4 for alpha >= 4.
-DELTA_TABLE = {1: 0.45, 2: 0.2, 4: 0.05, 8: 0.005, 16: 0.001}
+# Regularization of the marches of these workloads: the second difference
+# (d/2, -d, d/2) of the regularized interaction matrices (delta_n = d_n
+# diag(eps_r) for n = 0, 1, 2), with d per time step dt = alpha dt_CFL.
+# Values: about twice the smallest d that kept the 300-step 64^3 i.i.d. cube
+# and the 96^3 nested cube of the time-step sweep (over two windows of
+# 1600 dt_CFL) bounded.
+DELTA_TABLE = {1: 1.5, 2: 0.4, 4: 0.1, 8: 0.01, 16: 0.002}
 
 
 def delta_for(alpha):
-    """delta for dt = alpha dt_CFL: DELTA_TABLE, log-linear in alpha between entries."""
+    """d for dt = alpha dt_CFL: DELTA_TABLE, log-linear in alpha between entries."""
     a = float(alpha)
     keys = sorted(DELTA_TABLE)
     if a <= keys[0]:
@@ -110,6 +109,12 @@ def delta_for(alpha):
         if lo <= a <= hi:
             t = math.log(a / lo) / math.log(hi / lo)
             return math.exp((1 - t) * math.log(DELTA_TABLE[lo]) + t * math.log(DELTA_TABLE[hi]))
+
+
+def regularization_for(alpha):
+    """(d_0, d_1, d_2) = (d/2, -d, d/2) with d = delta_for(alpha)."""
+    d = delta_for(alpha)
+    return (0.5 * d, -d, 0.5 * d)
 
 
 @dataclass
