@@ -316,7 +316,8 @@ def sweep_leg(args, log_fn):
     probe = n[0] // 2 + n[0] * (n[1] // 2 + n[1] * (n[2] // 2))   # x component, central voxel
     common = math.lcm(*args.sweep_alphas)
     rows, probes = [], {}
-    for alpha in args.sweep_alphas:
+
+    def march(alpha, scheme):
         steps = args.sweep_window // alpha
         L = alpha / math.sqrt(3.0)
         t0 = time.perf_counter()
@@ -324,6 +325,7 @@ def sweep_leg(args, log_fn):
         c.set_material(eps)
         c.build_green_spectra()
         c.set_regularization(W.regularization_for(alpha))
+        c.set_history_scheme(scheme)
         if not args.no_autotune:
             c.autotune(reps=5)
         c.reset()
@@ -350,16 +352,15 @@ def sweep_leg(args, log_fn):
                 pr.append(float(J[probe]))
         torch.cuda.synchronize()
         el = time.perf_counter() - t
-        probes[alpha] = pr
         done = len(st)
         mv = sum(s_["matvecs"] for s_ in st)
         q = max(steps // 4, 1)
         quarters = [max(amax[i:i + q], default=None) for i in range(0, steps, q)][:4]
-        peak = max(amax, default=0.0)
         # bounded: ran the whole window and the last quarter stays below the
         # peak of the earlier ones (ringing after the pulse, no growth)
         bounded = diverged is None and len(quarters) == 4 and quarters[-1] <= max(quarters[:3])
         row = {"alpha": alpha, "delta": list(W.regularization_for(alpha)), "steps": steps, "steps_done": done,
+               "history_scheme": {1: "blocked", 2: "fft_time"}[info["history_scheme"]],
                "diverged_at_step": diverged,
                "bounded": bounded, "max_abs_J_per_quarter": quarters,
                "nlags": info["nlags"], "z0_nnz": native.zk_nnz(*n, k=0, alpha=alpha),
@@ -372,22 +373,36 @@ def sweep_leg(args, log_fn):
                "ms_rhs_per_step": sum(s_["ms_rhs"] for s_ in st) / max(done, 1),
                "ms_per_matvec_in_solve": sum(s_["ms_lhs"] for s_ in st) / max(mv, 1),
                "relres_max": max((s_["relres"] for s_ in st), default=None)}
-        rows.append(row)
-        log_fn(f"sweep alpha {alpha}: {done} of {steps} steps in {el:.2f} s (diverged at {diverged}), "
-               f"ell {info['nlags']}, "
+        log_fn(f"sweep alpha {alpha} ({row['history_scheme']}): {done} of {steps} steps in {el:.2f} s "
+               f"(diverged at {diverged}), ell {info['nlags']}, "
                f"{row['iters_per_step']['mean']:.2f} iterations/step, LHS {row['ms_lhs_per_step']:.2f} ms/step, "
                f"RHS {row['ms_rhs_per_step']:.2f} ms/step")
         c.close()
         del c
         torch.cuda.empty_cache()
+        return row, pr
+
+    for alpha in args.sweep_alphas:
+        # the library's history scheme, then (--sweep-history both) the other
+        # one where an FP32 ring of >= 32 lags allows both
+        row, pr = march(alpha, args.sweep_history if args.sweep_history != "both" else "auto")
+        row["default_scheme"] = args.sweep_history in ("auto", "both")
+        rows.append(row)
+        probes[alpha] = pr
+        if args.sweep_history == "both" and args.precision != "f64" and row["nlags"] >= 32:
+            other = "blocked" if row["history_scheme"] == "fft_time" else "fft_time"
+            alt, _ = march(alpha, other)
+            alt["default_scheme"] = False
+            rows.append(alt)
     # the march's own time-step convergence, against the smallest alpha whose
     # current stayed bounded over the whole window
-    ok = [r["alpha"] for r in rows if r["bounded"]]
+    main = [r for r in rows if r["default_scheme"]]
+    ok = [r["alpha"] for r in main if r["bounded"]]
     a0 = min(ok) if ok else None
     if a0 is not None:
         ref = probes[a0]
         scale = max(abs(v) for v in ref) or 1.0
-        for row in rows:
+        for row in main:
             pr = probes[row["alpha"]]
             m = min(len(pr), len(ref))
             row["probe_diff_vs_ref"] = (max(abs(a - b) for a, b in zip(pr[:m], ref[:m])) / scale) if m else None
@@ -396,7 +411,7 @@ def sweep_leg(args, log_fn):
                                                    (max(abs(v) for v in ref[:h]) or 1.0)) if h else None
     # the same sweep on a 24^3 cut of this medium against the FP64 oracle
     cut = w.eps()[24:48, 24:48, 24:48]
-    for row in rows:
+    for row in main:
         row["cut24_field_err_vs_oracle"] = _trace_march(args, f"nested24_a{row['alpha']}", cut, w.ppw, log_fn)
     return {"workload": "nested_cube_96x96x96_fixed_window", "precision": args.precision,
             "tol": args.tol, "window_dt_cfl": args.sweep_window, "probe": "J_x at voxel (48, 48, 48)",
@@ -452,6 +467,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
     ap.add_argument("--graphs", action="store_true", help="replay TFQMR iterations from HIP graphs")
+    ap.add_argument("--history", default="auto", choices=["auto", "blocked", "fft_time"],
+                    help="history scheme of the benchmarked march (auto: the library's choice)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch of 32 independent cubes (sides 24..80, alpha 4) stepped together")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -460,6 +477,9 @@ def main():
     ap.add_argument("--sweep-only", action="store_true", help="run only the time-step sweep and print its JSON line")
     ap.add_argument("--sweep-alphas", type=int, nargs="+", default=[1, 2, 4, 8, 16])
     ap.add_argument("--sweep-window", type=int, default=1600, help="window length in dt_CFL")
+    ap.add_argument("--sweep-history", default="both", choices=["auto", "blocked", "fft_time", "both"],
+                    help="history scheme of the sweep's marches (both: the library's choice, then the other one "
+                         "where both are possible)")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no timing events in the timed region (the roofline then uses the breakdown steps)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -501,6 +521,7 @@ def main():
     log(f"context: {ctx.info()}")
     imag = ctx.build_green_spectra()
     ctx.set_regularization(W.regularization_for(w.alpha))
+    ctx.set_history_scheme(args.history)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = ctx.info()
@@ -644,6 +665,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(n), "unknowns": 3 * N, "alpha": w.alpha, "nlags": nl,
                    "delta": list(W.regularization_for(w.alpha)), "precision": args.precision, "tol": args.tol,
+                   "history_scheme": {1: "blocked", 2: "fft_time"}[info["history_scheme"]],
                    "parallelism": "single GPU"},
         "z0_matvecs_per_s": {k: v["per_s"] for k, v in mv.items()},
         "z0_matvec_ms": {k: v["ms"] for k, v in mv.items()},

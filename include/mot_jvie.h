@@ -108,8 +108,9 @@ int mot_destroy(mot_ctx* ctx);
 /* Sizes: out[0] = ell, out[1..3] = 2nx, 2ny, 2nz, out[4] = padded row
  * stride of the spectral buffers, out[5] = device bytes held by the context,
  * out[6] = steps taken since the last reset, and with n >= 8 out[7] = B, the
- * steps per history block (temporal blocking of the history sum).  Host array
- * of n >= 7 entries. */
+ * steps per history block (temporal blocking of the history sum), with
+ * n >= 9 out[8] = the history scheme in use (1 or 2, mot_set_history_scheme).
+ * Host array of n >= 7 entries. */
 int mot_info(const mot_ctx* ctx, int64_t* out, int32_t n);
 
 /* Operator precompute (Sec. II: Z_k for lags 0..ell; Sec. IV: spectra of the
@@ -153,7 +154,11 @@ int gk_matvec(mot_ctx* ctx, int32_t k, const void* J, void* y, mot_precision dty
  * The spectral sums are blocked in time: every B steps (B = 8, halved while
  * B > ell) one pass over the ring accumulates the contributions of all
  * stored currents to the next B right-hand sides; the steps in between add
- * only their newest lags.  Errors: MOT_ESTATE, MOT_EHIP. */
+ * only their newest lags.  With the history scheme of FFTs in time (see
+ * mot_set_history_scheme) the lags that reach back before the current block
+ * of 32 steps are applied once per such block in the frequency domain of
+ * time, and the blocked pass covers the current block's currents only.
+ * Errors: MOT_ESTATE, MOT_EHIP. */
 int history_update(mot_ctx* ctx, const double* J_n);
 
 /* Copy the prepared history right-hand side (FP64, 3N) to `out` (device). */
@@ -249,6 +254,29 @@ int mot_set_predictor(mot_ctx* ctx, int32_t k);
  * Errors: MOT_EINVAL (NULL, a value not finite, 1/2 + d0 <= 0), MOT_ENOMEM. */
 int mot_set_regularization(mot_ctx* ctx, double d0, double d1, double d2);
 
+/* How history_update evaluates sum_k Lambda_k J^_{n+1-k}, the history
+ * right-hand side that dominates at small time steps (Sec. III-A, small
+ * time-step regime; Sec. III-B evaluates it with an FFT-based
+ * delayed-history scheme):
+ *   1  per-lag multiply-accumulate over all ell lags, blocked in time (B = 8);
+ *   2  FFTs in time: the steps are grouped in blocks of S = 32; at the first
+ *      push of a block the lags reaching back into each earlier block m are
+ *      applied as one product per frequency of a length-2S transform in time
+ *      (the spectra of the lag segments Lambda_{(m-1)S+1..(m+1)S-1} are
+ *      computed once, with the spectra, from the stored Lambda_k), and the
+ *      lags inside the current block stay with the blocked pass of scheme 1.
+ *      The same sums up to rounding; the work per step drops from O(ell)
+ *      multiply-adds per frequency to O((ell / S) log S).  Needs an FP32 ring
+ *      (precision MOT_F32 or MOT_F32_REFINED) and ell >= 32; it holds
+ *      (ell - 1) / 32 + 1 transformed lag segments (33 complex frequencies
+ *      of the 6 components each, FP32) and 32 right-hand-side spectra;
+ *   0  the library's choice (the default): 2 when possible and ell >= 128.
+ * A change applies from the next push on (a block of 32 steps that has
+ * begun finishes with scheme 1).  mot_info reports the scheme in use.
+ * Errors: MOT_EINVAL (NULL, scheme not 0..2, scheme 2 not possible),
+ * MOT_ENOMEM. */
+int mot_set_history_scheme(mot_ctx* ctx, int32_t scheme);
+
 /* Start a new march of Eq. 3: n = 0, history ring and history right-hand
  * side zeroed (J_{n<0} = 0: the causal start of the recursion). */
 int mot_reset(mot_ctx* ctx);
@@ -272,11 +300,12 @@ int mot_green_table(mot_ctx* ctx, int32_t k, double* out);
  *   epilogue, 5 z forward (history spectra), 6 history multiply-accumulate
  *   over all old slots (start of a block of steps), 7 z inverse (history),
  *   8 Krylov vector/reduction kernels (FP64: odd class), 9 excitation,
- *   10 history multiply-accumulate of the newest lags inside a block.
+ *   10 history multiply-accumulate of the newest lags inside a block,
+ *   11 history far lags by FFTs in time (start of a block of 32 steps).
  * mot_profile_read copies the accumulated milliseconds and launch counts of
  * the n = MOT_PROF_NCLASS classes to host arrays, then clears them (it
  * waits for the stream).  Timing adds a few microseconds per launch. */
-#define MOT_PROF_NCLASS 22
+#define MOT_PROF_NCLASS 24
 int mot_profile(mot_ctx* ctx, int32_t enable);
 int mot_profile_read(mot_ctx* ctx, double* ms, int64_t* counts, int32_t n);
 /* Restrict timing to the kinds whose bit is set in kind_mask (bit k = kind

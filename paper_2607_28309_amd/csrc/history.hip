@@ -295,4 +295,293 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
   return hipGetLastError();
 }
 
+// ---- History by FFTs in time (FP32 ring) ----------------------------------
+//
+// The lags beyond the current time block are applied block by block in the
+// frequency domain of time.  Steps are grouped in blocks of S = TF_S; at the
+// push of J^_n with n = beta S, the right-hand sides of steps n + 1 + i,
+// i = 0..S-1, receive from the currents of block m (times
+// t = (beta - m) S + 1 + q, q = 0..S-1) the lags L = m S + i - q, which lie
+// in (m-1) S + 1 .. (m+1) S - 1.  With x_m[q] = J^_t zero-padded to 2S and
+// k_m[d] = Lambda_{(m-1) S + d} (d = 1..2S-1, k_m[0] = 0), that sum is the
+// entry S + i of the cyclic convolution of length 2S (no index wraps), so
+//   far_i = IDFT_2S( sum_m K_m . X_m )[S + i],  K_m = DFT_2S(k_m), X_m = DFT_2S(x_m).
+// Block m = 1 ends at n itself.  The lags inside the current block (the
+// currents of steps beta S + 1 .. n' - 1 for step n') are left to the blocked
+// multiply-accumulate above, which takes far as its initial value.
+//
+// Each workgroup takes 32 consecutive frequencies kx of one row (kz, ky) and
+// all three components; thread (component j, point p, parity h) transforms
+// its current at the frequencies w = 2u + h, u = 0..31, as a 32-point DFT of
+// x[q] W_64^{hq} (the two parities split the 64-point transform, whose upper
+// inputs are zero).  The spectra X go through LDS so that the thread of row i
+// forms sum_j K_m,ij X_m,j at its frequencies; after the last block it
+// inverts its parity (a 32-point inverse DFT each), and the two parities of a
+// point combine through a lane exchange:
+//   y[S + i] = (E(i) - W_64^{-i} O(i)) / 2S.
+// K_m is real in time, so K_m(2S - w) = conj K_m(w) and only w = 0..S are
+// stored.  Lambda is shared by the four mirror points of an octant frequency
+// (reflection signs as in mac3); the four workgroups of one octant row and
+// kx range are neighbours in the XCD-aware order, so they read K through one L2.
+
+struct Tw64 {
+  // cos(2 pi j / 64); sin(2 pi j / 64) = cos(2 pi (j - 16) / 64)
+  static constexpr double c[64] = {1, 0.99518472667219693, 0.98078528040323043, 0.95694033573220882, 0.92387953251128674, 0.88192126434835505, 0.83146961230254524, 0.77301045336273699, 0.70710678118654757, 0.63439328416364549, 0.55557023301960229, 0.47139673682599781, 0.38268343236508984, 0.29028467725446233, 0.19509032201612833, 0.09801714032956077, 6.123233995736766e-17, -0.098017140329560645, -0.19509032201612819, -0.29028467725446216, -0.38268343236508973, -0.4713967368259977, -0.55557023301960196, -0.63439328416364538, -0.70710678118654746, -0.77301045336273699, -0.83146961230254535, -0.88192126434835494, -0.92387953251128674, -0.95694033573220882, -0.98078528040323043, -0.99518472667219682, -1, -0.99518472667219693, -0.98078528040323043, -0.95694033573220894, -0.92387953251128685, -0.88192126434835505, -0.83146961230254546, -0.7730104533627371, -0.70710678118654768, -0.63439328416364593, -0.55557023301960218, -0.47139673682599786, -0.38268343236509034, -0.29028467725446244, -0.19509032201612866, -0.098017140329560451, -1.8369701987210297e-16, 0.09801714032956009, 0.1950903220161283, 0.29028467725446205, 0.38268343236509, 0.47139673682599759, 0.55557023301960184, 0.6343932841636456, 0.70710678118654735, 0.77301045336273666, 0.83146961230254524, 0.88192126434835483, 0.92387953251128652, 0.95694033573220882, 0.98078528040323032, 0.99518472667219693};
+  static constexpr double cs(int j) { return c[j & 63]; }
+  static constexpr double sn(int j) { return c[(j + 48) & 63]; }
+};
+
+__constant__ double tf_cos64[64] = {1, 0.99518472667219693, 0.98078528040323043, 0.95694033573220882, 0.92387953251128674, 0.88192126434835505, 0.83146961230254524, 0.77301045336273699, 0.70710678118654757, 0.63439328416364549, 0.55557023301960229, 0.47139673682599781, 0.38268343236508984, 0.29028467725446233, 0.19509032201612833, 0.09801714032956077, 6.123233995736766e-17, -0.098017140329560645, -0.19509032201612819, -0.29028467725446216, -0.38268343236508973, -0.4713967368259977, -0.55557023301960196, -0.63439328416364538, -0.70710678118654746, -0.77301045336273699, -0.83146961230254535, -0.88192126434835494, -0.92387953251128674, -0.95694033573220882, -0.98078528040323043, -0.99518472667219682, -1, -0.99518472667219693, -0.98078528040323043, -0.95694033573220894, -0.92387953251128685, -0.88192126434835505, -0.83146961230254546, -0.7730104533627371, -0.70710678118654768, -0.63439328416364593, -0.55557023301960218, -0.47139673682599786, -0.38268343236509034, -0.29028467725446244, -0.19509032201612866, -0.098017140329560451, -1.8369701987210297e-16, 0.09801714032956009, 0.1950903220161283, 0.29028467725446205, 0.38268343236509, 0.47139673682599759, 0.55557023301960184, 0.6343932841636456, 0.70710678118654735, 0.77301045336273666, 0.83146961230254524, 0.88192126434835483, 0.92387953251128652, 0.95694033573220882, 0.98078528040323032, 0.99518472667219693};
+
+// In-register DFT of length 32, in place: for inputs v[j] in natural order,
+// X[k] = sum_j v[j] exp(-+2 pi i jk/32) ends up in v[tf_pos(k)].  32 = 8 x 4:
+// inputs j = 4 j1 + j2, outputs k = k1 + 8 k2; length-8 transforms over j1,
+// rotations W_32^{j2 k1}, length-4 transforms over j2 (no temporary copy of
+// the 32 values, so that two such arrays and the loads fit the registers).
+__device__ __forceinline__ constexpr int tf_pos(int k) { return 4 * (k & 7) + (k >> 3); }
+
+template <bool INV>
+__device__ __forceinline__ void dft32(cpx<float> (&v)[32]) {
+#pragma unroll
+  for (int j2 = 0; j2 < 4; ++j2) {
+    cpx<float> a[8];
+#pragma unroll
+    for (int j1 = 0; j1 < 8; ++j1) a[j1] = v[4 * j1 + j2];
+    motfft::Dft<8, INV, float>::run(a);
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      const int e = 2 * j2 * k1;  // W_32^{j2 k1} = W_64^{2 j2 k1}
+      if (e == 0) {
+        v[4 * k1 + j2] = a[k1];
+      } else {
+        const float cr = (float)Tw64::cs(e), si = INV ? (float)Tw64::sn(e) : -(float)Tw64::sn(e);
+        v[4 * k1 + j2] = motfft::cmul(a[k1], cpx<float>{cr, si});
+      }
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) motfft::Dft<4, INV, float>::run(&v[4 * k1]);
+}
+
+// K_m(w) = sum_{d=1..2S-1} Lambda_{(m-1)S+d} exp(-2 pi i w d / 2S) in FP64 from
+// the stored Lambda (Lambda_L = 0 for L > nl); one thread per (octant point,
+// component, m), all S + 1 frequencies.
+__global__ __launch_bounds__(256) void k_tfft_prep(const float* __restrict__ lamh, cpx<float>* __restrict__ K,
+                                                   long long lcomp, int nl, int M) {
+  constexpr int S = TF_S;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= lcomp * 6 * M) return;
+  const long long lo = id % lcomp;
+  const int c = (int)((id / lcomp) % 6), m = (int)(id / (lcomp * 6)) + 1;
+  double re[S + 1], im[S + 1];
+#pragma unroll
+  for (int w = 0; w <= S; ++w) re[w] = im[w] = 0.0;
+  for (int d = 1; d < 2 * S; ++d) {
+    const int L = (m - 1) * S + d;
+    if (L > nl) break;
+    const double v = (double)lamh[((size_t)(L - 1) * 6 + c) * lcomp + lo];
+#pragma unroll
+    for (int w = 0; w <= S; ++w) {
+      const int e = (w * d) & 63;
+      re[w] += v * tf_cos64[e];
+      im[w] -= v * tf_cos64[(e + 48) & 63];
+    }
+  }
+#pragma unroll
+  for (int w = 0; w <= S; ++w)
+    K[((size_t)((m - 1) * 6 + c) * (S + 1) + w) * lcomp + lo] = cpx<float>{(float)re[w], (float)im[w]};
+}
+
+// LDS index of X_j(2u + h) of point p: the two parities of a half-wave land
+// on different banks
+__device__ __forceinline__ int tf_lds(int j, int h, int u, int p) { return (j * 32 + u) * 64 + h * 32 + (p ^ (h << 4)); }
+
+__global__ __launch_bounds__(192, 3) void k_tfft_far(const cpx<float>* __restrict__ ring, const cpx<float>* __restrict__ K,
+                                                     cpx<float>* __restrict__ far, Geo g, long long n, int M, int nkb,
+                                                     int nlog) {
+  constexpr int S = TF_S;
+  __shared__ cpx<float> xs[3 * 32 * 64];
+  // logical tile: (octant row, kx block, mirror), mirror fastest; tiles go to
+  // the XCDs in contiguous ranges (ids are dealt to the 8 XCDs in turn)
+  const int q8 = (nlog + 7) / 8;
+  const int t = (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8);
+  if (t >= nlog) return;
+  const int mu = t & 3, kb = (t >> 2) % nkb, orow = (t >> 2) / nkb;
+  const int kyc = orow % (g.ny + 1), kzc = orow / (g.ny + 1);
+  const int a = mu >> 1, b = mu & 1;
+  if ((a && (kzc == 0 || kzc == g.nz)) || (b && (kyc == 0 || kyc == g.ny))) return;
+  const int py = 2 * g.ny, pz = 2 * g.nz;
+  const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
+  // transforms: thread (component j, point p, parity h); products: thread
+  // (point p, frequency group fg = 2 j + h), which owns the frequencies
+  // w' = fg + 6 r <= S and their partners 2S - w'
+  const int j = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, p = lane >> 1, h = lane & 1;
+  const int fg = 2 * j + h;
+  const int kx = kb * 32 + p;
+  const bool act = kx <= g.nx;
+  const size_t comp = (size_t)pz * py * g.kxs;
+  const size_t slot_bytes = 3 * comp * sizeof(cpx<float>);
+  const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;
+  // byte offsets below 4 GiB from a wave-uniform base: one ring slot (3
+  // components) and one (m, component) plane of K (S + 1 frequencies; the
+  // plane's base is added in 64 bits)
+  const unsigned roff = act ? (unsigned)(((size_t)j * comp + ((size_t)kz * py + ky) * g.kxs + kx) * sizeof(cpx<float>)) : 0u;
+  const unsigned loff = act ? (unsigned)((((size_t)kzc * (g.ny + 1) + kyc) * g.kxs + kx) * sizeof(cpx<float>)) : 0u;
+  const unsigned lstride = (unsigned)(lcomp * sizeof(cpx<float>));
+  // reflection signs of the xy, xz, yz components at this mirror point
+  const float sxy = b ? -1.f : 1.f, sxz = a ? -1.f : 1.f, syz = sxy * sxz;
+  const long long beta = n / S;
+  const int mmax = (int)(beta + 1 < M ? beta + 1 : M);
+  cpx<float> acc[6][2][3];  // Y_i at w' = fg + 6 r (e = 0) and 2S - w' (e = 1)
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[r][e][i] = cpx<float>{0.f, 0.f};
+  for (int m = 1; m <= mmax; ++m) {
+    // currents of times t0 .. t0 + S - 1 (uniform across the workgroup)
+    const long long t0 = (beta - m) * S + 1;
+    const long long tlo = t0 > n - g.nl + 1 ? t0 : n - g.nl + 1;  // oldest time the ring still holds
+    const long long tfirst = tlo > 0 ? tlo : 0;
+    int sl = (int)(((t0 % g.nl) + g.nl) % g.nl);
+    cpx<float> x[32];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const long long tt = t0 + q;
+      x[q] = cpx<float>{0.f, 0.f};
+      if (tt >= tfirst) {
+        const char* base = (const char*)ring + (size_t)sl * slot_bytes;
+        const cpx<float> v = *(const cpx<float>*)(base + roff);
+        if (act) x[q] = v;
+      }
+      sl = sl + 1 == g.nl ? 0 : sl + 1;
+    }
+    // odd frequencies: x[q] W_64^q, then a 32-point DFT
+#pragma unroll
+    for (int q = 1; q < S; ++q) {
+      const cpx<float> rr = motfft::cmul(x[q], cpx<float>{(float)Tw64::cs(q), -(float)Tw64::sn(q)});
+      x[q] = h ? rr : x[q];
+    }
+    dft32<false>(x);
+    __syncthreads();  // the previous block's reads of xs are done
+#pragma unroll
+    for (int u = 0; u < 32; ++u) xs[tf_lds(j, h, u, p)] = x[tf_pos(u)];
+    __syncthreads();
+    // Y_i(w) += sum_j K_m,ij(w) X_m,j(w): the six components of K_m(w') are
+    // loaded once for w' and its partner 2S - w' (conjugate)
+    const char* Kb = (const char*)(K + (size_t)(m - 1) * 6 * (S + 1) * lcomp);
+    // (opaque per block: the addresses are formed here rather than held in
+    // registers across the loop)
+    unsigned ls = lstride, lof = loff;
+    int fgm = fg;
+    asm volatile("" : "+s"(ls));
+    asm volatile("" : "+v"(lof));
+    asm volatile("" : "+v"(fgm));
+    // two halves of three frequency pairs: the 18 loads of a half are issued
+    // together (no branch between them; w' > S reads w' = S and is dropped)
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      cpx<float> kk[3][6];
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr) {
+        const int wp = fgm + 6 * (3 * hf + rr);
+        const unsigned wl = (unsigned)(wp <= S ? wp : S);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) kk[rr][c] = *(const cpx<float>*)(Kb + (size_t)c * (S + 1) * lstride + (wl * ls + lof));
+      }
+#pragma unroll
+      for (int rr = 0; rr < 3; ++rr) {
+        const int r = 3 * hf + rr;
+        const int wp = fgm + 6 * r;
+        if (wp > S) continue;
+        cpx<float> k6[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) k6[c] = act ? kk[rr][c] : cpx<float>{0.f, 0.f};
+        k6[3] = cpx<float>{k6[3].x * sxy, k6[3].y * sxy};
+        k6[4] = cpx<float>{k6[4].x * sxz, k6[4].y * sxz};
+        k6[5] = cpx<float>{k6[5].x * syz, k6[5].y * syz};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (e == 1 && (wp == 0 || wp == S)) continue;
+          const int w = e ? 2 * S - wp : wp;
+          const float cs = e ? -1.f : 1.f;  // K(2S - w') = conj K(w')
+          cpx<float> xv[3];
+#pragma unroll
+          for (int jj = 0; jj < 3; ++jj) xv[jj] = xs[tf_lds(jj, w & 1, w >> 1, p)];
+          // rows (xx xy xz), (xy yy yz), (xz yz zz)
+          const int ci[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+              const cpx<float> kv = k6[ci[i][jj]];
+              const float ky_ = cs * kv.y;
+              acc[r][e][i].x += kv.x * xv[jj].x - ky_ * xv[jj].y;
+              acc[r][e][i].y += kv.x * xv[jj].y + ky_ * xv[jj].x;
+            }
+        }
+      }
+    }
+  }
+  // Y back through LDS to the transform layout, one inverse per parity, then
+  // y[S + i] = (E(i) - W_64^{-i} O(i)) / 2S: the even lane writes i < 16,
+  // the odd lane i >= 16
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    const int wp = fg + 6 * r;
+    if (wp > S) continue;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      if (e == 1 && (wp == 0 || wp == S)) continue;
+      const int w = e ? 2 * S - wp : wp;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) xs[tf_lds(i, w & 1, w >> 1, p)] = acc[r][e][i];
+    }
+  }
+  __syncthreads();
+  cpx<float> y[32];
+#pragma unroll
+  for (int u = 0; u < 32; ++u) y[u] = xs[tf_lds(j, h, u, p)];
+  dft32<true>(y);
+  const float inv = 1.f / (2 * S);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const cpx<float> lo_ = y[tf_pos(u)], hi_ = y[tf_pos(16 + u)];
+    const cpx<float> send = h ? lo_ : hi_;
+    const cpx<float> recv{__shfl_xor(send.x, 1), __shfl_xor(send.y, 1)};
+    const cpx<float> e = h ? recv : lo_, o = h ? hi_ : recv;
+    // both rotations with literal constants, then the lane's one (a select
+    // of the constants would become a table read)
+    const cpx<float> wo0 = motfft::cmul(o, cpx<float>{(float)Tw64::cs(u), (float)Tw64::sn(u)});
+    const cpx<float> wo1 = motfft::cmul(o, cpx<float>{(float)Tw64::cs(16 + u), (float)Tw64::sn(16 + u)});
+    const cpx<float> wo = h ? wo1 : wo0;
+    if (act)
+      *(cpx<float>*)((char*)far + (size_t)(u + 16 * h) * slot_bytes + roff) =
+          cpx<float>{(e.x - wo.x) * inv, (e.y - wo.y) * inv};
+  }
+}
+
+hipError_t launch_tfft_prep(const float* lamh, void* K, int nl, int nx, int ny, int nz, int kxs, hipStream_t s) {
+  const long long lcomp = (long long)(nz + 1) * (ny + 1) * kxs;
+  const int M = tfft_blocks(nl);
+  const long long cnt = lcomp * 6 * M;
+  hipLaunchKernelGGL(k_tfft_prep, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, lamh, (cpx<float>*)K, lcomp,
+                     nl, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_tfft_far(const void* ring, const void* K, void* far, int nl, long long n, int nx, int ny, int nz,
+                           int kxs, hipStream_t s) {
+  if (n % TF_S != 0 || nl < TF_S) return hipErrorInvalidValue;
+  const Geo g{nx, ny, nz, kxs, nl};
+  const int nkb = (nx + 1 + 31) / 32;
+  const int nlog = (nz + 1) * (ny + 1) * nkb * 4;
+  const unsigned grid = (unsigned)(((nlog + 7) / 8) * 8);
+  hipLaunchKernelGGL(k_tfft_far, dim3(grid), dim3(192), 0, s, (const cpx<float>*)ring, (const cpx<float>*)K,
+                     (cpx<float>*)far, g, n, tfft_blocks(nl), nkb, nlog);
+  return hipGetLastError();
+}
+
 }  // namespace motimpl

@@ -124,6 +124,18 @@ hipError_t launch_mac_recent(const void* ring, const void* lamh, const void* ini
 // P_b -> pblk + (b-2) slots; init_b = iblk + (b-1) slots (zero if iblk is null)
 hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, const void* iblk, int f64,
                             int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s);
+// History by FFTs in time (FP32 ring): time blocks of TF_S steps, transforms
+// of length 2 TF_S.  tfft_blocks(nl) spectra K_m (m = 1..M) of the lag
+// segments Lambda_{(m-1)S+d}, d = 1..2S-1, each at the S+1 frequencies
+// w = 0..S, [m-1][w][component][octant point] complex FP32.
+constexpr int TF_S = 32;
+inline int tfft_blocks(int nl) { return (nl - 1) / TF_S + 1; }
+hipError_t launch_tfft_prep(const float* lamh, void* K, int nl, int nx, int ny, int nz, int kxs, hipStream_t s);
+// far[i] = sum over the time blocks before step n + 1 of the lags they reach,
+// for the S right-hand sides of steps n + 1 + i, i = 0..S-1 (n a multiple of
+// S; ring slots older than n - nl + 1 or before step 0 read as zero)
+hipError_t launch_tfft_far(const void* ring, const void* K, void* far, int nl, long long n, int nx, int ny, int nz,
+                           int kxs, hipStream_t s);
 
 // ---- mot_api.hip: excitation
 hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* out, int nx, int ny, int nz,

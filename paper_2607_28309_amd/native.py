@@ -31,12 +31,12 @@ EXPORTS = (
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
     "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor", "mot_set_regularization",
-    "mot_farfield_static",
+    "mot_farfield_static", "mot_set_history_scheme",
 )
 TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
-PROF_NCLASS = 22
+PROF_NCLASS = 24
 PROF_KINDS = ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue", "z_forward",
-              "history_mac", "z_inverse", "krylov", "excitation", "history_mac_recent")
+              "history_mac", "z_inverse", "krylov", "excitation", "history_mac_recent", "history_far")
 
 
 class MotGrid(ctypes.Structure):
@@ -103,6 +103,7 @@ def _load():
         "mot_autotune": (ctypes.c_int, [vp, i32, ctypes.POINTER(dbl)]),
         "mot_set_predictor": (ctypes.c_int, [vp, i32]),
         "mot_set_regularization": (ctypes.c_int, [vp, dbl, dbl, dbl]),
+        "mot_set_history_scheme": (ctypes.c_int, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -211,9 +212,9 @@ class Context:
             pass
 
     def info(self):
-        out = (ctypes.c_int64 * 8)()
-        self._check(LIB.mot_info(self.h, out, 8), "mot_info")
-        keys = ("nlags", "px", "py", "pz", "kxs", "bytes", "steps", "history_block")
+        out = (ctypes.c_int64 * 9)()
+        self._check(LIB.mot_info(self.h, out, 9), "mot_info")
+        keys = ("nlags", "px", "py", "pz", "kxs", "bytes", "steps", "history_block", "history_scheme")
         return dict(zip(keys, list(out)))
 
     def build_green_spectra(self):
@@ -264,6 +265,12 @@ class Context:
         if len(d) != 3:
             raise ValueError("delta: a number or (d_0, d_1, d_2)")
         self._check(LIB.mot_set_regularization(self.h, *d), "mot_set_regularization")
+
+    def set_history_scheme(self, scheme):
+        """History sums: "auto" (0), "blocked" (1, per-lag multiply-accumulate) or
+        "fft_time" (2, far lags by FFTs in time over blocks of 32 steps)."""
+        code = {"auto": 0, "blocked": 1, "fft_time": 2}.get(scheme, scheme)
+        self._check(LIB.mot_set_history_scheme(self.h, int(code)), "mot_set_history_scheme")
 
     def set_predictor(self, k):
         """Initial guess of the refined solve from the last k solutions (0 = off)."""

@@ -515,7 +515,7 @@ def _trace(name):
         return {k: z[k] for k in z.files}
 
 
-def _march_vs_trace(gpu_lib, name, eps, prec):
+def _march_vs_trace(gpu_lib, name, eps, prec, history="auto"):
     """March the workload of an oracle trace on the GPU (tol 1e-6) and return the
     field error max_n ||J_n - J_n^ref|| / max_n ||J_n^ref|| on the sampled voxels,
     and the largest relative difference of the full norms."""
@@ -530,6 +530,7 @@ def _march_vs_trace(gpu_lib, name, eps, prec):
     c = _ctx(gpu_lib, n, alpha, prec, eps)
     c.set_regularization(tuple(float(v) for v in np.atleast_1d(tr["delta"])) if np.size(tr["delta"]) == 3
                          else float(tr["delta"]))
+    c.set_history_scheme(history)
     c.reset()
     N3 = 3 * math.prod(n)
     einc = torch.empty(N3, dtype=torch.float64, device="cuda")
@@ -546,7 +547,9 @@ def _march_vs_trace(gpu_lib, name, eps, prec):
         den = max(den, float(torch.linalg.vector_norm(ref)))
         nerr = max(nerr, abs(float(torch.linalg.vector_norm(J)) - float(tr["norms"][s])))
     c.close()
-    return num / den, nerr / float(tr["norms"].max())
+    err, nerr = num / den, nerr / float(tr["norms"].max())
+    print(f"[trace] {name} {prec} history {history}: field error {err:.2e}, norm error {nerr:.2e}")
+    return err, nerr
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32_refined"])
@@ -568,14 +571,16 @@ def test_march_pillars80_vs_oracle(gpu_lib, prec):
     assert err <= 1e-4 and nerr <= 1e-4, (err, nerr)
 
 
-@pytest.mark.parametrize("alpha", [1, 2, 4, 8, 16])
-def test_march_nested24_time_step_sweep_vs_oracle(gpu_lib, alpha):
+@pytest.mark.parametrize("alpha,history", [(1, "auto"), (1, "fft_time"), (2, "auto"), (2, "fft_time"), (4, "auto"),
+                                           (8, "auto"), (16, "auto")])
+def test_march_nested24_time_step_sweep_vs_oracle(gpu_lib, alpha, history):
     # the time-step sweep on a 24^3 cut of the 96^3 nested cube (eps_r 6 core
     # and 4 layer, +-5 % noise), dt = alpha dt_CFL over the window of 1600
     # dt_CFL from t = 0 with the regularization of the workloads, FP32 refined,
-    # against the oracle's FP64 march of each alpha (stored traces)
+    # against the oracle's FP64 march of each alpha (stored traces); at
+    # alpha = 1 and 2 (ell = 73 and 37) also with the far lags by FFTs in time
     eps = np.ascontiguousarray(W.CUBE96.eps()[24:48, 24:48, 24:48])
-    err, nerr = _march_vs_trace(gpu_lib, f"nested24_a{alpha}", eps, "f32_refined")
+    err, nerr = _march_vs_trace(gpu_lib, f"nested24_a{alpha}", eps, "f32_refined", history)
     assert err <= 1e-4 and nerr <= 1e-4, (err, nerr)
 
 
