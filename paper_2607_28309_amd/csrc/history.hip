@@ -310,19 +310,23 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
 // currents of steps beta S + 1 .. n' - 1 for step n') are left to the blocked
 // multiply-accumulate above, which takes far as its initial value.
 //
-// Each workgroup takes 32 consecutive frequencies kx of one row (kz, ky) and
-// all three components; thread (component j, point p, parity h) transforms
-// its current at the frequencies w = 2u + h, u = 0..31, as a 32-point DFT of
-// x[q] W_64^{hq} (the two parities split the 64-point transform, whose upper
-// inputs are zero).  The spectra X go through LDS so that the thread of row i
-// forms sum_j K_m,ij X_m,j at its frequencies; after the last block it
-// inverts its parity (a 32-point inverse DFT each), and the two parities of a
-// point combine through a lane exchange:
+// Each workgroup takes 32 consecutive octant frequencies (numbered over the
+// used kx of the octant rows, so that no lane idles on padding columns) at
+// one mirror side, and all three components.  Per earlier block m, thread
+// (component j, point p, parity h) transforms its current at the
+// frequencies w = 2u + h, u = 0..31, as a 32-point DFT of x[q] W_64^{hq}
+// (the two parities split the 64-point transform, whose upper inputs are
+// zero), and the spectra go through LDS to thread (point p, group
+// fg = 2j + h), which owns the frequencies w' = fg + 6r <= S and their
+// partners 2S - w': it loads the six components of K_m(w') once for both
+// (K_m is real in time, so K_m(2S - w) = conj K_m(w) and only w = 0..S are
+// stored) and accumulates Y_i = sum_j K_m,ij X_m,j.  After the last block Y
+// goes back through LDS, each parity is inverted (a 32-point inverse DFT),
+// and the two parities of a point combine through a lane exchange:
 //   y[S + i] = (E(i) - W_64^{-i} O(i)) / 2S.
-// K_m is real in time, so K_m(2S - w) = conj K_m(w) and only w = 0..S are
-// stored.  Lambda is shared by the four mirror points of an octant frequency
-// (reflection signs as in mac3); the four workgroups of one octant row and
-// kx range are neighbours in the XCD-aware order, so they read K through one L2.
+// K is shared by the four mirror points of an octant frequency (reflection
+// signs as in mac3); the four workgroups of one tile are neighbours in the
+// XCD-aware order, so they read K through one L2.
 
 struct Tw64 {
   // cos(2 pi j / 64); sin(2 pi j / 64) = cos(2 pi (j - 16) / 64)
@@ -397,28 +401,43 @@ __global__ __launch_bounds__(256) void k_tfft_prep(const float* __restrict__ lam
 __device__ __forceinline__ int tf_lds(int j, int h, int u, int p) { return (j * 32 + u) * 64 + h * 32 + (p ^ (h << 4)); }
 
 __global__ __launch_bounds__(192, 3) void k_tfft_far(const cpx<float>* __restrict__ ring, const cpx<float>* __restrict__ K,
-                                                     cpx<float>* __restrict__ far, Geo g, long long n, int M, int nkb,
-                                                     int nlog) {
+                                                     cpx<float>* __restrict__ far, Geo g, long long n, int M, int nlog) {
   constexpr int S = TF_S;
   __shared__ cpx<float> xs[3 * 32 * 64];
-  // logical tile: (octant row, kx block, mirror), mirror fastest; tiles go to
-  // the XCDs in contiguous ranges (ids are dealt to the 8 XCDs in turn)
+  // logical tile: (32 consecutive octant frequencies in the numbering
+  // f = (kzc (ny+1) + kyc)(nx+1) + kx over the used kx, mirror), mirror
+  // fastest; tiles go to the XCDs in contiguous ranges (ids are dealt to
+  // the 8 XCDs in turn)
   const int q8 = (nlog + 7) / 8;
   const int t = (int)(blockIdx.x % 8) * q8 + (int)(blockIdx.x / 8);
   if (t >= nlog) return;
-  const int mu = t & 3, kb = (t >> 2) % nkb, orow = (t >> 2) / nkb;
-  const int kyc = orow % (g.ny + 1), kzc = orow / (g.ny + 1);
-  const int a = mu >> 1, b = mu & 1;
-  if ((a && (kzc == 0 || kzc == g.nz)) || (b && (kyc == 0 || kyc == g.ny))) return;
+  const int mu = t & 3, a = mu >> 1, b = mu & 1;
+  const int kxu = g.nx + 1;
+  const long long ftot = (long long)(g.nz + 1) * (g.ny + 1) * kxu;
+  const long long f0 = (long long)(t >> 2) * 32;
+  {
+    // a tile whose rows are all duplicate mirrors (kz or ky on its own
+    // mirror plane) has nothing to do
+    const long long f1 = f0 + 31 < ftot ? f0 + 31 : ftot - 1;
+    bool any = false;
+    for (long long r = f0 / kxu; r <= f1 / kxu; ++r) {
+      const int yc = (int)(r % (g.ny + 1)), zc = (int)(r / (g.ny + 1));
+      any = any || !((a && (zc == 0 || zc == g.nz)) || (b && (yc == 0 || yc == g.ny)));
+    }
+    if (!any) return;
+  }
   const int py = 2 * g.ny, pz = 2 * g.nz;
-  const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
   // transforms: thread (component j, point p, parity h); products: thread
   // (point p, frequency group fg = 2 j + h), which owns the frequencies
   // w' = fg + 6 r <= S and their partners 2S - w'
   const int j = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63, p = lane >> 1, h = lane & 1;
   const int fg = 2 * j + h;
-  const int kx = kb * 32 + p;
-  const bool act = kx <= g.nx;
+  const long long f = f0 + p;
+  const long long orow = f / kxu;
+  const int kx = (int)(f - orow * kxu);
+  const int kyc = (int)(orow % (g.ny + 1)), kzc = (int)(orow / (g.ny + 1));
+  const bool act = f < ftot && !((a && (kzc == 0 || kzc == g.nz)) || (b && (kyc == 0 || kyc == g.ny)));
+  const int kz = a ? pz - kzc : kzc, ky = b ? py - kyc : kyc;
   const size_t comp = (size_t)pz * py * g.kxs;
   const size_t slot_bytes = 3 * comp * sizeof(cpx<float>);
   const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;
@@ -444,18 +463,27 @@ __global__ __launch_bounds__(192, 3) void k_tfft_far(const cpx<float>* __restric
     const long long t0 = (beta - m) * S + 1;
     const long long tlo = t0 > n - g.nl + 1 ? t0 : n - g.nl + 1;  // oldest time the ring still holds
     const long long tfirst = tlo > 0 ? tlo : 0;
-    int sl = (int)(((t0 % g.nl) + g.nl) % g.nl);
+    const int q0 = (int)(tfirst - t0);  // first q the ring holds (0..S)
+    // slot of time t0 + q: sl0 + q, wrapped once at q = qw
+    const int sl0 = (int)(((t0 % g.nl) + g.nl) % g.nl), qw = g.nl - sl0;
+    const char* rb = (const char*)ring;
+    // wave-uniform slot address plus the lane's 32-bit offset; idle lanes
+    // (past the last frequency, or on a duplicate mirror) read offset 0 and
+    // store nothing
+    // every slot read is a valid one; times the ring no longer holds (or
+    // before step 0) are zeroed afterwards, on a branch taken only by the
+    // first blocks of a march
     cpx<float> x[32];
+    const char* pq = rb + (size_t)sl0 * slot_bytes;
 #pragma unroll
     for (int q = 0; q < S; ++q) {
-      const long long tt = t0 + q;
-      x[q] = cpx<float>{0.f, 0.f};
-      if (tt >= tfirst) {
-        const char* base = (const char*)ring + (size_t)sl * slot_bytes;
-        const cpx<float> v = *(const cpx<float>*)(base + roff);
-        if (act) x[q] = v;
-      }
-      sl = sl + 1 == g.nl ? 0 : sl + 1;
+      x[q] = *(const cpx<float>*)(pq + roff);
+      pq = q + 1 == qw ? rb : pq + slot_bytes;
+    }
+    if (q0 > 0) {
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+        if (q < q0) x[q] = cpx<float>{0.f, 0.f};
     }
     // odd frequencies: x[q] W_64^q, then a 32-point DFT
 #pragma unroll
@@ -482,6 +510,7 @@ __global__ __launch_bounds__(192, 3) void k_tfft_far(const cpx<float>* __restric
     // together (no branch between them; w' > S reads w' = S and is dropped)
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf) {
+      // (idle lanes read offset 0)
       cpx<float> kk[3][6];
 #pragma unroll
       for (int rr = 0; rr < 3; ++rr) {
@@ -497,7 +526,7 @@ __global__ __launch_bounds__(192, 3) void k_tfft_far(const cpx<float>* __restric
         if (wp > S) continue;
         cpx<float> k6[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) k6[c] = act ? kk[rr][c] : cpx<float>{0.f, 0.f};
+        for (int c = 0; c < 6; ++c) k6[c] = kk[rr][c];
         k6[3] = cpx<float>{k6[3].x * sxy, k6[3].y * sxy};
         k6[4] = cpx<float>{k6[4].x * sxz, k6[4].y * sxz};
         k6[5] = cpx<float>{k6[5].x * syz, k6[5].y * syz};
@@ -515,10 +544,13 @@ __global__ __launch_bounds__(192, 3) void k_tfft_far(const cpx<float>* __restric
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) {
+              // four multiply-adds per complex product, accumulated in order
               const cpx<float> kv = k6[ci[i][jj]];
               const float ky_ = cs * kv.y;
-              acc[r][e][i].x += kv.x * xv[jj].x - ky_ * xv[jj].y;
-              acc[r][e][i].y += kv.x * xv[jj].y + ky_ * xv[jj].x;
+              acc[r][e][i].x = fmaf(kv.x, xv[jj].x, acc[r][e][i].x);
+              acc[r][e][i].x = fmaf(-ky_, xv[jj].y, acc[r][e][i].x);
+              acc[r][e][i].y = fmaf(kv.x, xv[jj].y, acc[r][e][i].y);
+              acc[r][e][i].y = fmaf(ky_, xv[jj].x, acc[r][e][i].y);
             }
         }
       }
@@ -576,11 +608,12 @@ hipError_t launch_tfft_far(const void* ring, const void* K, void* far, int nl, l
                            int kxs, hipStream_t s) {
   if (n % TF_S != 0 || nl < TF_S) return hipErrorInvalidValue;
   const Geo g{nx, ny, nz, kxs, nl};
-  const int nkb = (nx + 1 + 31) / 32;
-  const int nlog = (nz + 1) * (ny + 1) * nkb * 4;
+  const long long ftot = (long long)(nz + 1) * (ny + 1) * (nx + 1);
+  const long long nlog = (ftot + 31) / 32 * 4;
+  if (nlog > (1LL << 30)) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(((nlog + 7) / 8) * 8);
   hipLaunchKernelGGL(k_tfft_far, dim3(grid), dim3(192), 0, s, (const cpx<float>*)ring, (const cpx<float>*)K,
-                     (cpx<float>*)far, g, n, tfft_blocks(nl), nkb, nlog);
+                     (cpx<float>*)far, g, n, tfft_blocks(nl), (int)nlog);
   return hipGetLastError();
 }
 

@@ -211,9 +211,9 @@ int dmalloc(mot_ctx* c, void** p, size_t bytes);
 // Far lags by FFTs in time: possible with an FP32 ring of at least TF_S
 // lags; chosen by default from TF_AUTO_LAGS lags on.  The per-lag
 // multiply-accumulate does O(nl) multiply-adds per frequency and step, the
-// transforms O(nl / TF_S) blocks of 2 TF_S frequencies, but below ~128 lags
-// the blocked pass is as fast or faster on the 96^3 cube (measured: ell 289
-// 0.94 against 1.10 ms of history per step, 146 0.67 / 0.70, 74 0.56 / 0.51).
+// transforms O(nl / TF_S) blocks of 2 TF_S frequencies, but below ~100 lags
+// the blocked pass is as fast on the 96^3 cube (measured history time per
+// step: ell 289 0.81 against 1.15 ms, 146 0.59 / 0.71, 74 0.52 / 0.50).
 constexpr int TF_AUTO_LAGS = 128;
 // (the far kernel addresses one ring slot and one plane of K with 32-bit
 // byte offsets)
