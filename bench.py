@@ -57,6 +57,11 @@ def algorithmic_bytes(kind, n, t_bytes, io_bytes, nvalid, blk=1):
         "z_forward": b + f,
         "history_mac": nvalid * (f + lam) + blk * f,
         "z_inverse": f + b,
+        # far lags by FFTs in time, at a block start with nvalid earlier
+        # blocks of blk steps in reach: their currents, the lag-segment
+        # spectra (blk + 1 frequencies of the 6 components, complex), and
+        # the far parts of the next blk right-hand sides
+        "history_far": nvalid * blk * f + nvalid * (blk + 1) * 2 * lam + blk * f,
     }.get(kind)
 
 
@@ -452,6 +457,30 @@ def _cpu_name():
     return "unknown"
 
 
+def counter_summary(path, counter):
+    """Per-kernel averages of one rocprofv3 --pmc counter (KiB per dispatch)
+    from the counter_collection.csv files under path, keyed "name|grid size"
+    (one kernel runs on the grids of several workloads).  Dispatches launched
+    behind a closed convergence gate end at once and move almost nothing:
+    a dispatch counts when its value exceeds 20 % of the kernel's median."""
+    import csv
+    import glob
+    import statistics
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") == counter:
+                key = f'{r["Kernel_Name"]}|{r.get("Grid_Size", "")}'
+                per.setdefault(key, []).append(float(r["Counter_Value"]))
+    out = {}
+    for k, vs in per.items():
+        med = statistics.median(vs)
+        kept = [v for v in vs if v > 0.2 * med] or vs
+        out[k] = {"kib": statistics.mean(kept), "dispatches": len(kept), "all_dispatches": len(vs)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,7 +516,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy kernel three times "
                          "(reference for the HBM traffic counters) and exit")
+    ap.add_argument("--counter-summary", nargs=3, metavar=("DIR", "COUNTER", "OUT"),
+                    help="reduce the rocprofv3 --pmc csv output under DIR to per-kernel averages of COUNTER "
+                         "(KiB per dispatch), write them to OUT as JSON and exit (no GPU)")
     args = ap.parse_args()
+    if args.counter_summary:
+        d, cnt, out = args.counter_summary
+        json.dump(counter_summary(d, cnt), open(out, "w"), indent=1)
+        return
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU path only; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)

@@ -24,6 +24,9 @@ def test_algorithmic_bytes_pillars():
     assert bench.algorithmic_bytes("y_forward", n, 4, 4, 52) == a + b
     f = 3 * 96 * 640 * 321 * 8
     assert bench.algorithmic_bytes("history_mac", n, 4, 4, 52, blk=8) == 52 * (f + lam) + 8 * f
+    # far lags by FFTs in time, two earlier blocks of 32 steps: 64 spectra
+    # read, 2 x 33 frequencies of the complex lag-segment spectra, 32 written
+    assert bench.algorithmic_bytes("history_far", n, 4, 4, 2, blk=32) == 64 * f + 2 * 33 * 2 * lam + 32 * f
 
 
 def test_measured_traffic_lookup():
@@ -46,3 +49,21 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "single-GPU" in r.stderr
+
+
+def test_counter_summary(tmp_path):
+    # per-kernel averages of a --pmc counter; dispatches under 20 % of the
+    # kernel's median (behind a closed convergence gate) are left out
+    d = tmp_path / "pmc" / "host"
+    d.mkdir(parents=True)
+    rows = [("k_a", 100.0), ("k_a", 110.0), ("k_a", 1.0), ("k_b", 50.0)]
+    with open(d / "run_counter_collection.csv", "w") as f:
+        f.write("Kernel_Name,Grid_Size,Counter_Name,Counter_Value\n")
+        for k, v in rows:
+            f.write(f"{k},256,FETCH_SIZE,{v}\n")
+        f.write("k_a,256,WRITE_SIZE,999\n")
+        f.write("k_a,512,FETCH_SIZE,7\n")
+    out = bench.counter_summary(str(tmp_path / "pmc"), "FETCH_SIZE")
+    assert out["k_a|256"]["kib"] == 105.0 and out["k_a|256"]["dispatches"] == 2
+    assert out["k_a|256"]["all_dispatches"] == 3
+    assert out["k_b|256"]["kib"] == 50.0 and out["k_a|512"]["kib"] == 7.0
