@@ -254,6 +254,16 @@ int mot_set_predictor(mot_ctx* ctx, int32_t k);
  * Errors: MOT_EINVAL (NULL, a value not finite, 1/2 + d0 <= 0), MOT_ENOMEM. */
 int mot_set_regularization(mot_ctx* ctx, double d0, double d1, double d2);
 
+/* TFQMR (the solver of Eq. 3 at every step, Sec. II) breaks down when
+ * rho = r~^T r or sigma = r~^T A u vanishes.  By default only an exact zero
+ * counts (t = 0); with t > 0 the solver also stops when |rho| or |sigma| is at
+ * most t |b|^2 (|b| of the solve's right-hand side): a near-breakdown guard,
+ * and the way to make the breakdown exit happen on purpose (failure
+ * injection: a huge t ends every solve with MOT_EBREAKDOWN at its first
+ * reduction, mot_step still advances the history).  Applies from the next
+ * solve.  Errors: MOT_EINVAL (NULL, t negative or not finite). */
+int mot_set_breakdown_tolerance(mot_ctx* ctx, double t);
+
 /* How history_update evaluates sum_k Lambda_k J^_{n+1-k}, the history
  * right-hand side that dominates at small time steps (Sec. III-A, small
  * time-step regime; Sec. III-B evaluates it with an FFT-based

@@ -68,7 +68,10 @@ __device__ void post_op(double* scal, int post) {
     }
     case POST_ALPHA: {  // alpha = rho / sigma; d coefficient theta^2 eta / alpha
       const double sigma = scal[S_SIGMA], rho = scal[S_RHO];
-      if (sigma == 0.0 || rho == 0.0 || !isfinite(sigma)) {
+      // breakdown: rho or sigma zero, or within the near-breakdown
+      // tolerance of zero (relative to |b|^2; 0 by default)
+      const double bd = scal[S_BDTOL] * scal[S_B2];
+      if (fabs(sigma) <= bd || fabs(rho) <= bd || !isfinite(sigma)) {
         scal[S_FLAG] = 1.0;
         scal[S_ALPHA] = 0.0;
         scal[S_DCOEF] = 0.0;
@@ -109,7 +112,7 @@ __device__ void post_op(double* scal, int post) {
     }
     case POST_BETA: {  // beta = rho'/rho, rho = rho'; end of an iteration: convergence bound
       const double rn = scal[S_RHONEW], rho = scal[S_RHO];
-      if (rho == 0.0) {
+      if (fabs(rho) <= scal[S_BDTOL] * scal[S_B2]) {
         scal[S_FLAG] = 1.0;
         scal[S_BETA] = 0.0;
       } else {
@@ -219,9 +222,10 @@ __global__ __launch_bounds__(FIN_THREADS) void k_reduce2(const double* __restric
   }
 }
 
-__global__ void k_solver_setup(double* scal, double tol, double max_iter, double bound_only) {
+__global__ void k_solver_setup(double* scal, double tol, double max_iter, double bound_only, double bdtol) {
   if (threadIdx.x != 0) return;
   scal[S_BOUND_ONLY] = bound_only;
+  scal[S_BDTOL] = bdtol;
   scal[S_TOL] = tol;
   scal[S_MAXIT] = max_iter;
   scal[S_ITER] = 0.0;
@@ -421,8 +425,9 @@ hipError_t reduce_post2(const double* partials, double* scal, int slot1, int pos
                      nparts, stride);
   return hipGetLastError();
 }
-hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only) {
-  hipLaunchKernelGGL(k_solver_setup, dim3(1), dim3(64), 0, s, scal, tol, (double)max_iter, bound_only ? 1.0 : 0.0);
+hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only, double breakdown_tol) {
+  hipLaunchKernelGGL(k_solver_setup, dim3(1), dim3(64), 0, s, scal, tol, (double)max_iter, bound_only ? 1.0 : 0.0,
+                     breakdown_tol);
   return hipGetLastError();
 }
 template <typename V>

@@ -92,6 +92,7 @@ struct mot_ctx {
   // zero: the unregularized operator)
   double dreg[3];
   double* jprev2;      // the current pushed before the last one (history term of dreg[2])
+  double bd_tol;       // TFQMR near-breakdown tolerance (0: rho or sigma exactly zero)
   double* ffpart;      // scratch: far-field block partials
   size_t ffpart_n;
   int tune[2][TUNE_N]; // tile variants of the FFT passes (0 or 1)
@@ -466,7 +467,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   double* sc = c->scal;
   const bool f64 = sizeof(V) == 8;
   const motfft::Gate RUN{sc + S_DONE, 1}, CHK{sc + S_DONE, 2};
-  HTP(K_KRY, f64, solver_setup(sc, tol, max_iter, s, bound_only));
+  HTP(K_KRY, f64, solver_setup(sc, tol, max_iter, s, bound_only, c->bd_tol));
   // w = u = r~ = r0 = b, d = 0, x = 0 (also for b = 0)
   if constexpr (sizeof(V) == 4) {
     if (b64) {
@@ -1610,6 +1611,12 @@ int mot_set_history_scheme(mot_ctx* c, int32_t scheme) {
   // has begun finishes with the per-lag multiply-accumulate
   c->tf_beta = -1;
   return tf_configure(c);
+}
+
+int mot_set_breakdown_tolerance(mot_ctx* c, double t) {
+  if (!c || !std::isfinite(t) || t < 0.0) return MOT_EINVAL;
+  c->bd_tol = t;
+  return MOT_OK;
 }
 
 int mot_set_graphs(mot_ctx* c, int32_t on) {

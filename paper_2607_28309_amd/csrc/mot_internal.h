@@ -42,6 +42,7 @@ enum Slot {
   S_STATUS,
   S_RELRES,
   S_NMV,
+  S_BDTOL,  // near-breakdown tolerance: |rho| or |sigma| <= S_BDTOL |b|^2 (0: exact zero only)
   S_NSLOT
 };
 static_assert(S_CHECK == S_DONE + 1, "gates read done and check as a pair");
@@ -74,7 +75,8 @@ hipError_t reduce_post2(const double* partials, double* scal, int slot1, int pos
 // Start of a solve: tol, max_iter and the convergence state (iteration 0, not
 // done); bound_only: stop when the quasi-residual bound passes (for inner
 // solves whose result an outer residual checks).
-hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only = false);
+hipError_t solver_setup(double* scal, double tol, int max_iter, hipStream_t s, bool bound_only = false,
+                        double breakdown_tol = 0.0);
 // x += scal[slot] d
 template <typename V> hipError_t vec_axpy_scal(V* x, const V* d, const double* coef, long long n, hipStream_t s);
 // Initial guess from earlier solutions (at most PRED_MAX pairs J_i, Z0 J_i).
@@ -127,7 +129,7 @@ hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void
 // History by FFTs in time (FP32 ring): time blocks of TF_S steps, transforms
 // of length 2 TF_S.  tfft_blocks(nl) spectra K_m (m = 1..M) of the lag
 // segments Lambda_{(m-1)S+d}, d = 1..2S-1, each at the S+1 frequencies
-// w = 0..S, [m-1][w][component][octant point] complex FP32.
+// w = 0..S, [m-1][component][w][octant point] complex FP32.
 constexpr int TF_S = 32;
 inline int tfft_blocks(int nl) { return (nl - 1) / TF_S + 1; }
 hipError_t launch_tfft_prep(const float* lamh, void* K, int nl, int nx, int ny, int nz, int kxs, hipStream_t s);

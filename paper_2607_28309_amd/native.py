@@ -31,7 +31,7 @@ EXPORTS = (
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
     "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor", "mot_set_regularization",
-    "mot_farfield_static", "mot_set_history_scheme",
+    "mot_farfield_static", "mot_set_history_scheme", "mot_set_breakdown_tolerance",
 )
 TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
 PROF_NCLASS = 24
@@ -104,6 +104,7 @@ def _load():
         "mot_set_predictor": (ctypes.c_int, [vp, i32]),
         "mot_set_regularization": (ctypes.c_int, [vp, dbl, dbl, dbl]),
         "mot_set_history_scheme": (ctypes.c_int, [vp, i32]),
+        "mot_set_breakdown_tolerance": (ctypes.c_int, [vp, dbl]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -271,6 +272,10 @@ class Context:
         "fft_time" (2, far lags by FFTs in time over blocks of 32 steps)."""
         code = {"auto": 0, "blocked": 1, "fft_time": 2}.get(scheme, scheme)
         self._check(LIB.mot_set_history_scheme(self.h, int(code)), "mot_set_history_scheme")
+
+    def set_breakdown_tolerance(self, t):
+        """TFQMR stops as broken down when |rho| or |sigma| <= t |b|^2 (0: exact zero only)."""
+        self._check(LIB.mot_set_breakdown_tolerance(self.h, float(t)), "mot_set_breakdown_tolerance")
 
     def set_predictor(self, k):
         """Initial guess of the refined solve from the last k solutions (0 = off)."""

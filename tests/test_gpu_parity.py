@@ -584,6 +584,50 @@ def test_march_nested24_time_step_sweep_vs_oracle(gpu_lib, alpha, history):
     assert err <= 1e-4 and nerr <= 1e-4, (err, nerr)
 
 
+@pytest.mark.parametrize("prec,expect", [("f64", "MOT_EBREAKDOWN"), ("f32", "MOT_EBREAKDOWN"),
+                                         ("f32_refined", "MOT_ENOCONV")])
+def test_forced_breakdown_is_reported_and_recoverable(gpu_lib, prec, expect):
+    # failure injection from the host: a near-breakdown tolerance that no
+    # reduction passes ends every TFQMR solve at its first reduction.  The
+    # FP64 and FP32 solves report MOT_EBREAKDOWN; the refined solve, whose
+    # inner solves all break down, gives up after its refinement sweeps with
+    # MOT_ENOCONV.  The history still advances, and with the tolerance back at
+    # 0 the march is bit-identical to that of a context that never broke down.
+    import torch
+    n, alpha = (16, 6, 4), 4
+    eps = _eps(n)
+    p = W.pulse(20)
+    L = basis.cdt_from_alpha(alpha)
+    c = _ctx(gpu_lib, n, alpha, prec, eps)
+    ref = _ctx(gpu_lib, n, alpha, prec, eps)
+    N3 = 3 * math.prod(n)
+    E = torch.empty(N3, dtype=torch.float64, device="cuda")
+    J = torch.empty_like(E)
+    Jr = torch.empty_like(E)
+    code = getattr(gpu_lib, expect)
+    c.set_breakdown_tolerance(1e300)
+    c.reset()
+    for s in range(3):
+        c.excitation(p, (30 + s) * L, E)
+        rc, _ = c.step(E, J, tol=1e-8, max_iter=60, allow=(code,))
+        assert rc == code, (s, rc)
+    assert c.info()["steps"] == 3
+    with pytest.raises(gpu_lib.MotError) as ei:
+        c.set_breakdown_tolerance(-1.0)
+    assert ei.value.status == gpu_lib.MOT_EINVAL
+    c.set_breakdown_tolerance(0.0)
+    c.reset()
+    ref.reset()
+    tol = 1e-5 if prec == "f32" else 1e-8  # what a plain FP32 solve reaches
+    for s in range(4):
+        c.excitation(p, (30 + s) * L, E)
+        assert c.step(E, J, tol=tol)[0] == 0
+        assert ref.step(E, Jr, tol=tol)[0] == 0
+        assert torch.equal(J, Jr), s
+    c.close()
+    ref.close()
+
+
 def test_out_of_memory_is_reported(gpu_lib):
     # the largest grid the transforms support at dt = dt_CFL needs ell = 1359
     # history spectra (terabytes): creation fails with MOT_ENOMEM, frees what
