@@ -121,6 +121,34 @@ def test_adjoint_march_vs_oracle(gpu_lib):
     assert _rel(_np(lam).reshape(lam_ref.shape), lam_ref) <= 1e-7
 
 
+_ADJ_REF = {}
+
+
+@pytest.mark.parametrize("history", ["blocked", "fft_time"])
+def test_adjoint_march_fp32_ring_vs_oracle(gpu_lib, history):
+    # the adjoint march on an FP32 history ring (refined solves), ell = 49 and
+    # 72 backward steps: with FFTs in time its far lags reach two earlier
+    # blocks of 32 steps; the FP32 ring bounds the agreement (1e-5)
+    import torch
+    n, alpha, nt = (24, 12, 6), 1, 72
+    eps = _eps(n, 83)
+    c = _ctx(gpu_lib, n, alpha, eps, prec="f32_refined")
+    nl = c.info()["nlags"]
+    assert nl >= 33
+    g = np.random.default_rng(84).standard_normal((nt, 3) + eps.shape)
+    if nl not in _ADJ_REF:
+        _ADJ_REF[nl] = OA.adjoint_march(eps, green.green_all(*n, nl, alpha=alpha), g, tol=1e-12)
+    lam_ref = _ADJ_REF[nl]
+    c.set_history_scheme(history)
+    c.set_adjoint(True)
+    c.reset()
+    lam = torch.empty((nt, 3 * eps.size), dtype=torch.float64, device="cuda")
+    for k in range(nt - 1, -1, -1):
+        c.step(_t(g[k].ravel()), lam[k], tol=1e-9, stats=False)
+    c.set_adjoint(False)
+    assert _rel(_np(lam).reshape(lam_ref.shape), lam_ref) <= 1e-5
+
+
 def test_history_gfield_vs_oracle(gpu_lib):
     import torch
     from oracle import operators
