@@ -247,11 +247,23 @@ template <int M, int R, int... Rest> struct FirstRadix<M, RadixList<R, Rest...>>
 // through an LDS buffer of M * np reals (half the bytes of a complex buffer,
 // so twice the pencils fit a CU's LDS; four barriers per exchange instead of
 // two).  The registers a phase reads into hold values already written out.
-template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, typename L, bool SPLIT = false>
+// LDS slot of element e of pencil p in an exchange buffer of row stride np.
+// SW = 1: the pencil index is XOR-swizzled by bit 5 of the element (p ^ 2
+// when it is set).  Lanes that step the element by 4 (the scattered writes of
+// radix-4 stages) put elements 32 apart on the same banks; the swizzle moves
+// one of each such pair to another pencil's banks.  Needs a pencil count that
+// is a multiple of 4 (p ^ 2 stays a pencil of the workgroup).
+template <int SW>
+__device__ __forceinline__ int lslot(int e, int p, int np) {
+  return e * np + (SW ? (p ^ (((e >> 5) & 1) << 1)) : p);
+}
+
+template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, typename L, bool SPLIT = false,
+          int SW = 0>
 struct Stages;
 
-template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, int R, int... Rest, bool SPLIT>
-struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>, SPLIT> {
+template <typename T, int M, int TJ, bool INV, int NS, bool HIN, bool HOUT, int R, int... Rest, bool SPLIT, int SW>
+struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>, SPLIT, SW> {
   template <typename Store>
   static __device__ __forceinline__ void run(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt,
                                              int np, Store&& store) {
@@ -298,13 +310,13 @@ struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>, SPLIT> {
           const int j = jt + t * TJ;
           const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-          for (int r = 0; r < R; ++r) lds[(base + r * NS) * np + p] = v[t * R + r];
+          for (int r = 0; r < R; ++r) lds[lslot<SW>(base + r * NS, p, np)] = v[t * R + r];
         }
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < B2; ++t)
 #pragma unroll
-          for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[(jt + t * TJ + r * MR2) * np + p];
+          for (int r = 0; r < R2; ++r) v[t * R2 + r] = lds[lslot<SW>(jt + t * TJ + r * MR2, p, np)];
         __syncthreads();
       } else {
         T* ldr = reinterpret_cast<T*>(lds);
@@ -315,14 +327,15 @@ struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>, SPLIT> {
             const int j = jt + t * TJ;
             const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-            for (int r = 0; r < R; ++r) ldr[(base + r * NS) * np + p] = part ? v[t * R + r].y : v[t * R + r].x;
+            for (int r = 0; r < R; ++r)
+              ldr[lslot<SW>(base + r * NS, p, np)] = part ? v[t * R + r].y : v[t * R + r].x;
           }
           __syncthreads();
 #pragma unroll
           for (int t = 0; t < B2; ++t)
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
-              const T val = ldr[(jt + t * TJ + r * MR2) * np + p];
+              const T val = ldr[lslot<SW>(jt + t * TJ + r * MR2, p, np)];
               if (part)
                 v[t * R2 + r].y = val;
               else
@@ -331,7 +344,7 @@ struct Stages<T, M, TJ, INV, NS, HIN, HOUT, RadixList<R, Rest...>, SPLIT> {
           __syncthreads();
         }
       }
-      Stages<T, M, TJ, INV, NS * R, false, HOUT, RadixList<Rest...>, SPLIT>::run(v, lds, tw, p, jt, np, store);
+      Stages<T, M, TJ, INV, NS * R, false, HOUT, RadixList<Rest...>, SPLIT, SW>::run(v, lds, tw, p, jt, np, store);
     }
   }
 };
@@ -391,11 +404,11 @@ __device__ __forceinline__ void load_first(cpx<T>* v, int p, int jt, Load&& elem
     for (int r = 0; r < (HIN ? R / 2 : R); ++r) v[t * R + r] = elem(p, jt, t * PI::TJ + r * (M / R));
 }
 
-template <typename T, int M, bool INV, bool HIN, bool HOUT, bool SPLIT = false, typename Store>
+template <typename T, int M, bool INV, bool HIN, bool HOUT, bool SPLIT = false, int SW = 0, typename Store>
 __device__ __forceinline__ void run_fft(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw, int p, int jt, int np,
                                         Store&& store) {
   using PI = PlanInfo<M>;
-  Stages<T, M, PI::TJ, INV, 1, HIN, HOUT, typename PI::list, SPLIT>::run(v, lds, tw, p, jt, np, store);
+  Stages<T, M, PI::TJ, INV, 1, HIN, HOUT, typename PI::list, SPLIT, SW>::run(v, lds, tw, p, jt, np, store);
 }
 
 }  // namespace motfft

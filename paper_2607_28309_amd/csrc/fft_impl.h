@@ -43,6 +43,9 @@ template <typename T, int M, int V = 0> struct XCfg {
   static constexpr int NP = V == 0 ? NP0 : (NP0 >= 4 ? 3 * (NP0 / 4) : cmax(1, NP0 / 2));
   static constexpr int NPS = NP + 1;
   static constexpr int BLOCK = NP * TJ;
+  // swizzled exchange slots (lslot) for FP32 when the row count allows them
+  // (FP32 products 0.368 -> 0.362 ms at 320x320x48; FP64 unchanged)
+  static constexpr int SW = sizeof(T) == 4 && NP % 4 == 0 ? 1 : 0;
   // FP64: the twiddle tables are read from global memory (L1/L2) instead
   // of LDS, which leaves room for more rows per CU
   static constexpr bool TWG = sizeof(T) == 8;

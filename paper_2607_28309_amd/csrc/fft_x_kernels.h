@@ -227,13 +227,12 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
     load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
     load_table<cpx<T>, M + 1, C::BLOCK>(twl + M, tw2_g);
   }
-  run_fft<T, M, false, HIN, false>(v, lds, tw, p, jt, NPS,
-                                   [&](int pp, int, int u, cpx<T> val) { lds[(jt + u) * NPS + pp] = val; });
+  run_fft<T, M, false, HIN, false, false, C::SW>(
+      v, lds, tw, p, jt, NPS, [&](int pp, int, int u, cpx<T> val) { lds[lslot<C::SW>(jt + u, pp, NPS)] = val; });
   __syncthreads();
   if (valid) {
     // bins k = jt + TJ i of row p (and k = M by lane jt = 0)
     cpx<T>* dst = out + (size_t)grow * kxs + jt;
-    const cpx<T>* zr = lds + p;
     auto unpack = [&](cpx<T> zk, cpx<T> zm, cpx<T> w) {
       // E = (zk + conj zm)/2, O = -i/2 (zk - conj zm), X = E + w O
       const cpx<T> ev{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
@@ -244,9 +243,9 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
     for (int i = 0; i < E; ++i) {
       const int k = jt + TJ * i;
       const int m = i == 0 ? (jt == 0 ? 0 : M - jt) : M - k;
-      dst[TJ * i] = unpack(zr[k * NPS], zr[m * NPS], tw2[k]);
+      dst[TJ * i] = unpack(lds[lslot<C::SW>(k, p, NPS)], lds[lslot<C::SW>(m, p, NPS)], tw2[k]);
     }
-    if (jt == 0) dst[M] = unpack(zr[0], zr[0], tw2[M]);
+    if (jt == 0) dst[M] = unpack(lds[lslot<C::SW>(0, p, NPS)], lds[lslot<C::SW>(0, p, NPS)], tw2[M]);
   }
   if constexpr (KM == KRY_HALF0) {
     __syncthreads();  // the unpack's LDS reads are done: LDS holds the sums
@@ -264,6 +263,9 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g, Gate gate, Krylov kry) {
   using C = XCfg<T, M, V>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
+  // the inverse keeps the plain slots: with the solver's vector work its
+  // swizzled form was slower (x inverse passes 1.81 -> 1.98 ms per step)
+  constexpr int SWI = 0;
   if (gate_closed(gate)) return;
   static_assert((M / 2) % TJ == 0, "the kept half of a row is whole columns of the lane layout");
   constexpr int EH = E / 2;
@@ -316,15 +318,14 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     load_table<cpx<T>, M, C::BLOCK>(twl, tw_g);
     load_table<cpx<T>, M + 1, C::BLOCK>(twl + M, tw2_g);
   }
-  cpx<T>* xr = lds + p;
 #pragma unroll
-  for (int i = 0; i < E; ++i) xr[(jt + TJ * i) * NPS] = x[i];
-  if (jt == 0) xr[M * NPS] = xM;
+  for (int i = 0; i < E; ++i) lds[lslot<SWI>(jt + TJ * i, p, NPS)] = x[i];
+  if (jt == 0) lds[lslot<SWI>(M, p, NPS)] = xM;
   __syncthreads();
   cpx<T> v[E];
   load_first<T, M, false>(v, p, jt, [&](int, int, int u) {
     const int k = jt + u;
-    const cpx<T> xk = xr[k * NPS], xm = xr[(M - k) * NPS];
+    const cpx<T> xk = lds[lslot<SWI>(k, p, NPS)], xm = lds[lslot<SWI>(M - k, p, NPS)];
     // Z[k] = (Xk + conj Xm) + i W^{-k} (Xk - conj Xm)
     const cpx<T> dk{xk.x - xm.x, xk.y + xm.y};
     const cpx<T> rk = cmulc(dk, tw2[k]);
@@ -341,7 +342,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   if constexpr (KM == KRY_V) kb = (IO)*kry.beta;
   double acc1 = 0.0, acc2 = 0.0;
   V2 yo[KM == KRY_HALF1 || KM == KRY_V ? EH : 1];  // the y pairs this lane wrote (solver forms)
-  run_fft<T, M, true, false, true>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> z) {
+  run_fft<T, M, true, false, true, false, SWI>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> z) {
     if (!valid) return;
     const int i = u / TJ;
     const double2 e2 = ev[i];
