@@ -263,9 +263,9 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g, Gate gate, Krylov kry) {
   using C = XCfg<T, M, V>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
-  // the inverse keeps the plain slots: with the solver's vector work its
+  // swizzled slots only without the solver's vector work: with it the
   // swizzled form was slower (x inverse passes 1.81 -> 1.98 ms per step)
-  constexpr int SWI = 0;
+  constexpr int SWI = KM == KRY_NONE ? C::SW : 0;
   if (gate_closed(gate)) return;
   static_assert((M / 2) % TJ == 0, "the kept half of a row is whole columns of the lane layout");
   constexpr int EH = E / 2;
