@@ -189,54 +189,84 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
         for (int q = 0; q < 3; ++q) acc[b][i][q] = cpx<T>{(T)0, (T)0};
       }
     }
+  // ring slot of J^_{n0-m} for 0 <= m < nl: one 64-bit remainder per thread,
+  // then 32-bit steps
+  const int s0 = (int)(n0 % g.nl);
   auto load_slot = [&](int m, cpx<T> (&jv)[NM][3]) {
-    const cpx<T>* R = ring + (size_t)((n0 - m) % g.nl) * slot;
+    const int sl = s0 - m < 0 ? s0 - m + g.nl : s0 - m;
+    const cpx<T>* R = ring + (size_t)sl * slot;
 #pragma unroll
     for (int i = 0; i < NM; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
   };
-  // FP32: the next slot's currents and the next window value are loaded
-  // before this slot's multiply-adds, so that their latency overlaps them
-  // (FP64 has no registers to spare for it)
-  constexpr bool PREFETCH = sizeof(T) == 4;
-  cpx<T> jv[NM][3];
-  if (PREFETCH && nold > 0) load_slot(0, jv);
-  // the loop starts with no load in flight (vmcnt 0): the wait counts inside
-  // the loop then follow its own loads only
-  if constexpr (PREFETCH) __builtin_amdgcn_s_waitcnt(0x0F70);
-  for (int m = 0; m < nold; ++m) {
-    cpx<T> jn[NM][3];
-    T ln[6];
-    if constexpr (PREFETCH) {
-      load_slot(m + 1 < nold ? m + 1 : m, jn);
-      lam_at(m + 1 + B, ln);
-    } else {
-      load_slot(m, jv);
-    }
-    if constexpr (NM <= 2)
+  // One slot: its multiply-adds with the window, then the window moves on
+  // (w[B - 1] = the next Lambda value, ln, or 0 past the last lag).  The
+  // loaded registers are only read here (the signs go into copies).
+  auto mac_slot = [&](const cpx<T> (&jv)[NM][3], const T (&ln)[6], bool lzero) {
+    cpx<T> j[NM][3];
 #pragma unroll
-      for (int i = 0; i < NM; ++i) jv[i][2] = cpx<T>{sz2 * jv[i][2].x, sz2 * jv[i][2].y};
-    if constexpr (NM == 1) jv[0][1] = cpx<T>{sy2 * jv[0][1].x, sy2 * jv[0][1].y};
+    for (int i = 0; i < NM; ++i) {
+      j[i][0] = jv[i][0];
+      j[i][1] = NM == 1 ? cpx<T>{sy2 * jv[i][1].x, sy2 * jv[i][1].y} : jv[i][1];
+      j[i][2] = NM <= 2 ? cpx<T>{sz2 * jv[i][2].x, sz2 * jv[i][2].y} : jv[i][2];
+    }
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
       for (int i = 0; i < NM; ++i)
         mac3<T>(acc[b][i], w[b], (NM != 1 && (i & 1)) ? (T)-1 : (T)1, (NM == 4 && (i >> 1)) ? (T)-1 : (T)1,
-                jv[i][0], jv[i][1], jv[i][2]);
+                j[i][0], j[i][1], j[i][2]);
 #pragma unroll
     for (int b = 0; b + 1 < B; ++b)
 #pragma unroll
       for (int c = 0; c < 6; ++c) w[b][c] = w[b + 1][c];
-    if constexpr (PREFETCH) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) w[B - 1][c] = ln[c];
+    for (int c = 0; c < 6; ++c) w[B - 1][c] = lzero ? (T)0 : ln[c];
+  };
+  // Lambda_lag, clamped to the last lag (the caller zeroes lags past it)
+  auto lam_ld = [&](int lag, T (&l)[6]) {
+    const T* L = lamh + (size_t)((lag < g.nl ? lag : g.nl) - 1) * 6 * lcomp + lo;
 #pragma unroll
-      for (int i = 0; i < NM; ++i)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) jv[i][q] = jn[i][q];
-    } else {
-      lam_at(m + 1 + B, w[B - 1]);
+    for (int c = 0; c < 6; ++c) l[c] = L[c * lcomp];
+  };
+  if constexpr (sizeof(T) == 4) {
+    // FP32: three register sets take the slots in turn (slot m in set
+    // m mod 3).  The work on slot m first issues the loads of slot m + 2
+    // (and of the window value two slots ahead) into the set that slot m - 1
+    // has just released, then does slot m's multiply-adds: every load has
+    // two slots of multiply-adds to arrive in.  All loads in the loop are
+    // unconditional (indices clamped to valid slots and lags), so that no
+    // register with a load in flight is merged or copied at a branch or at
+    // the loop's back edge; the last nold mod 3 slots run after the loop.
+    const int last = nold > 0 ? nold - 1 : 0;
+    cpx<T> j0[NM][3], j1[NM][3], j2[NM][3];
+    T l0[6], l1[6], l2[6];
+    load_slot(0, j0);
+    load_slot(last < 1 ? last : 1, j1);
+    lam_ld(1 + B, l0);
+    lam_ld(2 + B, l1);
+    auto step = [&](int m, cpx<T> (&jc)[NM][3], T (&lc)[6], cpx<T> (&jn)[NM][3], T (&ln)[6]) {
+      load_slot(m + 2 < last ? m + 2 : last, jn);
+      lam_ld(m + 3 + B, ln);
+      mac_slot(jc, lc, m + 1 + B > g.nl);
+    };
+    const int nfull = nold / 3 * 3;
+    for (int m = 0; m < nfull; m += 3) {
+      step(m, j0, l0, j2, l2);
+      step(m + 1, j1, l1, j0, l0);
+      step(m + 2, j2, l2, j1, l1);
+    }
+    if (nfull < nold) mac_slot(j0, l0, nfull + 1 + B > g.nl);
+    if (nfull + 1 < nold) mac_slot(j1, l1, nfull + 2 + B > g.nl);
+  } else {
+    // FP64 has no registers to spare for loads ahead
+    for (int m = 0; m < nold; ++m) {
+      cpx<T> jv[NM][3];
+      T ln[6];
+      load_slot(m, jv);
+      lam_at(m + 1 + B, ln);
+      mac_slot(jv, ln, false);
     }
   }
 #pragma unroll
