@@ -509,6 +509,8 @@ def main():
     ap.add_argument("--sweep-history", default="both", choices=["auto", "blocked", "fft_time", "both"],
                     help="history scheme of the sweep's marches (both: the library's choice, then the other one "
                          "where both are possible)")
+    ap.add_argument("--time-every", type=int, default=4,
+                    help="timed steps whose launches of the dominant kernel carry timing events: every n-th")
     ap.add_argument("--no-kernel-timing", action="store_true",
                     help="no timing events in the timed region (the roofline then uses the breakdown steps)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -585,9 +587,12 @@ def main():
     Js = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(n_keep)]
     J_spare = torch.empty(3 * N, dtype=torch.float64, device="cuda")
 
-    def one_step(c, s):
+    def one_step(c, s, wait=True):
+        """One step; wait=False: no device wait at its end (the statistics
+        then carry no LHS/RHS times)."""
         c.excitation(p, (args.start_step + s) * L, einc)
-        return c.step(einc, Js[s] if s < n_keep else J_spare, tol=args.tol, stats=True)[1]
+        st = c.step(einc, Js[s] if s < n_keep else J_spare, tol=args.tol, stats=wait)[1]
+        return st if wait else c.last_stats()
 
     for s in range(args.warmup):
         st = one_step(ctx, s)
@@ -597,8 +602,7 @@ def main():
     ctx.profile_kinds(None)
     ctx.profile(True)
     ctx.profile_read()
-    for s in range(nbd):
-        one_step(ctx, args.warmup + s)
+    bd_stats = [one_step(ctx, args.warmup + s) for s in range(nbd)]
     breakdown = ctx.profile_read()
     ctx.profile(False)
     dom = max(((k, pr, ms, cnt) for (k, pr), (ms, cnt) in breakdown.items() if k in ROOFLINE_KINDS),
@@ -606,18 +610,23 @@ def main():
     log(f"dominant kernel over {nbd} steps: {dom[0]}.{dom[1]} ({dom[2] / nbd:.2f} ms/step)")
     if args.graphs:
         ctx.set_graphs(True)
-    # inside the timed region only the dominant kernel carries timing events
-    ctx.profile_kinds([dom[0]])
+    # inside the timed region only the dominant kernel carries timing events,
+    # in every `--time-every`-th step (an event pair leaves the device idle
+    # for a few microseconds on each side of the launch it brackets)
+    sampled = [s for s in range(args.steps) if s % max(args.time_every, 1) == 0]
+    ctx.profile_kinds([])
     ctx.profile(not args.no_kernel_timing)
     ctx.profile_read()
     torch.cuda.synchronize()
     t = time.perf_counter()
     stats = []
+    # the timed steps do not wait for each other: each returns with its
+    # history update in flight, and the next one's launches queue behind it
     for s in range(args.steps):
-        stats.append(one_step(ctx, first_timed + s))
+        ctx.profile_kinds([dom[0]] if s in sampled else [])
+        stats.append(one_step(ctx, first_timed + s, wait=False))
         log(f"step {s}: {stats[-1]['iters']} it, {stats[-1]['matvecs']} mv "
-            f"({stats[-1]['matvecs_f64']} f64), relres {stats[-1]['relres']:.2e}, "
-            f"lhs {stats[-1]['ms_lhs']:.1f} ms, rhs {stats[-1]['ms_rhs']:.1f} ms")
+            f"({stats[-1]['matvecs_f64']} f64), relres {stats[-1]['relres']:.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     prof = ctx.profile_read()
@@ -670,7 +679,7 @@ def main():
         steps_counted, st_counted = nbd, None
     else:
         (kind, prec), (ms, cnt) = max(((k, v) for k, v in prof.items() if k[0] == dom[0]), key=lambda r: r[1][0])
-        steps_counted, st_counted = args.steps, stats
+        steps_counted, st_counted = len(sampled), [stats[s] for s in sampled]
     # Launches of the product passes behind a closed convergence gate end at
     # once; the device counts the products that ran (one launch of each pass
     # each), so the average is the class's whole time over those.
@@ -692,7 +701,10 @@ def main():
     roofline = {"bound": "hbm", "kernel": f"{kind}.{prec}", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "traffic": measured_traffic(f"{kind}.{prec}", var),
-                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": ms / cnt, "tile_variant": var}
+                "algorithmic_bytes_per_launch": alg, "avg_launch_ms": ms / cnt, "tile_variant": var,
+                "launches_timed": cnt,
+                "timed_steps": (f"{len(sampled)} of the {args.steps} timed steps (every {args.time_every}-th)"
+                                if not args.no_kernel_timing else f"the {nbd} breakdown steps")}
     # Z0 pipeline as a whole (five passes)
     pipe_bytes = sum(algorithmic_bytes(k, n, 4, 4, nl) for k in
                      ("x_forward", "y_forward", "z_fused", "y_inverse", "x_inverse_epilogue"))
@@ -723,8 +735,9 @@ def main():
         "iters_per_step": {"min": min(its), "max": max(its), "mean": sum(its) / len(its)},
         "matvecs_per_step": sum(s["matvecs"] for s in stats) / len(stats),
         "relres_max": max(s["relres"] for s in stats),
-        "ms_lhs_mean": sum(s["ms_lhs"] for s in stats) / len(stats),
-        "ms_rhs_mean": sum(s["ms_rhs"] for s in stats) / len(stats),
+        # LHS and RHS times of Eq. 6 from the breakdown steps (one history block)
+        "ms_lhs_mean": sum(s["ms_lhs"] for s in bd_stats) / len(bd_stats),
+        "ms_rhs_mean": sum(s["ms_rhs"] for s in bd_stats) / len(bd_stats),
         "setup_s": setup_s,
         "autotune_s": tune_s,
         "tile_variants": variants,

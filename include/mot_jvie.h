@@ -171,10 +171,19 @@ int mot_excitation(mot_ctx* ctx, const mot_pulse* pulse, double t, double* out);
 /* One MOT step (Eq. 3): b = einc + h_n, solve Z0 J_n = b by TFQMR from
  * J = 0 to ||b - Z0 J_n|| <= tol ||b|| (true residual, FP64), then
  * history_update(J_n) and n += 1.  b = 0 gives J_n = 0 after 0 iterations.
- * einc, J_n: FP64 device vectors of 3N (distinct).  `stats` may be NULL.
+ * einc, J_n: FP64 device vectors of 3N (distinct).  `stats` may be NULL;
+ * with stats the call waits for the step to finish (it times the solve and
+ * the right-hand side), without it the history update is still in flight
+ * when it returns.
  * Errors: MOT_ENOCONV (J_n = last iterate, history still advanced),
  * MOT_EBREAKDOWN, MOT_ENONFINITE, MOT_ESTATE, MOT_EHIP. */
 int mot_step(mot_ctx* ctx, const double* einc, double* J_n, double tol, int32_t max_iter, mot_stats* stats);
+
+/* Statistics of the context's last mot_step (host copy, no device wait):
+ * iterations, products, refinements and the final residual of Eq. 3's
+ * solve; ms_lhs and ms_rhs are -1 when that step was called without
+ * stats.  Errors: MOT_EINVAL (NULL). */
+int mot_last_stats(const mot_ctx* ctx, mot_stats* stats);
 
 /* on = 1: each TFQMR iteration of mot_step is replayed from a HIP graph
  * (captured on first use, per vector precision, operator and whether it

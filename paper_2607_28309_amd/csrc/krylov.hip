@@ -196,13 +196,23 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ partia
 // FIN_THREADS threads: a wide block, so that each thread adds few partials.
 constexpr int FIN_THREADS = 1024;
 
+// mirror (optional, host memory the device can write): the scalars are
+// copied there after the recurrence, also when the gate is closed, so that
+// the host reads the solver's state without a copy command of its own.
 __global__ __launch_bounds__(FIN_THREADS) void k_reduce(const double* __restrict__ partials, double* scal,
-                                                        int slot, int post, Gate g, int nparts) {
-  if (motfft::gate_closed(g)) return;
+                                                        int slot, int post, Gate g, int nparts, double* mirror) {
+  if (motfft::gate_closed(g)) {
+    if (mirror && threadIdx.x < S_NSLOT) mirror[threadIdx.x] = scal[threadIdx.x];
+    return;
+  }
   const double sum = sum_partials<FIN_THREADS>(partials, nparts);
   if (threadIdx.x == 0) {
     scal[slot] = sum;
     post_op(scal, post);
+  }
+  if (mirror) {
+    __syncthreads();
+    if (threadIdx.x < S_NSLOT) mirror[threadIdx.x] = scal[threadIdx.x];
   }
 }
 
@@ -413,9 +423,9 @@ hipError_t dot_partial(const V* a, const V* b, long long n, double* partials, hi
   LAUNCH(k_dot<V>, a, b, n, partials);
 }
 hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g,
-                       int nparts) {
+                       int nparts, double* mirror) {
   if (nparts < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(FIN_THREADS), 0, s, partials, scal, slot, post, g, nparts);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(FIN_THREADS), 0, s, partials, scal, slot, post, g, nparts, mirror);
   return hipGetLastError();
 }
 hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,

@@ -106,6 +106,7 @@ struct mot_ctx {
   double pred_G[PRED_MAX][PRED_MAX];  // Gram matrix of the stored Z0 J_i
   double* pred_dots;                  // device: dots of one multidot
   size_t bytes;
+  mot_stats last;  // statistics of the last mot_step (host-side values)
   char err[512];
 };
 
@@ -534,7 +535,11 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   kfix.mode = motfft::KRY_XFIX;  // in = x
   kfix.x = x;
   kfix.d = v[V_D];
-  // one iteration's launches on the context stream (gated; see above)
+  // one iteration's launches on the context stream (gated; see above); its
+  // last reduction writes the scalars to the host bank `mirror` (stream
+  // launches only: a captured graph keeps one pointer, so graph replays copy
+  // the scalars with a memory copy instead)
+  double* mirror = nullptr;
   auto enqueue_iter = [&](bool check) -> int {
     hipStream_t st = c->stream;
     auto half0_sum = [&]() -> int {
@@ -553,7 +558,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
     }
     // u = w + beta u2; au = A u and v = au + beta (au2 + beta v)
     TRY(apply_z0(c, v[V_W], v[V_AU], RUN, &ku, &kvv, v[V_U]));
-    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, st, RUN, xb));
+    HTP(K_KRY, f64, reduce_post(P, sc, S_SIGMA, POST_ALPHA, st, RUN, xb, mirror));
     return MOT_OK;
   };
   // graph mode: the same launches captured once per (precision, operator,
@@ -617,9 +622,10 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
     bool check = !bound_only;
     if (check && tau_last > 0.0 && tolb > 0.0 && it < max_iter)
       check = tau_last * std::sqrt(2.0 * it + 1.0) <= 1e3 * tolb;
-    TRY(launch_iter(check));
     double* bank = c->hscal + (1 + (it & 1)) * S_NSLOT;
-    HT(hipMemcpyAsync(bank, sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, s));
+    mirror = graphs ? nullptr : bank;
+    TRY(launch_iter(check));
+    if (graphs) HT(hipMemcpyAsync(bank, sc, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, s));
     HT(hipEventRecord(c->evq[it & 1], s));
     if (it >= 2) {
       HT(hipEventSynchronize(c->evq[(it - 1) & 1]));
@@ -1532,7 +1538,11 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
   double* x = c->kv[V_X];
   if (st) HT(hipEventRecord(c->ev[0], s));
   HTP(K_KRY, true, vec_add64(einc, c->hrhs, b, c->n3, c->partials, s));
-  int rc = solve(c, b, x, tol, max_iter, st, true);
+  // the solve's counts and residual are known on the host when it returns
+  c->last = mot_stats{};
+  c->last.ms_lhs = c->last.ms_rhs = -1.0;
+  int rc = solve(c, b, x, tol, max_iter, &c->last, true);
+  if (st) *st = c->last;
   if (rc != MOT_OK && rc != MOT_ENOCONV && rc != MOT_EBREAKDOWN) return rc;
   if (c->prec == MOT_F32_REFINED || rc == MOT_OK || rc == MOT_ENOCONV || rc == MOT_EBREAKDOWN)
     HT(hipMemcpyAsync(J_n, x, sizeof(double) * c->n3, hipMemcpyDeviceToDevice, s));
@@ -1547,8 +1557,16 @@ int mot_step(mot_ctx* c, const double* einc, double* J_n, double tol, int32_t ma
     HT(hipEventElapsedTime(&bms, c->ev[1], c->ev[2]));
     st->ms_lhs = a;
     st->ms_rhs = bms;
+    c->last.ms_lhs = a;
+    c->last.ms_rhs = bms;
   }
   return rc;
+}
+
+int mot_last_stats(const mot_ctx* c, mot_stats* st) {
+  if (!c || !st) return MOT_EINVAL;
+  *st = c->last;
+  return MOT_OK;
 }
 
 int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* einc, double* const* J_n, double tol,

@@ -65,9 +65,11 @@ using motfft::Gate;
 // Scalar recurrence applied by the reduction that produced scal[slot].
 enum Post { POST_NONE = 0, POST_INIT, POST_ALPHA, POST_HALF0, POST_HALF1, POST_BETA, POST_RESID };
 // Sum of nparts partials (RED_BLOCKS for the vector kernels here, the
-// workgroup count for sums fused into the x passes) into scal[slot].
+// workgroup count for sums fused into the x passes) into scal[slot]; with
+// mirror (pinned host memory), the S_NSLOT scalars are also written there,
+// whether or not the gate is open.
 hipError_t reduce_post(const double* partials, double* scal, int slot, int post, hipStream_t s, Gate g = Gate{},
-                       int nparts = RED_BLOCKS);
+                       int nparts = RED_BLOCKS, double* mirror = nullptr);
 // Two sums at once (partials[0, nparts) and [stride, stride + nparts)), then
 // post1 and post2 in that order.
 hipError_t reduce_post2(const double* partials, double* scal, int slot1, int post1, int slot2, int post2,

@@ -31,7 +31,7 @@ EXPORTS = (
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
     "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor", "mot_set_regularization",
-    "mot_farfield_static", "mot_set_history_scheme", "mot_set_breakdown_tolerance",
+    "mot_farfield_static", "mot_set_history_scheme", "mot_set_breakdown_tolerance", "mot_last_stats",
 )
 TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
 PROF_NCLASS = 24
@@ -77,6 +77,7 @@ def _load():
         "mot_get_history_rhs": (ctypes.c_int, [vp, vp]),
         "mot_excitation": (ctypes.c_int, [vp, ctypes.POINTER(MotPulse), dbl, vp]),
         "mot_step": (ctypes.c_int, [vp, vp, vp, dbl, i32, ctypes.POINTER(MotStats)]),
+        "mot_last_stats": (ctypes.c_int, [vp, ctypes.POINTER(MotStats)]),
         "mot_reset": (ctypes.c_int, [vp]),
         "mot_set_step": (ctypes.c_int, [vp, i64]),
         "mot_green_table": (ctypes.c_int, [vp, i32, vp]),
@@ -365,6 +366,13 @@ class Context:
                           float(tol), int(max_iter), ctypes.byref(st) if st is not None else None)
         self._check(rc, "mot_step", allow=allow)
         return rc, (st.as_dict() if st is not None else None)
+
+    def last_stats(self):
+        """Statistics of the last step (no device wait; ms_lhs and ms_rhs are
+        -1 when it ran without stats)."""
+        st = MotStats()
+        self._check(LIB.mot_last_stats(self.h, ctypes.byref(st)), "mot_last_stats")
+        return st.as_dict()
 
     def reset(self):
         self._check(LIB.mot_reset(self.h), "mot_reset")
