@@ -196,8 +196,8 @@ int mot_set_graphs(mot_ctx* ctx, int32_t on);
  * `count` contexts, run by `nthreads` host threads so that contexts created
  * on different streams overlap on the GPU (streams share the device's few
  * hardware queues: about 8 threads reach the best rate for 32 small grids).  einc[i], J_n[i]: the i-th
- * context's vectors; stats (may be NULL) and status (required) are arrays of
- * count.  Every context must be distinct (a context is not thread-safe).
+ * context's vectors; stats (may be NULL: those of mot_last_stats, without
+ * LHS/RHS times) and status (required) are arrays of count.  Every context must be distinct (a context is not thread-safe).
  * Returns MOT_OK or the first non-OK status; status[i] holds each one.
  * Errors: MOT_EINVAL, and those of mot_step. */
 int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* einc, double* const* J_n, double tol,

@@ -1578,9 +1578,14 @@ int mot_step_batch(mot_ctx* const* ctxs, int32_t count, const double* const* ein
       if (ctxs[k] == ctxs[i]) return MOT_EINVAL;  // a context is not thread-safe
   }
   std::atomic<int> next{0};
+  // members are stepped without stats (no wait for a member's history
+  // update before the thread takes the next one); their statistics are the
+  // host-side ones of mot_last_stats
   auto worker = [&]() {
-    for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1))
-      status[i] = mot_step(ctxs[i], einc[i], J_n[i], tol, max_iter, stats ? &stats[i] : nullptr);
+    for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
+      status[i] = mot_step(ctxs[i], einc[i], J_n[i], tol, max_iter, nullptr);
+      if (stats) stats[i] = ctxs[i]->last;
+    }
   };
   const int nt = nthreads < count ? nthreads : count;
   std::vector<std::thread> pool;
