@@ -495,7 +495,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--start-step", type=int, default=22, help="pulse time index of the first warm-up step")
-    ap.add_argument("--graphs", action="store_true", help="replay TFQMR iterations from HIP graphs")
+    ap.add_argument("--graphs", type=int, default=0, choices=[0, 1, 2],
+                    help="1: replay TFQMR iterations from HIP graphs; 2: the first refinement sweep of each step as "
+                         "one graph (timing events stay off in the steps that replay it)")
     ap.add_argument("--history", default="auto", choices=["auto", "blocked", "fft_time"],
                     help="history scheme of the benchmarked march (auto: the library's choice)")
     ap.add_argument("--no-batch", action="store_true",
@@ -609,7 +611,7 @@ def main():
               key=lambda r: r[2])
     log(f"dominant kernel over {nbd} steps: {dom[0]}.{dom[1]} ({dom[2] / nbd:.2f} ms/step)")
     if args.graphs:
-        ctx.set_graphs(True)
+        ctx.set_graphs(args.graphs)
     # inside the timed region only the dominant kernel carries timing events,
     # in every `--time-every`-th step (an event pair leaves the device idle
     # for a few microseconds on each side of the launch it brackets)

@@ -188,8 +188,16 @@ int mot_last_stats(const mot_ctx* ctx, mot_stats* stats);
 /* on = 1: each TFQMR iteration of mot_step is replayed from a HIP graph
  * (captured on first use, per vector precision, operator and whether it
  * carries the true-residual check; the capture uses a stream of the
- * context's own, the replay the context's stream).  Timing (mot_profile)
- * uses the launch-by-launch path.  Errors: MOT_EINVAL. */
+ * context's own, the replay the context's stream).
+ * on = 2 (MOT_F32_REFINED without an initial guess): the first refinement
+ * sweep of a step, i.e. the inner FP32 TFQMR with a fixed number of
+ * iterations behind the convergence gates (one more than the most that the
+ * first sweeps of the last 8 steps needed) and its FP64 residual, is one
+ * graph replay, followed by one read of the residual; further sweeps, and
+ * the first step after the mode is set, run launch by launch.  The graph is
+ * captured again when that iteration count, the tolerance or the operator
+ * changes.  The currents are those of on = 0, bit for bit.
+ * Timing (mot_profile) uses the launch-by-launch path.  Errors: MOT_EINVAL. */
 int mot_set_graphs(mot_ctx* ctx, int32_t on);
 
 /* Batch of independent scatterers: one MOT step (as mot_step) of each of the

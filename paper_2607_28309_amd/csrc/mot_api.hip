@@ -77,6 +77,12 @@ struct mot_ctx {
   // TFQMR iterations as graphs: [FP64 vectors][adjoint][with residual check]
   int use_graphs;
   hipStream_t cap_stream;   // capture only; graphs are launched on `stream`
+  // mode 2: the refined solve's first sweep as one graph (sg_G gated
+  // iterations, FP32 tolerance sg_tol, operator sg_adj); sg_hist: the
+  // iterations the last 8 first sweeps needed, sg_need their maximum
+  hipGraphExec_t sg_exec;
+  int sg_G, sg_adj, sg_need, sg_last, sg_pos, sg_hist[8];
+  double sg_tol;
   hipGraphExec_t iter_graph[2][2][2];
   // kernel timing (mot_profile)
   int prof_on, prof_used, prof_cap;
@@ -458,9 +464,13 @@ template <> struct KV<float> {
 // to FP32, formed by the start kernel itself (b is then not read: the
 // rounded copy r~ = r0 stands in for it).  x64 (FP32 solves only): the
 // solution goes to x64 (x64_acc: added to it) instead of x.
+// fixed > 0: exactly `fixed` iterations are enqueued (each behind the
+// convergence gates, max_iter = fixed) with the final x update, and the call
+// returns without waiting for the device or reading its scalars (a sequence
+// that a graph can capture; the caller reads the outcome).
 template <typename V>
 int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, bool bound_only = false,
-          const double* b64 = nullptr, double* x64 = nullptr, bool x64_acc = false) {
+          const double* b64 = nullptr, double* x64 = nullptr, bool x64_acc = false, int fixed = 0) {
   hipStream_t s = c->stream;
   const long long n = c->n3;
   V** v = KV<V>::get(c);
@@ -564,7 +574,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   // graph mode: the same launches captured once per (precision, operator,
   // check) on the capture stream and replayed on the context stream; b and x
   // are the context's own vectors, so the captured arguments stay valid
-  const bool graphs = c->use_graphs && !c->prof_on;
+  const bool graphs = c->use_graphs == 1 && !c->prof_on;
   auto launch_iter = [&](bool check) -> int {
     if (!graphs) return enqueue_iter(check);
     hipGraphExec_t& ex = c->iter_graph[f64 ? 1 : 0][c->adjoint ? 1 : 0][check ? 1 : 0];
@@ -607,7 +617,8 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
   // it before enqueueing the next: a short idle gap instead of a whole empty
   // iteration.
   double tau_last = -1.0, tau_prev = -1.0, tolb = -1.0;
-  for (int it = 1; it <= max_iter + 1; ++it) {
+  for (int it = 1; it <= fixed; ++it) TRY(enqueue_iter(!bound_only));
+  for (int it = 1; fixed == 0 && it <= max_iter + 1; ++it) {
     if (it >= 3 && tau_last > 0.0 && tau_prev > 0.0 && tolb > 0.0 && tau_last < tau_prev) {
       const double pred = tau_last * (tau_last / tau_prev) * std::sqrt(2.0 * it);
       if (pred <= 1.5 * tolb) {
@@ -664,6 +675,7 @@ int tfqmr(mot_ctx* c, const V* b, V* x, double tol, int max_iter, SolveOut* so, 
     if (bound_only) HTP(K_KRY, f64, vec_axpy_scal<V>(x, v[V_D], sc + S_ETAP, n, s));
     HTP(K_KRY, f64, vec_scale_voxel<V>(x, rs, n, c->N, s));
   }
+  if (fixed > 0) return MOT_OK;
   if (!h || h[S_DONE] == 0.0) return set_err(c, MOT_ENOCONV, "TFQMR did not converge in max_iter%s%d");
   so->iters = (int)h[S_ITER];
   so->matvecs += (int)h[S_NMV];
@@ -838,44 +850,108 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
       // iterations, after which its iterate is kept and the solve restarts
       // from the FP64 residual
       constexpr int kInnerCap = 40;
-      while (true) {
-        ++refinements;
-        double tin = bnorm < 0.0 ? 0.5 * tol : rnorm > 0.0 ? 0.5 * tol * bnorm / rnorm : 1.0;
-        // FP32 floor of the inner tolerance: the solve stops on its bound,
-        // which sits well above the true residual, and the FP64 residual
-        // below decides (a looser floor would risk second sweeps)
-        if (tin < 3e-6) tin = 3e-6;
-        SolveOut inner;
-        const int left = max_iter - so.iters;
-        const int cap = left < kInnerCap ? (left > 1 ? left : 1) : kInnerCap;
-        // the inner solve (on r rounded to FP32) stops on its quasi-residual
-        // bound: the FP64 residual below is its check
-        // (x = e on the first sweep from x = 0, else x += e)
-        int irc = tfqmr<float>(c, nullptr, c->kf[V_X], tin, cap, &inner, true, r, x, refinements > 1 || guess);
-        so.iters += inner.iters;
-        so.matvecs += inner.matvecs;
-        if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
-        // r = b - Z0 x: the product's inverse x pass writes the residual and
-        // its partials (the predictor keeps Z0 x itself)
+      // r = b - Z0 x: the product's inverse x pass writes the residual and
+      // its partials (the predictor keeps Z0 x itself)
+      auto residual64 = [&]() -> int {
         if (c->pred_k > 0) {
           TRY(apply_z0(c, x, v[V_TMP]));
           HTP(K_KRY, true, vec_sub<double>(b, v[V_TMP], v[V_RO], n, P, s));
           HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s));
-        } else {
-          const int xb = motfft::x_pass_blocks(c->nx, true, c->tune[1][TUNE_X], 3 * c->nz * c->ny, c->nz * c->ny, 3);
-          if (xb < 1 || (size_t)xb > c->partials_n) return set_err(c, MOT_EINVAL, "x pass grid outside the partials%s%d");
-          motfft::Krylov kr;
-          kr.mode = motfft::KRY_RESID;
-          kr.v = (void*)b;
-          kr.partials = P;
-          kr.stride = xb;
-          kr.stream = (size_t)n * sizeof(double) >= ((size_t)32 << 20) ? 1 : 0;
-          TRY(apply_z0(c, x, v[V_RO], motfft::Gate{}, nullptr, &kr));
-          HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s, motfft::Gate{}, xb));
+          return MOT_OK;
         }
-        so.matvecs++;
-        so.matvecs64++;
+        const int xb = motfft::x_pass_blocks(c->nx, true, c->tune[1][TUNE_X], 3 * c->nz * c->ny, c->nz * c->ny, 3);
+        if (xb < 1 || (size_t)xb > c->partials_n) return set_err(c, MOT_EINVAL, "x pass grid outside the partials%s%d");
+        motfft::Krylov kr;
+        kr.mode = motfft::KRY_RESID;
+        kr.v = (void*)b;
+        kr.partials = P;
+        kr.stride = xb;
+        kr.stream = (size_t)n * sizeof(double) >= ((size_t)32 << 20) ? 1 : 0;
+        TRY(apply_z0(c, x, v[V_RO], motfft::Gate{}, nullptr, &kr));
+        HTP(K_KRY, true, reduce_post(P, c->scal, S_R2, POST_NONE, s, motfft::Gate{}, xb));
+        return MOT_OK;
+      };
+      // the first sweep's FP32 tolerance (|b| is not known yet)
+      const double tin1 = std::max(0.5 * tol, 3e-6);
+      // graph mode 2: the first sweep as one graph replay (a fixed number of
+      // gated iterations, one more than the most the recent steps needed, and
+      // the FP64 residual), then the host reads the outcome as below
+      const bool sweep_graph = c->use_graphs == 2 && !(c->prof_on && c->prof_mask) && !guess && c->pred_k == 0 &&
+                               c->sg_need > 0 && b == c->kv[V_B] && x == c->kv[V_X] && max_iter >= c->sg_need + 1;
+      bool first_done = false;
+      if (sweep_graph) {
+        const int G = c->sg_need + 1;
+        if (c->sg_exec && (c->sg_G != G || c->sg_tol != tin1 || c->sg_adj != c->adjoint)) {
+          (void)hipGraphExecDestroy(c->sg_exec);
+          c->sg_exec = nullptr;
+        }
+        if (!c->sg_exec) {
+          if (!c->cap_stream) HT(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+          hipStream_t saved = c->stream;
+          c->stream = c->cap_stream;
+          s = c->cap_stream;
+          HT(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+          SolveOut unused;
+          int crc = tfqmr<float>(c, nullptr, c->kf[V_X], tin1, G, &unused, true, r, x, false, G);
+          if (crc == MOT_OK) crc = residual64();
+          hipGraph_t gr = nullptr;
+          const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
+          c->stream = saved;
+          s = saved;
+          if (crc != MOT_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return crc;
+          }
+          HT(ec);
+          const hipError_t ei = hipGraphInstantiate(&c->sg_exec, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          if (ei != hipSuccess) {
+            c->sg_exec = nullptr;
+            HT(ei);
+          }
+          c->sg_G = G;
+          c->sg_tol = tin1;
+          c->sg_adj = c->adjoint;
+        }
+        HT(hipGraphLaunch(c->sg_exec, s));
         TRY(reduce_sync(c));
+        const double* h = c->hscal;
+        ++refinements;
+        so.iters += (int)h[S_ITER];
+        so.matvecs += (int)h[S_NMV] + 1;
+        so.matvecs64 += 1;
+        if ((int)h[S_STATUS] == MOT_ENONFINITE)
+          return set_err(c, MOT_ENONFINITE, "TFQMR: right-hand side or residual is not finite%s%d");
+        // the iterations the sweep needed (G + 1 when it ran out of them)
+        c->sg_last = h[S_DONE] != 0.0 && (int)h[S_STATUS] == MOT_OK ? (int)h[S_ITER] : G + 1;
+        first_done = true;
+      }
+      while (true) {
+        if (first_done) {
+          first_done = false;
+        } else {
+          ++refinements;
+          double tin = bnorm < 0.0 ? 0.5 * tol : rnorm > 0.0 ? 0.5 * tol * bnorm / rnorm : 1.0;
+          // FP32 floor of the inner tolerance: the solve stops on its bound,
+          // which sits well above the true residual, and the FP64 residual
+          // below decides (a looser floor would risk second sweeps)
+          if (tin < 3e-6) tin = 3e-6;
+          SolveOut inner;
+          const int left = max_iter - so.iters;
+          const int cap = left < kInnerCap ? (left > 1 ? left : 1) : kInnerCap;
+          // the inner solve (on r rounded to FP32) stops on its quasi-residual
+          // bound: the FP64 residual below is its check
+          // (x = e on the first sweep from x = 0, else x += e)
+          int irc = tfqmr<float>(c, nullptr, c->kf[V_X], tin, cap, &inner, true, r, x, refinements > 1 || guess);
+          so.iters += inner.iters;
+          so.matvecs += inner.matvecs;
+          if (irc != MOT_OK && irc != MOT_ENOCONV && irc != MOT_EBREAKDOWN) return irc;
+          if (refinements == 1 && !guess) c->sg_last = irc == MOT_OK ? inner.iters : cap + 1;
+          TRY(residual64());
+          so.matvecs++;
+          so.matvecs64++;
+          TRY(reduce_sync(c));
+        }
         if (bnorm < 0.0) {
           bnorm = sqrt(c->hscal[S_OB2]);
           if (!std::isfinite(bnorm)) return set_err(c, MOT_ENONFINITE, "right-hand side is not finite%s%d");
@@ -893,6 +969,15 @@ int solve(mot_ctx* c, const double* b, double* x, double tol, int max_iter, mot_
           rc = set_err(c, MOT_ENOCONV, "refinement did not reach the tolerance%s%d");
           break;
         }
+      }
+      // iterations the first sweep of the next graph replay gets: one more
+      // than the most any of the last 8 first sweeps needed
+      if (c->use_graphs == 2 && !guess && c->sg_last > 0) {
+        c->sg_hist[c->sg_pos] = c->sg_last;
+        c->sg_pos = (c->sg_pos + 1) % 8;
+        int mx = 0;
+        for (int k = 0; k < 8; ++k) mx = std::max(mx, c->sg_hist[k]);
+        c->sg_need = std::min(mx, kInnerCap);
       }
       // the last residual's product is Z0 x: the pair for later guesses
       if (c->pred_k > 0) TRY(pred_push(c, x, v[V_TMP]));
@@ -1001,6 +1086,10 @@ int history_update_impl(mot_ctx* c, const double* J) {
 }
 
 void drop_graphs(mot_ctx* c) {
+  if (c->sg_exec) {
+    (void)hipGraphExecDestroy(c->sg_exec);
+    c->sg_exec = nullptr;
+  }
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int k = 0; k < 2; ++k)
@@ -1639,11 +1728,12 @@ int mot_set_history_scheme(mot_ctx* c, int32_t scheme) {
 int mot_set_breakdown_tolerance(mot_ctx* c, double t) {
   if (!c || !std::isfinite(t) || t < 0.0) return MOT_EINVAL;
   c->bd_tol = t;
+  drop_graphs(c);  // a captured first sweep holds the old tolerance
   return MOT_OK;
 }
 
 int mot_set_graphs(mot_ctx* c, int32_t on) {
-  if (!c || (on != 0 && on != 1)) return MOT_EINVAL;
+  if (!c || on < 0 || on > 2) return MOT_EINVAL;
   c->use_graphs = on;
   return MOT_OK;
 }

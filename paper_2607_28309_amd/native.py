@@ -254,7 +254,10 @@ class Context:
                     "mot_excitation")
 
     def set_graphs(self, on=True):
-        self._check(LIB.mot_set_graphs(self.h, 1 if on else 0), "mot_set_graphs")
+        """on: False/0 stream launches, True/1 TFQMR iterations from graphs,
+        2 the refined solve's first sweep as one graph per step."""
+        mode = int(on) if not isinstance(on, bool) else (1 if on else 0)
+        self._check(LIB.mot_set_graphs(self.h, mode), "mot_set_graphs")
 
     def set_adjoint(self, on=True):
         self._check(LIB.mot_set_adjoint(self.h, 1 if on else 0), "mot_set_adjoint")

@@ -660,6 +660,33 @@ def test_graph_replay_matches_stream_launches(gpu_lib, prec):
         assert torch.equal(J[0], J[1])
 
 
+def test_sweep_graph_matches_stream_launches(gpu_lib):
+    # graph mode 2 (the refined first sweep as one graph with a fixed number of
+    # gated iterations) gives the currents and counts of stream launches, bit
+    # for bit, also in steps whose tighter tolerance needs a second sweep
+    import torch
+    n, alpha = (24, 20, 12), 8
+    eps = _eps(n)
+    cs = [_ctx(gpu_lib, n, alpha, "f32_refined", eps=eps) for _ in range(2)]
+    for c in cs:
+        c.reset()
+    cs[1].set_graphs(2)
+    p = W.pulse(20)
+    N = int(np.prod(n))
+    e = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    J = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(2)]
+    for k in range(40):
+        tol = 1e-6 if k < 25 else 3e-7
+        cs[0].excitation(p, (40 + k) * alpha / math.sqrt(3.0), e)
+        st = [c.step(e, Jc, tol=tol)[1] for c, Jc in zip(cs, J)]
+        for key in ("iters", "matvecs", "matvecs_f64", "refinements"):
+            assert st[0][key] == st[1][key], (k, key)
+        assert st[1]["relres"] <= tol
+        assert torch.equal(J[0], J[1]), k
+    for c in cs:
+        c.close()
+
+
 def test_step_batch_matches_single_steps(gpu_lib):
     # contexts of uneven grids on their own streams, stepped together by the
     # library's thread pool, give the currents of one-by-one steps, bit for bit
