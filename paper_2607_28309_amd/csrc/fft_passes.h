@@ -97,7 +97,7 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
 // a length-2M real signal; y/J rows of row_len reals, eps indexed by
 // (row mod rows_per_comp) * row_len + x.
 template <typename T, typename IO>
-hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M,
+hipError_t x_inverse(const void* in, IO* y, const IO* J, const T* eps, Epilogue ep, int M,
                      int nrows, int rows_per_comp, int ncomp, int row_len, int n_out, int kxs,
                      const void* tw, const void* tw2, hipStream_t s, Gate g = Gate{}, int var = 0,
                      const Krylov* kry = nullptr);

@@ -13,7 +13,7 @@ MOT_X_VARIANT(0)
                                                        const void*, const void*, hipStream_t, const double*,  \
                                                        Gate, const Krylov&);
 #define MOT_X_EXT_INV(T, IO, V, KM)                                                                          \
-  extern template hipError_t x_inverse_v<T, IO, V, KM>(const void*, IO*, const IO*, const double*, Epilogue,  \
+  extern template hipError_t x_inverse_v<T, IO, V, KM>(const void*, IO*, const IO*, const T*, Epilogue,  \
                                                        int, int, int, int, int, int, int, const void*,        \
                                                        const void*, hipStream_t, Gate, const Krylov&);
 MOT_X_EXT_FWD(float, float, 1, KRY_NONE)
@@ -63,7 +63,7 @@ hipError_t x_forward_k(const IO* in, void* out, int M, int nrows, int rows_per_c
 }
 
 template <typename T, typename IO, int V>
-hipError_t x_inverse_k(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M, int nrows,
+hipError_t x_inverse_k(const void* in, IO* y, const IO* J, const T* eps, Epilogue ep, int M, int nrows,
                        int rows_per_comp, int ncomp, int row_len, int n_out, int kxs, const void* tw,
                        const void* tw2, hipStream_t s, Gate gg, const Krylov* kry) {
   const int mode = kry ? kry->mode : KRY_NONE;
@@ -98,7 +98,7 @@ hipError_t x_forward(const IO* in, void* out, int M, int nrows, int rows_per_com
 }
 
 template <typename T, typename IO>
-hipError_t x_inverse(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M, int nrows,
+hipError_t x_inverse(const void* in, IO* y, const IO* J, const T* eps, Epilogue ep, int M, int nrows,
                      int rows_per_comp, int ncomp, int row_len, int n_out, int kxs, const void* tw,
                      const void* tw2, hipStream_t s, Gate gg, int var, const Krylov* kry) {
   if (var == 1)
@@ -118,7 +118,7 @@ int x_pass_blocks(int M, bool f64, int var, int nrows, int rows_per_comp, int nc
 #define XINST(T, IO)                                                                                      \
   template hipError_t x_forward<T, IO>(const IO*, void*, int, int, int, int, int, int, int, const void*,    \
                                        const void*, hipStream_t, const double*, Gate, int, const Krylov*); \
-  template hipError_t x_inverse<T, IO>(const void*, IO*, const IO*, const double*, Epilogue, int, int, int, \
+  template hipError_t x_inverse<T, IO>(const void*, IO*, const IO*, const T*, Epilogue, int, int, int, \
                                        int, int, int, int, const void*, const void*, hipStream_t, Gate, int, \
                                        const Krylov*);
 XINST(float, float)

@@ -259,7 +259,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_forward(const IO* 
 template <typename T, typename IO, int M, int V, int KM>
 __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
     const cpx<T>* __restrict__ in, IO* __restrict__ y, const IO* __restrict__ J,
-    const double* __restrict__ eps, Epilogue ep, int nrows, int rows_per_comp, int ncomp, int row_len,
+    const T* __restrict__ eps, Epilogue ep, int nrows, int rows_per_comp, int ncomp, int row_len,
     int kxs, const cpx<T>* __restrict__ tw_g, const cpx<T>* __restrict__ tw2_g, Gate gate, Krylov kry) {
   using C = XCfg<T, M, V>;
   constexpr int NP = C::NP, NPS = C::NPS, TJ = C::TJ, E = PlanInfo<M>::E;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   const size_t roff = (size_t)growc * row_len + 2 * jt;
   const size_t eoff = (size_t)(growc % rows_per_comp) * row_len + 2 * jt;
   V2 jv[EH];
-  double2 ev[EH];
+  typename io2<T>::t ev[EH];
   // right scaling of the solver's operator: the diagonal term's current is rs J
   constexpr bool SCALED = KM != KRY_NONE && KM != KRY_RESID;
   const IO* rsrow = SCALED && kry.rs ? (const IO*)kry.rs + eoff : nullptr;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
 #pragma unroll
   for (int i = 0; i < EH; ++i) {
     jv[i] = *reinterpret_cast<const V2*>(J + roff + 2 * TJ * i);
-    ev[i] = *reinterpret_cast<const double2*>(eps + eoff + 2 * TJ * i);
+    ev[i] = *reinterpret_cast<const typename io2<T>::t*>(eps + eoff + 2 * TJ * i);
     if constexpr (SCALED) {
       if (rsrow) sv[i] = *reinterpret_cast<const V2*>(rsrow + 2 * TJ * i);
     }
@@ -345,7 +345,7 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   run_fft<T, M, true, false, true, false, SWI>(v, lds, tw, p, jt, NPS, [&](int, int, int u, cpx<T> z) {
     if (!valid) return;
     const int i = u / TJ;
-    const double2 e2 = ev[i];
+    const auto e2 = ev[i];
     V2 j2 = jv[i];
     if constexpr (SCALED) {
       if (rsrow) {
@@ -468,7 +468,7 @@ hipError_t x_forward_v(const IO* in, void* out, int M, int nrows, int rows_per_c
 
 // Supported form: n_out = M reals (the physical half of the length-2M row).
 template <typename T, typename IO, int V, int KM>
-hipError_t x_inverse_v(const void* in, IO* y, const IO* J, const double* eps, Epilogue ep, int M, int nrows,
+hipError_t x_inverse_v(const void* in, IO* y, const IO* J, const T* eps, Epilogue ep, int M, int nrows,
                        int rows_per_comp, int ncomp, int row_len, int n_out, int kxs, const void* tw,
                        const void* tw2, hipStream_t s, Gate gg, const Krylov& kry) {
   if (n_out != M || row_len < M || kxs < M + 1) return hipErrorInvalidValue;
@@ -510,7 +510,7 @@ int x_pass_blocks_v(int M, bool f64, int nrows, int rows_per_comp, int ncomp) {
                                                 const void*, const void*, hipStream_t, const double*, Gate,     \
                                                 const Krylov&);
 #define MOT_X_INV(T, IO, V, KM)                                                                                \
-  template hipError_t x_inverse_v<T, IO, V, KM>(const void*, IO*, const IO*, const double*, Epilogue, int, int, \
+  template hipError_t x_inverse_v<T, IO, V, KM>(const void*, IO*, const IO*, const T*, Epilogue, int, int, \
                                                 int, int, int, int, int, const void*, const void*,              \
                                                 hipStream_t, Gate, const Krylov&);
 #define MOT_X_VARIANT(V)                                                                                       \

@@ -42,6 +42,7 @@ struct mot_ctx {
   // diag(Z0) = eps/2 - (eps - 1) G0(0)_pp (G0(0) is isotropic)
   double g0self;       // G0(0)_xx
   float* rs32;
+  float* eps32;  // eps_r rounded to FP32: the epilogues of the FP32 passes
   double* rs64;
   double* lam0_64;
   float* lam0_32;
@@ -313,13 +314,15 @@ __global__ void k_relayout(const T* __restrict__ src, T* __restrict__ dst, int n
 
 // rs = 1 / (w0 eps - (eps - 1) g0), the inverse diagonal of Z0 per voxel
 // (w0 = 1/2 + dreg[0])
+// (and eps32 = eps rounded to FP32, read by the epilogues of FP32 passes)
 __global__ void k_right_scale(const double* __restrict__ eps, double g0, double w0, float* __restrict__ rs32,
-                              double* __restrict__ rs64, long long n) {
+                              double* __restrict__ rs64, float* __restrict__ eps32, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double r = 1.0 / (eps[i] * (w0 - g0) + g0);
   rs64[i] = r;
   rs32[i] = (float)r;
+  eps32[i] = (float)eps[i];
 }
 
 // fused z pass tile layout of width ws -> the same spectra in width wd
@@ -351,6 +354,11 @@ hipError_t launch_einc(const mot_pulse* p, double t, const double* eps, double* 
 namespace {
 
 // ---------------------------------------------------------------- Green product
+// eps_r in the precision of a pass's epilogue
+template <typename T> const T* eps_of(const mot_ctx* c);
+template <> const double* eps_of<double>(const mot_ctx* c) { return c->eps; }
+template <> const float* eps_of<float>(const mot_ctx* c) { return c->eps32; }
+
 struct NoMid {
   int operator()() const { return MOT_OK; }
 };
@@ -379,7 +387,7 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
                                      c->nz, c->nz, lam, c->twz[ti], s, g, tv[TUNE_ZF]));
   HTP(K_YI, d, motfft::y_pass<T>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny, c->ny,
                                  c->twy[ti], s, g, tv[TUNE_Y]));
-  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, Jd, c->eps, ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
+  HTP(K_XI, d, (motfft::x_inverse<T, IO>(c->wsA, y, Jd, eps_of<T>(c), ep, c->nx, rows, c->nz * c->ny, 3, c->nx, c->nx,
                                          c->kxs, c->twx[ti], c->tw2x[ti], s, g, tv[TUNE_X], ki)));
   return MOT_OK;
 }
@@ -1050,7 +1058,7 @@ int history_update_t(mot_ctx* c, const double* J) {
                                   c->nz, c->nz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
                                   c->ny, c->twy[ti], s, {}, tv[TUNE_Y]));
-  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, c->eps, c->adjoint ? ep_adj_hist(c) : ep_hist(c), c->nx,
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, eps_of<Tr>(c), c->adjoint ? ep_adj_hist(c) : ep_hist(c), c->nx,
                                               rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
                                               tv[TUNE_X])));
@@ -1075,7 +1083,7 @@ int history_gfield_t(mot_ctx* c, double* out) {
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
                                   c->ny, c->twy[ti], s, {}, tv[TUNE_Y]));
   // EP_G ignores its current argument; hrhs is passed as a valid vector
-  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, out, c->hrhs, c->eps, EP_G, c->nx, rows, c->nz * c->ny, 3,
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, out, c->hrhs, eps_of<Tr>(c), EP_G, c->nx, rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
                                               tv[TUNE_X])));
   return MOT_OK;
@@ -1103,7 +1111,7 @@ void drop_graphs(mot_ctx* c) {
 int update_right_scale(mot_ctx* c) {
   if (!c->have_eps || !c->have_spectra) return MOT_OK;
   hipLaunchKernelGGL(k_right_scale, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0, c->stream, c->eps,
-                     c->g0self, 0.5 + c->dreg[0], c->rs32, c->rs64, c->N);
+                     c->g0self, 0.5 + c->dreg[0], c->rs32, c->rs64, c->eps32, c->N);
   HT(hipGetLastError());
   return MOT_OK;
 }
@@ -1305,6 +1313,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
   const size_t wsB = (size_t)3 * c->nz * c->py * c->kxs * 16;
   if ((rc = dmalloc(c, (void**)&c->eps, sizeof(double) * c->N)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->rs32, sizeof(float) * c->N)) != MOT_OK) return fail(rc);
+  if ((rc = dmalloc(c, (void**)&c->eps32, sizeof(float) * c->N)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, (void**)&c->rs64, sizeof(double) * c->N)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->wsA, wsA)) != MOT_OK) return fail(rc);
   if ((rc = dmalloc(c, &c->wsB, wsB)) != MOT_OK) return fail(rc);
@@ -1350,7 +1359,7 @@ int mot_create(const mot_grid* grid, mot_precision prec, void* hip_stream, mot_c
 int mot_destroy(mot_ctx* c) {
   if (!c) return MOT_OK;
   (void)hipStreamSynchronize(c->stream);
-  void* bufs[] = {c->eps, c->rs32, c->rs64, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
+  void* bufs[] = {c->eps, c->eps32, c->rs32, c->rs64, c->wsA, c->wsB, c->lam0_64, c->lam0_32, c->lamh, c->spec, c->ring, c->hrhs,
                   c->partials, c->scal, c->lam_tile, c->pblk, c->ffpart, c->jprev2, c->tfK, c->tfar};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
