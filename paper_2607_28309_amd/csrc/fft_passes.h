@@ -13,8 +13,13 @@ enum ZMode { Z_FWD = 0, Z_INV = 1, Z_FUSED = 2 };
 // Epilogue of the inverse x pass:
 //   y = (ca*eps + c0) * J + (cb*eps + cb0) * g,    g = the transformed field
 // (Eq. 12: ca = 1/2, c0 = 0, cb = -1, cb0 = 1 gives D J - X (G J)).
+// Optionally (FP64 output without solver work): y -= cp eps jp with the
+// current jp of the previous step, and jp = J afterwards (in place: each
+// element is read before its thread writes it).
 struct Epilogue {
   double ca, c0, cb, cb0;
+  double* jp = nullptr;
+  double cp = 0.0;
 };
 
 // Optional early exit of a whole launch on device flags, for work enqueued

@@ -305,6 +305,10 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
   const IO* rsrow = SCALED && kry.rs ? (const IO*)kry.rs + eoff : nullptr;
   V2 sv[SCALED ? EH : 1];
   V2 bv[KM == KRY_RESID ? EH : 1];  // right-hand side pairs (residual form)
+  // the previous step's current (Epilogue::jp), FP64 outputs without solver
+  // work; read where it is used (prefetched, it took 40 more registers)
+  constexpr bool PREV = KM == KRY_NONE && std::is_same<IO, double>::value;
+  const bool prev = PREV && ep.jp != nullptr;
 #pragma unroll
   for (int i = 0; i < EH; ++i) {
     jv[i] = *reinterpret_cast<const V2*>(J + roff + 2 * TJ * i);
@@ -360,6 +364,15 @@ __global__ __launch_bounds__((XCfg<T, M, V>::BLOCK)) void k_x_inverse(
       r.x = bv[i].x - r.x;
       r.y = bv[i].y - r.y;
       acc1 += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+    }
+    if constexpr (PREV) {
+      if (prev) {
+        double2* q = reinterpret_cast<double2*>(ep.jp + roff + 2 * u);
+        const double2 pj = *q;
+        r.x -= ep.cp * (double)e2.x * pj.x;
+        r.y -= ep.cp * (double)e2.y * pj.y;
+        *q = double2{(double)jv[i].x, (double)jv[i].y};
+      }
     }
     *reinterpret_cast<V2*>(yrow + 2 * u) = r;
     if constexpr (KM == KRY_HALF1 || KM == KRY_V) yo[i] = r;

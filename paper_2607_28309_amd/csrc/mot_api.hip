@@ -394,30 +394,13 @@ int green_product(mot_ctx* c, const IO* J, IO* y, const T* lam, motfft::Epilogue
 
 // Epilogues of the products.  D = (1/2 + dreg[0]) eps_r is the diagonal of
 // Z0, (1/2 + dreg[1]) eps_r that of Z1 (dreg = 0 without regularization; the
-// dreg[2] eps_r J_{n-1} term of the history is added by k_reg2).
+// dreg[2] eps_r J_{n-1} term of the history rides on its epilogue, Epilogue::jp).
 motfft::Epilogue ep_z0(const mot_ctx* c) { return {0.5 + c->dreg[0], 0.0, -1.0, 1.0}; }     // D J - X (G J)
 const motfft::Epilogue EP_G{0.0, 0.0, 0.0, 1.0};                                             // G J
 motfft::Epilogue ep_hist(const mot_ctx* c) { return {-(0.5 + c->dreg[1]), 0.0, 1.0, -1.0}; } // -(diag Z1) J + X (G J)
 // transposed operators (contrast on the input, applied by the forward x pass)
 motfft::Epilogue ep_z0t(const mot_ctx* c) { return {0.5 + c->dreg[0], 0.0, 0.0, -1.0}; }      // D v - G (X v)
 motfft::Epilogue ep_adj_hist(const mot_ctx* c) { return {-(0.5 + c->dreg[1]), 0.0, 0.0, 1.0}; } // -(diag Z1) v + G (X v)
-
-// h -= w2 eps prev, then prev = J (3 components of nvox voxels): the
-// dreg[2] eps_r J_{n-1} part of the history right-hand side, and the
-// hand-over of the newest current for the next step
-__global__ void k_reg2(double* __restrict__ h, double* __restrict__ prev, const double* __restrict__ J,
-                       const double* __restrict__ eps, double w2, long long nvox) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * nvox) return;
-  h[i] -= w2 * eps[i % nvox] * prev[i];
-  prev[i] = J[i];
-}
-
-hipError_t launch_reg2(mot_ctx* c, const double* J) {
-  hipLaunchKernelGGL(k_reg2, dim3((unsigned)((c->n3 + 255) / 256)), dim3(256), 0, c->stream, c->hrhs, c->jprev2, J,
-                     c->eps, c->dreg[2], c->N);
-  return hipGetLastError();
-}
 
 int reduce_sync(mot_ctx* c) {
   HT(hipMemcpyAsync(c->hscal, c->scal, sizeof(double) * S_NSLOT, hipMemcpyDeviceToHost, c->stream));
@@ -1058,11 +1041,17 @@ int history_update_t(mot_ctx* c, const double* J) {
                                   c->nz, c->nz, nullptr, c->twz[ti], s, {}, tv[TUNE_Z]));
   HTP(K_YI, d, motfft::y_pass<Tr>(c->wsB, c->wsA, c->py, true, c->kx, c->kxs, 3 * c->nz, c->py, c->py, c->ny,
                                   c->ny, c->twy[ti], s, {}, tv[TUNE_Y]));
-  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, eps_of<Tr>(c), c->adjoint ? ep_adj_hist(c) : ep_hist(c), c->nx,
+  // the d2 eps J_{n-1} part of the regularized history right-hand side, and
+  // the hand-over of J_n for the next step, ride on the epilogue
+  motfft::Epilogue eh = c->adjoint ? ep_adj_hist(c) : ep_hist(c);
+  if (c->dreg[2] != 0.0) {
+    eh.jp = c->jprev2;
+    eh.cp = c->dreg[2];
+  }
+  HTP(K_XI, d, (motfft::x_inverse<Tr, double>(c->wsA, c->hrhs, J, eps_of<Tr>(c), eh, c->nx,
                                               rows, c->nz * c->ny, 3,
                                               c->nx, c->nx, c->kxs, c->twx[ti], c->tw2x[ti], s, {},
                                               tv[TUNE_X])));
-  if (c->dreg[2] != 0.0) HTP(K_KRY, d, launch_reg2(c, J));
   c->head = slot;
   c->nstep += 1;
   return MOT_OK;
