@@ -687,6 +687,33 @@ def test_sweep_graph_matches_stream_launches(gpu_lib):
         c.close()
 
 
+def test_last_stats_without_device_wait(gpu_lib):
+    # a step without stats returns with its history update in flight; its
+    # counts and residual are those a step with stats reports, bit for bit,
+    # and its LHS/RHS times are -1
+    import torch
+    n, alpha = (16, 6, 4), 4
+    eps = _eps(n)
+    cs = [_ctx(gpu_lib, n, alpha, "f32_refined", eps=eps) for _ in range(2)]
+    p = W.pulse(20)
+    N = int(np.prod(n))
+    e = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    J = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(2)]
+    for k in range(12):
+        cs[0].excitation(p, (60 + k) * alpha / math.sqrt(3.0), e)
+        st0 = cs[0].step(e, J[0], tol=1e-6)[1]
+        assert cs[1].step(e, J[1], tol=1e-6, stats=False)[1] is None
+        st1 = cs[1].last_stats()
+        for key in ("iters", "matvecs", "matvecs_f64", "refinements", "relres"):
+            assert st0[key] == st1[key], (k, key)
+        assert st1["ms_lhs"] == -1.0 and st1["ms_rhs"] == -1.0
+        assert cs[0].last_stats() == st0
+    torch.cuda.synchronize()
+    assert torch.equal(J[0], J[1])
+    for c in cs:
+        c.close()
+
+
 def test_step_batch_matches_single_steps(gpu_lib):
     # contexts of uneven grids on their own streams, stepped together by the
     # library's thread pool, give the currents of one-by-one steps, bit for bit
