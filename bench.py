@@ -235,6 +235,55 @@ def batch_leg(args, log_fn):
     return res
 
 
+def adjoint_leg(args, log_fn):
+    """Gradient of the far-field energy W with respect to eps_r by the adjoint
+    march, on the first cube of the batch workload with a side of at most 48
+    (alpha = 4, 150 steps from t = 0, its own incidence): the times of the
+    recorded forward march and of the adjoint march, and one directional
+    central difference of W checking <grad W, v>."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2607_28309_amd import adjoint as A
+    from paper_2607_28309_amd import native
+    sc = next(s_ for s_ in W.cube_batch() if s_.n[0] <= 48)
+    alpha, nt, tol = W.BATCH_ALPHA, W.BATCH_STEPS, 1e-10
+    c = native.Context(*sc.n, alpha=alpha, precision="f64")
+    eps0 = torch.from_numpy(sc.eps.ravel()).cuda()
+    c.set_material(eps0)
+    c.build_green_spectra()
+    c.set_regularization(W.regularization_for(alpha))
+    pulse = W.pulse(W.BATCH_PPW, k_hat=sc.k_hat, e_hat=sc.e_hat)
+    rhat = [-v for v in sc.k_hat]  # backscatter
+    march = A.FarFieldMarch(c, pulse, nt, rhat, tol=tol)
+    e_t = eps0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Wt = A.far_field_energy(e_t, march)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    Wt.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t
+    g = e_t.grad.detach()
+    # direction: seeded, unit norm; step h in eps_r
+    v = torch.from_numpy(np.random.default_rng(7).standard_normal(c.N)).cuda()
+    v /= torch.linalg.norm(v)
+    h = 1e-3
+    fd = (march.forward(eps0 + h * v) - march.forward(eps0 - h * v)) / (2 * h)
+    ad = float(torch.dot(g, v))
+    res = {"workload": f"cube{sc.n[0]}_a{alpha}_{nt}steps_backscatter", "unknowns": 3 * c.N,
+           "nlags": c.info()["nlags"], "precision": "f64", "tol": tol, "W": float(Wt.item()),
+           "forward_march_s": t_fwd, "adjoint_march_s": t_bwd, "grad_norm": float(torch.linalg.norm(g)),
+           "directional_check": {"h": h, "central_difference": fd, "adjoint": ad,
+                                 "rel_err": abs(fd - ad) / max(abs(ad), 1e-300)}}
+    log_fn(f"adjoint gradient on {res['workload']}: forward {t_fwd:.2f} s, adjoint {t_bwd:.2f} s, "
+           f"<grad, v> {ad:.6e} against central difference {fd:.6e}")
+    c.close()
+    return res
+
+
 def _trace_march(args, name, eps_full_cut, ppw, log_fn):
     """The march of the workload of a stored oracle trace (tests/golden/
     oracle_trace_<name>.npz: the oracle's FP64 march from t = 0, TFQMR to
@@ -503,6 +552,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batch of 32 independent cubes (sides 24..80, alpha 4) stepped together")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint leg (gradient of the far-field energy on one cube of the batch, "
+                         "with a directional central-difference check)")
     ap.add_argument("--sweep", action="store_true",
                     help="also run the time-step sweep on the 96^3 nested cube (alpha 1..16, one physical window)")
     ap.add_argument("--sweep-only", action="store_true", help="run only the time-step sweep and print its JSON line")
@@ -636,7 +688,7 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
 
     # Z0 product throughput (FP32 and FP64) on the context's stream (torch's
-    # current stream): three rounds of reps products back to back between one
+    # current stream): five rounds of reps products back to back between one
     # event pair, as the solver issues them (ms = the median round's average;
     # the first round after the march runs at lower clocks); then one event
     # pair per product (median)
@@ -645,10 +697,10 @@ def main():
     for dt_name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
         Jm = torch.randn(3 * N, dtype=tdt, device="cuda")
         ym = torch.empty_like(Jm)
-        for _ in range(5):
+        for _ in range(10):
             ctx.z0_matvec(Jm, ym, dt_name)
         rounds = []
-        for _ in range(3):
+        for _ in range(5):
             s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             s0.record()
             for _ in range(reps):
@@ -661,7 +713,7 @@ def main():
             ctx.z0_matvec(Jm, ym, dt_name)
             e1.record()
         torch.cuda.synchronize()
-        ms = sorted(a.elapsed_time(b) / reps for a, b in rounds)[1]
+        ms = sorted(a.elapsed_time(b) / reps for a, b in rounds)[len(rounds) // 2]
         times = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
         mv[dt_name] = {"ms": ms, "per_s": 1e3 / ms, "reps": reps, "ms_event_pairs_median": times[len(times) // 2]}
         log(f"z0_matvec {dt_name}: {ms:.4f} ms back to back over {reps} "
@@ -754,6 +806,8 @@ def main():
     out["field_err_vs_oracle"] = oracle_trace_leg(args, log)
     if not args.no_batch:
         out["batch"] = batch_leg(args, log)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(args, log)
     if args.sweep:
         out["sweep"] = sweep_leg(args, log)
     if not args.no_cpu_baseline:
