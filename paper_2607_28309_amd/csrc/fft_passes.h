@@ -135,11 +135,12 @@ int z_fused_width(int M, bool f64, int var = 0);
 
 // Offset of the octant spectrum value of component comp (order xx, yy, zz,
 // xy, xz, yz) at (kx, kyc, kzc) in the fused z pass's tile layout
-// [kyc][kx / W][kzc][comp][kx % W]: one workgroup's values are one contiguous
-// range, and lanes of consecutive kx read consecutive words.
+// [kyc][kx / W][kzc][kx % W][comp]: one workgroup's values are one contiguous
+// range, a thread reads the six components of a point as one contiguous
+// piece, and lanes of consecutive kx read consecutive pieces.
 __host__ __device__ inline size_t lam_tile_offset(int kx, int kyc, int kzc, int comp, int kxn, int nzc, int W) {
   const int ntile = (kxn + W - 1) / W;
-  return ((((size_t)kyc * ntile + kx / W) * nzc + kzc) * 6 + comp) * W + kx % W;
+  return ((((size_t)kyc * ntile + kx / W) * nzc + kzc) * W + kx % W) * 6 + comp;
 }
 
 }  // namespace motfft

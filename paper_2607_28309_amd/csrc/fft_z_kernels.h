@@ -90,7 +90,7 @@ __global__ __launch_bounds__((ZFCfg<T, M, V>::BLOCK)) void k_z_fused(
     const int kz = it < NI ? it / W : 0, cc = it % W;
     const int kzc = kz <= M / 2 ? kz : M - kz;
 #pragma unroll
-    for (int comp = 0; comp < 6; ++comp) lv[k][comp] = lt[(kzc * 6 + comp) * W + cc];
+    for (int comp = 0; comp < 6; ++comp) lv[k][comp] = lt[(kzc * W + cc) * 6 + comp];
   }
   load_table<cpx<T>, M, C::BLOCK>(tw, tw_g);
   run_fft<T, M, false, true, false>(v, lds, tw, p, jt, NPS,
