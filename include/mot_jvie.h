@@ -304,6 +304,16 @@ int mot_set_breakdown_tolerance(mot_ctx* ctx, double t);
  * MOT_ENOMEM. */
 int mot_set_history_scheme(mot_ctx* ctx, int32_t scheme);
 
+/* Address form of the FP32 blocked history multiply-accumulate (a check of
+ * the library against itself, not an operation of the method).  By default
+ * its loads take 32-bit byte offsets from a per-slot base whenever a ring
+ * slot (three spectra) and a lag of Lambda (six components) each fit in
+ * 4 GiB, and 64-bit addresses on larger grids; on = 1 forces the 64-bit form
+ * on any grid, on = 0 restores the default.  The two forms give the same
+ * sums bit for bit.  Applies from the next push on.
+ * Errors: MOT_EINVAL (NULL, on not 0 or 1). */
+int mot_set_wide_offsets(mot_ctx* ctx, int32_t on);
+
 /* Start a new march of Eq. 3: n = 0, history ring and history right-hand
  * side zeroed (J_{n<0} = 0: the causal start of the recursion). */
 int mot_reset(mot_ctx* ctx);

@@ -30,6 +30,10 @@ struct Geo {
   int nx, ny, nz, kxs, nl;
 };
 
+// Word 3 of a raw (untyped, stride 0) buffer resource on gfx9-family parts:
+// 32-bit data format, no swizzle; loads past num_records return zero.
+constexpr int BUF_WORD3 = 0x00020000;
+
 // The mirror points of one octant frequency that a thread takes: NM = 4
 // (both kz sides), NM = 2 (the kz side `side`, both ky sides) or NM = 1 (kz
 // side side >> 1, ky side side & 1); mirror i is kz side a(i), ky side b(i).
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256) void k_mac_recent(const cpx<T>* __restrict__ r
 // threads of a frequency take one kz side each and read the same Lambda
 // words; NM = 1 (long blocks in FP64): four threads per frequency, one
 // mirror point each.  Two waves per SIMD at least (a register budget of 256).
-template <typename T, int B, int NM>
+template <typename T, int B, int NM, bool O32 = false>
 __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__ ring, const T* __restrict__ lamh,
                                                    cpx<T>* out0, cpx<T>* pblk, const cpx<T>* iblk, Geo g,
                                                    long long n0, int nold) {
@@ -152,6 +156,24 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
   const size_t comp = (size_t)(2 * g.nz) * (2 * g.ny) * g.kxs;
   const size_t slot = 3 * comp;
   const size_t lcomp = (size_t)(g.nz + 1) * (g.ny + 1) * g.kxs;
+  // With NM = 2 the kz sign sz of a thread's points is known only at run time
+  // (with NM = 1 the ky sign sy too).  It goes into the window's copies of the
+  // off-diagonal Lambda components that it multiplies (xy by sy, xz by sz, yz
+  // by sy sz), so that the multiply-adds see compile-time signs only.  A
+  // product of two values one of which changed sign is exactly the negated
+  // product: the sums are those of the plain formula.
+  const T sz2 = NM <= 2 && pt.a[0] ? (T)-1 : (T)1;
+  const T sy2 = NM == 1 && pt.b[0] ? (T)-1 : (T)1;
+  auto fold_signs = [&](T* l) {
+    if constexpr (NM == 1) {
+      l[3] *= sy2;
+      l[5] *= sy2 * sz2;
+    }
+    if constexpr (NM <= 2) {
+      l[4] *= sz2;
+      if constexpr (NM == 2) l[5] *= sz2;
+    }
+  };
   auto lam_at = [&](int lag, T* l) {
     if (lag > g.nl) {
 #pragma unroll
@@ -161,17 +183,11 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
     const T* L = lamh + (size_t)(lag - 1) * 6 * lcomp + lo;
 #pragma unroll
     for (int c = 0; c < 6; ++c) l[c] = L[c * lcomp];
+    fold_signs(l);
   };
   T w[B][6];  // window: w[b] = Lambda_{m+1+b}
 #pragma unroll
   for (int b = 0; b < B; ++b) lam_at(b + 1, w[b]);
-  // With NM = 2 the kz sign sz is known only at run time (with NM = 1 the ky
-  // sign sy too): the z (y) component of each loaded current is multiplied
-  // by sz (sy) and the z (y) accumulators carry sz (sy) times their value
-  // (sz^2 = sy^2 = 1), so that the B multiply-adds per load see compile-time
-  // signs only.
-  const T sz2 = NM <= 2 && pt.a[0] ? (T)-1 : (T)1;
-  const T sy2 = NM == 1 && pt.b[0] ? (T)-1 : (T)1;
   cpx<T> acc[B][NM][3];
 #pragma unroll
   for (int b = 0; b < B; ++b)
@@ -179,11 +195,8 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
     for (int i = 0; i < NM; ++i) {
       if (iblk) {
         const cpx<T>* I = iblk + (size_t)b * slot;
-        acc[b][i][0] = I[pt.off[i]];
-        const cpx<T> y = I[comp + pt.off[i]];
-        acc[b][i][1] = cpx<T>{sy2 * y.x, sy2 * y.y};
-        const cpx<T> z = I[2 * comp + pt.off[i]];
-        acc[b][i][2] = cpx<T>{sz2 * z.x, sz2 * z.y};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[b][i][q] = I[q * comp + pt.off[i]];
       } else {
 #pragma unroll
         for (int q = 0; q < 3; ++q) acc[b][i][q] = cpx<T>{(T)0, (T)0};
@@ -192,31 +205,15 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
   // ring slot of J^_{n0-m} for 0 <= m < nl: one 64-bit remainder per thread,
   // then 32-bit steps
   const int s0 = (int)(n0 % g.nl);
-  auto load_slot = [&](int m, cpx<T> (&jv)[NM][3]) {
-    const int sl = s0 - m < 0 ? s0 - m + g.nl : s0 - m;
-    const cpx<T>* R = ring + (size_t)sl * slot;
-#pragma unroll
-    for (int i = 0; i < NM; ++i)
-#pragma unroll
-      for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
-  };
   // One slot: its multiply-adds with the window, then the window moves on
-  // (w[B - 1] = the next Lambda value, ln, or 0 past the last lag).  The
-  // loaded registers are only read here (the signs go into copies).
+  // (w[B - 1] = the next Lambda value, ln, or 0 past the last lag).
   auto mac_slot = [&](const cpx<T> (&jv)[NM][3], const T (&ln)[6], bool lzero) {
-    cpx<T> j[NM][3];
-#pragma unroll
-    for (int i = 0; i < NM; ++i) {
-      j[i][0] = jv[i][0];
-      j[i][1] = NM == 1 ? cpx<T>{sy2 * jv[i][1].x, sy2 * jv[i][1].y} : jv[i][1];
-      j[i][2] = NM <= 2 ? cpx<T>{sz2 * jv[i][2].x, sz2 * jv[i][2].y} : jv[i][2];
-    }
 #pragma unroll
     for (int b = 0; b < B; ++b)
 #pragma unroll
       for (int i = 0; i < NM; ++i)
         mac3<T>(acc[b][i], w[b], (NM != 1 && (i & 1)) ? (T)-1 : (T)1, (NM == 4 && (i >> 1)) ? (T)-1 : (T)1,
-                j[i][0], j[i][1], j[i][2]);
+                jv[i][0], jv[i][1], jv[i][2]);
 #pragma unroll
     for (int b = 0; b + 1 < B; ++b)
 #pragma unroll
@@ -224,47 +221,155 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
 #pragma unroll
     for (int c = 0; c < 6; ++c) w[B - 1][c] = lzero ? (T)0 : ln[c];
   };
-  // Lambda_lag, clamped to the last lag (the caller zeroes lags past it)
-  auto lam_ld = [&](int lag, T (&l)[6]) {
-    const T* L = lamh + (size_t)((lag < g.nl ? lag : g.nl) - 1) * 6 * lcomp + lo;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) l[c] = L[c * lcomp];
-  };
   if constexpr (sizeof(T) == 4) {
-    // FP32: three register sets take the slots in turn (slot m in set
-    // m mod 3).  The work on slot m first issues the loads of slot m + 2
-    // (and of the window value two slots ahead) into the set that slot m - 1
-    // has just released, then does slot m's multiply-adds: every load has
-    // two slots of multiply-adds to arrive in.  All loads in the loop are
-    // unconditional (indices clamped to valid slots and lags), so that no
-    // register with a load in flight is merged or copied at a branch or at
-    // the loop's back edge; the last nold mod 3 slots run after the loop.
+    // FP32: NS register sets of currents take the slots in turn (slot m in
+    // set m mod NS).  The work on slot m first issues the loads of slot
+    // m + NS - 1 (and of the Lambda value as many slots ahead) into the set
+    // that slot m - 1 has just released, then does slot m's multiply-adds:
+    // every load has NS - 1 slots of multiply-adds to arrive in (with two
+    // waves per SIMD, one slot is about 1.2 k cycles of each wave's issue).
+    // No load in the loop is conditional, so that no register with a load in
+    // flight is merged or copied at a branch or at the loop's back edge.  A
+    // loop trip takes U slots (all set indices compile-time); the last
+    // nold mod U slots follow, each behind a wave-uniform test.
+    //
+    // With O32 (a slot and a lag's six Lambda components each within 4 GiB)
+    // the loads are buffer loads: a wave-uniform resource per slot and lag
+    // (scalar registers) and per-thread 32-bit byte offsets that stay fixed
+    // over the slots, so that no address arithmetic is redone per slot.  A
+    // slot m >= nold and a lag past the last get an empty range, whose loads
+    // return zero without touching memory: no select zeroes the lags past
+    // the last, and the loads ahead of the last slots need no clamp.  Without
+    // O32 the indices are clamped to valid slots and lags and the window
+    // zeroes the lags past the last.
+    //
+    // Four sets with two mirror points per thread and 32-bit offsets, else
+    // three (the registers of a fourth set would spill).
+    constexpr int NS = O32 && NM == 2 ? 4 : 3;
     const int last = nold > 0 ? nold - 1 : 0;
-    cpx<T> j0[NM][3], j1[NM][3], j2[NM][3];
-    T l0[6], l1[6], l2[6];
-    load_slot(0, j0);
-    load_slot(last < 1 ? last : 1, j1);
-    lam_ld(1 + B, l0);
-    lam_ld(2 + B, l1);
-    auto step = [&](int m, cpx<T> (&jc)[NM][3], T (&lc)[6], cpx<T> (&jn)[NM][3], T (&ln)[6]) {
-      load_slot(m + 2 < last ? m + 2 : last, jn);
-      lam_ld(m + 3 + B, ln);
-      mac_slot(jc, lc, m + 1 + B > g.nl);
-    };
-    const int nfull = nold / 3 * 3;
-    for (int m = 0; m < nfull; m += 3) {
-      step(m, j0, l0, j2, l2);
-      step(m + 1, j1, l1, j0, l0);
-      step(m + 2, j2, l2, j1, l1);
+    unsigned jo[NM][3], lof[6];
+    if constexpr (O32) {
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) jo[i][q] = (unsigned)((q * comp + pt.off[i]) * sizeof(cpx<T>));
+#pragma unroll
+      for (int c = 0; c < 6; ++c) lof[c] = (unsigned)((c * lcomp + lo) * sizeof(T));
     }
-    if (nfull < nold) mac_slot(j0, l0, nfull + 1 + B > g.nl);
-    if (nfull + 1 < nold) mac_slot(j1, l1, nfull + 2 + B > g.nl);
+    auto ld_slot = [&](int m, cpx<T> (&jv)[NM][3]) {
+      const int mc = m < last ? m : last;
+      const int sl = s0 - mc < 0 ? s0 - mc + g.nl : s0 - mc;
+      const cpx<T>* R = ring + (size_t)sl * slot;
+      if constexpr (O32) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)R, (short)0, m < nold ? (int)(unsigned)(slot * sizeof(cpx<T>)) : 0, BUF_WORD3);
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            jv[i][q] = __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(rs, jo[i][q], 0, 0));
+      } else {
+#pragma unroll
+        for (int i = 0; i < NM; ++i)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
+      }
+    };
+    auto ld_lam = [&](int lag, T (&l)[6]) {
+      const T* L = lamh + (size_t)((lag < g.nl ? lag : g.nl) - 1) * 6 * lcomp;
+      if constexpr (O32) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)L, (short)0, lag <= g.nl ? (int)(unsigned)(6 * lcomp * sizeof(T)) : 0, BUF_WORD3);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) l[c] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, lof[c], 0, 0));
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) l[c] = L[c * lcomp + lo];
+      }
+    };
+    cpx<T> js[NS][NM][3];
+#pragma unroll
+    for (int k = 0; k + 1 < NS; ++k) ld_slot(k, js[k]);
+    if constexpr (O32 && NM == 2) {
+      // Lambda in place: the window rotates through NL >= B + NS register
+      // sets (NL a multiple of NS, U = NL): lag m + j (m a multiple of NL)
+      // sits in set j mod NL, so that every window access has a compile-time
+      // set and no value is copied.  Step k overwrites the set of lag
+      // m + k + NS + B - NL <= m + k, whose last use was step k - 1 at the
+      // latest, with lag m + k + NS + B.  The kz sign goes into the xz and yz
+      // components of lag m + k + 1 + B after the multiply-adds of step k
+      // (the lags of the first window come folded), NS - 1 slots after its
+      // load was issued and before its first use.
+      constexpr int NL = (B + NS + NS - 1) / NS * NS;
+      constexpr int U = NL;
+      T lp[NL][6];
+#pragma unroll
+      for (int j = 1; j <= B; ++j)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) lp[j % NL][c] = w[j - 1][c];
+#pragma unroll
+      for (int k = 0; k + 1 < NS; ++k) ld_lam(k + 1 + B, lp[(k + 1 + B) % NL]);
+      auto step = [&](int m, int k) {
+        ld_slot(m + NS - 1, js[(k + NS - 1) % NS]);
+        ld_lam(m + NS + B, lp[(k + NS + B) % NL]);
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+          for (int i = 0; i < NM; ++i)
+            mac3<T>(acc[b][i], lp[(k + 1 + b) % NL], (i & 1) ? (T)-1 : (T)1, (T)1, js[k % NS][i][0],
+                    js[k % NS][i][1], js[k % NS][i][2]);
+        fold_signs(lp[(k + 1 + B) % NL]);
+      };
+      const int nfull = nold / U * U;
+      for (int m = 0; m < nfull; m += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) step(m + k, k);
+      }
+#pragma unroll
+      for (int k = 0; k + 1 < U; ++k) {
+        if (nfull + k >= nold) break;
+        step(nfull + k, k);
+      }
+    } else {
+      // Lambda through the shifting window: NS sets receive the loads
+      // ahead, and each step moves one into w[B - 1].  A trip of U slots, U
+      // a multiple of B where B is one of NS, brings the window back to the
+      // registers it started in (no moves for its shifts).
+      constexpr int U = B % NS == 0 ? B : NS;
+      T ls[NS][6];
+#pragma unroll
+      for (int k = 0; k + 1 < NS; ++k) ld_lam(k + 1 + B, ls[k]);
+      auto step = [&](int m, int k) {
+        ld_slot(m + NS - 1, js[(k + NS - 1) % NS]);
+        ld_lam(m + NS + B, ls[(k + NS - 1) % NS]);
+        T l[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) l[c] = ls[k % NS][c];
+        fold_signs(l);
+        mac_slot(js[k % NS], l, !O32 && m + 1 + B > g.nl);
+      };
+      const int nfull = nold / U * U;
+      for (int m = 0; m < nfull; m += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) step(m + k, k);
+      }
+#pragma unroll
+      for (int k = 0; k + 1 < U; ++k) {
+        if (nfull + k >= nold) break;
+        step(nfull + k, k);
+      }
+    }
   } else {
     // FP64 has no registers to spare for loads ahead
     for (int m = 0; m < nold; ++m) {
       cpx<T> jv[NM][3];
       T ln[6];
-      load_slot(m, jv);
+      const int sl = s0 - m < 0 ? s0 - m + g.nl : s0 - m;
+      const cpx<T>* R = ring + (size_t)sl * slot;
+#pragma unroll
+      for (int i = 0; i < NM; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) jv[i][q] = R[q * comp + pt.off[i]];
       lam_at(m + 1 + B, ln);
       mac_slot(jv, ln, false);
     }
@@ -275,9 +380,8 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
 #pragma unroll
     for (int i = 0; i < NM; ++i)
       if (pt.keep[i]) {
-        dst[pt.off[i]] = acc[b][i][0];
-        dst[comp + pt.off[i]] = cpx<T>{sy2 * acc[b][i][1].x, sy2 * acc[b][i][1].y};
-        dst[2 * comp + pt.off[i]] = cpx<T>{sz2 * acc[b][i][2].x, sz2 * acc[b][i][2].y};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dst[q * comp + pt.off[i]] = acc[b][i][q];
       }
   }
 }
@@ -299,28 +403,38 @@ hipError_t launch_mac_recent(const void* ring, const void* lamh, const void* ini
 }
 
 hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, const void* iblk, int f64,
-                            int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s) {
+                            int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s,
+                            int wide) {
   const Geo g{nx, ny, nz, kxs, nl};
   const dim3 gr = mac_grid(g);
   const long long cnt = mac_count(g);
   const dim3 gr2((unsigned)((cnt + 127) / 128));  // two threads per octant frequency
   const dim3 gr4((unsigned)((cnt + 63) / 64));    // four
-#define LB(T, BB, NM, GR)                                                                                 \
-  hipLaunchKernelGGL((k_mac_block<T, BB, NM>), GR, dim3(256), 0, s, (const cpx<T>*)ring, (const T*)lamh,   \
+  // 32-bit per-thread offsets when a slot of the ring and a lag of Lambda
+  // each fit in 4 GiB (FP32 only)
+  const size_t comp = (size_t)(2 * nz) * (2 * ny) * kxs, lcomp = (size_t)(nz + 1) * (ny + 1) * kxs;
+  const bool o32 =
+      !wide && 3 * comp * sizeof(cpx<float>) <= 0xFFFFFFFFull && 6 * lcomp * sizeof(float) <= 0xFFFFFFFFull;
+#define LB(T, BB, NM, GR, O)                                                                              \
+  hipLaunchKernelGGL((k_mac_block<T, BB, NM, O>), GR, dim3(256), 0, s, (const cpx<T>*)ring, (const T*)lamh, \
                      (cpx<T>*)out0, (cpx<T>*)pblk, (const cpx<T>*)iblk, g, n0, nold)
+#define LBF(BB, NM, GR)              \
+  if (o32) LB(float, BB, NM, GR, true); \
+  else LB(float, BB, NM, GR, false)
   if (f64) {
-    if (B == 1) LB(double, 1, 4, gr);
-    else if (B == 2) LB(double, 2, 4, gr);
-    else if (B == 4) LB(double, 4, 2, gr2);
-    else if (B == 8) LB(double, 8, 1, gr4);
+    if (B == 1) LB(double, 1, 4, gr, false);
+    else if (B == 2) LB(double, 2, 4, gr, false);
+    else if (B == 4) LB(double, 4, 2, gr2, false);
+    else if (B == 8) LB(double, 8, 1, gr4, false);
     else return hipErrorInvalidValue;
   } else {
-    if (B == 1) LB(float, 1, 4, gr);
-    else if (B == 2) LB(float, 2, 4, gr);
-    else if (B == 4) LB(float, 4, 4, gr);
-    else if (B == 8) LB(float, 8, 2, gr2);
+    if (B == 1) { LBF(1, 4, gr); }
+    else if (B == 2) { LBF(2, 4, gr); }
+    else if (B == 4) { LBF(4, 4, gr); }
+    else if (B == 8) { LBF(8, 2, gr2); }
     else return hipErrorInvalidValue;
   }
+#undef LBF
 #undef LB
   return hipGetLastError();
 }

@@ -54,6 +54,7 @@ struct mot_ctx {
   void* ring;
   size_t slot_elems;   // complex elements per ring slot
   int blk_B;           // steps per history block (temporal blocking)
+  int mac_wide = 0;    // 1: the block multiply-accumulate takes 64-bit addresses
   long long blk_n0;    // step that started the current block, -1 = none
   void* pblk;          // partial sums P_2..P_B of the current block
   // history scheme: 0 = chosen by the library, 1 = blocked multiply-accumulate
@@ -1016,11 +1017,11 @@ int history_update_t(mot_ctx* c, const double* J) {
     if (tf && c->tf_beta == n / TF_S && r0 + c->blk_B <= TF_S) {
       // the far parts of the time block plus its slots so far (r0 of them)
       HTP(K_MAC, d, launch_mac_block(c->ring, c->lamh, c->spec, c->pblk, (const char*)c->tfar + r0 * bytes_per_slot,
-                                     0, c->blk_B, c->nl, n, (int)r0, c->nx, c->ny, c->nz, c->kxs, s));
+                                     0, c->blk_B, c->nl, n, (int)r0, c->nx, c->ny, c->nz, c->kxs, s, c->mac_wide));
     } else {
       const int nold = (int)(n + 1 < c->nl ? n + 1 : c->nl);
       HTP(K_MAC, d, launch_mac_block(c->ring, c->lamh, c->spec, c->pblk, nullptr, sizeof(Tr) == 8, c->blk_B, c->nl,
-                                     n, nold, c->nx, c->ny, c->nz, c->kxs, s));
+                                     n, nold, c->nx, c->ny, c->nz, c->kxs, s, c->mac_wide));
     }
   } else {
     // inside a block: P_{r+1} plus the r = n - n0 newest lags; with B = 8,
@@ -1030,7 +1031,8 @@ int history_update_t(mot_ctx* c, const double* J) {
     char* pb = (char*)c->pblk;
     if (c->blk_B == 8 && r == 4) {
       HTP(K_MACR, d, launch_mac_block(c->ring, c->lamh, c->spec, pb + 4 * bytes_per_slot, pb + 3 * bytes_per_slot,
-                                      sizeof(Tr) == 8, 4, c->nl, n, 4, c->nx, c->ny, c->nz, c->kxs, s));
+                                      sizeof(Tr) == 8, 4, c->nl, n, 4, c->nx, c->ny, c->nz, c->kxs, s,
+                                      c->mac_wide));
     } else {
       const int nrec = c->blk_B == 8 && r > 4 ? r - 4 : r;
       HTP(K_MACR, d, launch_mac_recent(c->ring, c->lamh, pb + (size_t)(r - 1) * bytes_per_slot, c->spec,
@@ -1721,6 +1723,12 @@ int mot_set_history_scheme(mot_ctx* c, int32_t scheme) {
   // has begun finishes with the per-lag multiply-accumulate
   c->tf_beta = -1;
   return tf_configure(c);
+}
+
+int mot_set_wide_offsets(mot_ctx* c, int32_t on) {
+  if (!c || on < 0 || on > 1) return MOT_EINVAL;
+  c->mac_wide = on;
+  return MOT_OK;
 }
 
 int mot_set_breakdown_tolerance(mot_ctx* c, double t) {

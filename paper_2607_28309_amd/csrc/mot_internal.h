@@ -125,9 +125,11 @@ template <typename V> hipError_t tfqmr_v0(V* v, const V* au, const V* rt, long l
 hipError_t launch_mac_recent(const void* ring, const void* lamh, const void* init, void* out, int f64, int nl,
                              long long n, int nrec, int nx, int ny, int nz, int kxs, hipStream_t s);
 // P_b = init_b + sum_{m<nold} Lambda_{m+b} J^_{n0-m}, b = 1..B: P_1 -> out0,
-// P_b -> pblk + (b-2) slots; init_b = iblk + (b-1) slots (zero if iblk is null)
+// P_b -> pblk + (b-2) slots; init_b = iblk + (b-1) slots (zero if iblk is null).
+// wide != 0: 64-bit addresses also where 32-bit buffer offsets would do.
 hipError_t launch_mac_block(const void* ring, const void* lamh, void* out0, void* pblk, const void* iblk, int f64,
-                            int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s);
+                            int B, int nl, long long n0, int nold, int nx, int ny, int nz, int kxs, hipStream_t s,
+                            int wide = 0);
 // History by FFTs in time (FP32 ring): time blocks of TF_S steps, transforms
 // of length 2 TF_S.  tfft_blocks(nl) spectra K_m (m = 1..M) of the lag
 // segments Lambda_{(m-1)S+d}, d = 1..2S-1, each at the S+1 frequencies

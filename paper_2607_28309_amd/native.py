@@ -31,7 +31,7 @@ EXPORTS = (
     "mot_set_step", "mot_set_adjoint", "z0t_matvec", "mot_history_gfield", "mot_farfield",
     "mot_farfield_adjoint", "mot_adjoint_gradient", "mot_profile_kinds", "mot_set_graphs", "mot_step_batch",
     "mot_set_variants", "mot_get_variants", "mot_autotune", "mot_set_predictor", "mot_set_regularization",
-    "mot_farfield_static", "mot_set_history_scheme", "mot_set_breakdown_tolerance", "mot_last_stats",
+    "mot_farfield_static", "mot_set_history_scheme", "mot_set_wide_offsets", "mot_set_breakdown_tolerance", "mot_last_stats",
 )
 TUNE_KNOBS = ("x", "y", "z_history", "z_fused")
 PROF_NCLASS = 24
@@ -105,6 +105,7 @@ def _load():
         "mot_set_predictor": (ctypes.c_int, [vp, i32]),
         "mot_set_regularization": (ctypes.c_int, [vp, dbl, dbl, dbl]),
         "mot_set_history_scheme": (ctypes.c_int, [vp, i32]),
+        "mot_set_wide_offsets": (ctypes.c_int, [vp, i32]),
         "mot_set_breakdown_tolerance": (ctypes.c_int, [vp, dbl]),
     }
     for name, (res, args) in sig.items():
@@ -276,6 +277,11 @@ class Context:
         "fft_time" (2, far lags by FFTs in time over blocks of 32 steps)."""
         code = {"auto": 0, "blocked": 1, "fft_time": 2}.get(scheme, scheme)
         self._check(LIB.mot_set_history_scheme(self.h, int(code)), "mot_set_history_scheme")
+
+    def set_wide_offsets(self, on):
+        """Force (True) or release (False) the 64-bit address form of the FP32
+        blocked history multiply-accumulate; both give the same sums bit for bit."""
+        self._check(LIB.mot_set_wide_offsets(self.h, int(bool(on))), "mot_set_wide_offsets")
 
     def set_breakdown_tolerance(self, t):
         """TFQMR stops as broken down when |rho| or |sigma| <= t |b|^2 (0: exact zero only)."""

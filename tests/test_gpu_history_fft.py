@@ -214,3 +214,31 @@ def test_history_fft_time_pillars_full_size(gpu_lib):
         assert err <= 1e-5 * scale, (s, err / scale)
     print(f"[history fft_time] pillars full size: worst relative error {worst:.2e}")
     c.close()
+
+
+@pytest.mark.parametrize("scheme", ["blocked", "fft_time"])
+def test_history_wide_offsets_bit_identical(gpu_lib, scheme):
+    # the FP32 blocked multiply-accumulate takes 32-bit buffer offsets on
+    # grids that allow them and 64-bit addresses otherwise; forced onto the
+    # 64-bit form it must give the same right-hand sides bit for bit.  ell =
+    # 49 and 110 pushes: block starts with every count of older slots from 1
+    # to ell (every remainder of the pipelined loop), the second level of each
+    # block, and with FFTs in time the partial blocks of 0..24 slots.
+    import torch
+    n, alpha = (24, 12, 6), 1
+    eps = W.eps_iid(n, 1.5, 6.0, seed=31)
+    cs = [_ctx(gpu_lib, n, alpha, "f32", eps) for _ in range(2)]
+    cs[1].set_wide_offsets(True)
+    for c in cs:
+        c.set_history_scheme(scheme)
+    N = math.prod(n)
+    out = [torch.empty(3 * N, dtype=torch.float64, device="cuda") for _ in range(2)]
+    for s in range(110):
+        J = _t(W.random_current(n, seed=500 + s).ravel())
+        for c, o in zip(cs, out):
+            c.history_update(J)
+            c.history_rhs(o)
+        assert torch.equal(out[0], out[1]), s
+    assert float(out[0].abs().max()) > 0.0
+    for c in cs:
+        c.close()
