@@ -332,9 +332,9 @@ __global__ __launch_bounds__(256, 2) void k_mac_block(const cpx<T>* __restrict__
       }
     } else {
       // Lambda through the shifting window: NS sets receive the loads
-      // ahead, and each step moves one into w[B - 1].  A trip of U slots, U
-      // a multiple of B where B is one of NS, brings the window back to the
-      // registers it started in (no moves for its shifts).
+      // ahead, and each step moves one into w[B - 1].  A loop trip takes
+      // U = B slots when B is a multiple of NS (the window is then back in
+      // the registers it started in: no moves for its shifts), else NS.
       constexpr int U = B % NS == 0 ? B : NS;
       T ls[NS][6];
 #pragma unroll
