@@ -92,3 +92,11 @@ def test_lengths_and_invalid_grids():
     assert native.LIB.mot_create(ctypes.byref(native.make_grid(16, 8, 8, 1)), 7, None, ctypes.byref(h)) == \
         native.MOT_EINVAL
     assert native.LIB.mot_strerror(native.MOT_ENOCONV) == b"TFQMR did not converge"
+
+
+def test_setters_reject_a_null_context():
+    # argument checks before any device work: a NULL context is MOT_EINVAL
+    from paper_2607_28309_amd import native
+    assert native.LIB.mot_set_wide_offsets(None, 0) == native.MOT_EINVAL
+    assert native.LIB.mot_set_history_scheme(None, 1) == native.MOT_EINVAL
+    assert native.LIB.mot_set_graphs(None, 0) == native.MOT_EINVAL

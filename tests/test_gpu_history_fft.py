@@ -229,6 +229,7 @@ def test_history_wide_offsets_bit_identical(gpu_lib, scheme):
     eps = W.eps_iid(n, 1.5, 6.0, seed=31)
     cs = [_ctx(gpu_lib, n, alpha, "f32", eps) for _ in range(2)]
     cs[1].set_wide_offsets(True)
+    assert gpu_lib.LIB.mot_set_wide_offsets(cs[0].h, 2) == gpu_lib.MOT_EINVAL
     for c in cs:
         c.set_history_scheme(scheme)
     N = math.prod(n)
